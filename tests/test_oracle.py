@@ -1,0 +1,379 @@
+"""Pins of the CPU oracle against what the mathematics fixes.
+
+The paper prints no per-tile values (its figures did not survive), so each
+stage is pinned by closed forms, invariants, brute force on tiny inputs and
+independent library routines (scipy.ndimage, numpy.linalg), chosen so that a
+dropped term, a wrong sign or index, or a transposed operand fails a test.
+"""
+import numpy as np
+import pytest
+from scipy import ndimage as ndi
+
+from paper_1405_7958_amd import synth
+from tests import brute as B
+
+rng0 = np.random.Generator(np.random.PCG64(12345))
+
+
+def _norm_rows(st):
+    M = np.asarray(st, np.float64).reshape(3, 3).copy()
+    for i in range(2):
+        M[i] /= np.linalg.norm(M[i])
+    if not M[2].any():
+        c = np.cross(M[0], M[1])
+        M[2] = c / np.linalg.norm(c)
+    else:
+        M[2] /= np.linalg.norm(M[2])
+    return M
+
+
+# ----------------------------------------------------------------------------
+# colour deconvolution (Sec. 5.1)
+# ----------------------------------------------------------------------------
+
+def test_deconv_white_is_zero(oracle):
+    rgb = np.full((3, 5, 3), 255, np.uint8)
+    hq, ch = oracle.deconv(rgb, want_ch=True)
+    assert (ch == 0.0).all() and (hq == 0).all()
+
+
+@pytest.mark.parametrize("t", [0.1, 0.5, 1.0, 2.5])
+def test_deconv_closed_forms(oracle, t):
+    """OD = t*h gives c_H = t; OD along the other two stains gives c_H = 0.
+    A transposed inverse or a wrong cofactor fails these."""
+    M = _norm_rows(oracle.STAIN_HE)
+    assert oracle.deconv_od(t * M[0]) == pytest.approx(t, rel=1e-12)
+    assert abs(oracle.deconv_od(t * M[1])) < 1e-12
+    assert abs(oracle.deconv_od(t * M[2])) < 1e-12
+    # a general third stain (not the cross product) follows the same rule
+    st = np.array([0.65, 0.70, 0.29, 0.07, 0.99, 0.11, 0.27, 0.57, 0.78])
+    Mg = _norm_rows(st)
+    assert oracle.deconv_od(t * Mg[0], st) == pytest.approx(t, rel=1e-12)
+    assert abs(oracle.deconv_od(t * Mg[2], st)) < 1e-12
+
+
+def test_deconv_exhaustive_vs_numpy(oracle):
+    """All 2^24 RGB triples (one 4096 x 4096 image) against numpy.linalg.inv."""
+    v = np.arange(1 << 24, dtype=np.uint32)
+    rgb = np.stack([(v >> 16) & 255, (v >> 8) & 255, v & 255], -1).astype(np.uint8).reshape(4096, 4096, 3)
+    hq, ch = oracle.deconv(rgb, want_ch=True)
+    M = _norm_rows(oracle.STAIN_HE)
+    m = np.linalg.inv(M)[:, 0]
+    od = -np.log((rgb.astype(np.float64) + 1.0) / 256.0)
+    ref = od @ m
+    err = np.abs(ch - ref)
+    assert (err <= 1e-12 * np.maximum(np.abs(ref), 1.0)).all()
+    q = np.clip(np.floor(ref * 85.0 + 0.5), 0, 255)
+    diff = hq.astype(np.int64) != q
+    # a mismatch is allowed only where the scaled value is within rounding of a .5 boundary
+    frac = np.abs(ref * 85.0 + 0.5 - np.rint(ref * 85.0 + 0.5))
+    assert (frac[diff] < 1e-9).all()
+    assert diff.sum() <= 16
+
+
+def test_deconv_generator_colours(oracle):
+    """Noise-free generator colours: background ~19, nucleus ~100, low-contrast ~54."""
+    cols = np.array([[synth.BG_RGB, synth.NUC_RGB, synth.LOW_RGB]], np.uint8)
+    hq = oracle.deconv(cols)
+    hq, ch = oracle.deconv(cols, want_ch=True)
+    M = _norm_rows(oracle.STAIN_HE)
+    ref = (-np.log((cols[0].astype(np.float64) + 1) / 256.0)) @ np.linalg.inv(M)[:, 0]
+    assert np.allclose(ch[0], ref, rtol=1e-12)
+    assert hq[0].tolist() == [19, 100, 54]
+
+
+# ----------------------------------------------------------------------------
+# morphological reconstruction (ReconToNuclei / IWPP, Sec. 5.1)
+# ----------------------------------------------------------------------------
+
+def _recon_cases(n, hi=12, neg=False):
+    r = np.random.Generator(np.random.PCG64(7))
+    for t in range(n):
+        h, w = (int(v) for v in r.integers(1, 15, 2))
+        lo = -5 if neg else 0
+        I = r.integers(lo, hi, (h, w))
+        J = np.where(r.random((h, w)) < 0.25, r.integers(lo, hi + 3, (h, w)), lo - 1)
+        dom = (r.random((h, w)) < 0.85).astype(np.uint8) if t % 3 else None
+        yield I, J, dom
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_recon_vs_iterated_dilation(oracle, conn):
+    for I, J, dom in _recon_cases(200, neg=True):
+        assert np.array_equal(oracle.recon(J, I, dom, conn), B.recon_iterate(J, I, dom, conn))
+
+
+def test_recon_u8_threshold_decomposition(oracle):
+    r = np.random.Generator(np.random.PCG64(8))
+    for t in range(40):
+        h, w = (int(v) for v in r.integers(2, 24, 2))
+        I = r.integers(0, 256, (h, w))
+        J = np.where(r.random((h, w)) < 0.1, r.integers(0, 256, (h, w)), 0)
+        for conn in (4, 8):
+            assert np.array_equal(oracle.recon(J, I, None, conn), B.recon_threshold_u8(J, I, conn))
+
+
+def test_recon_invariants(oracle):
+    r = np.random.Generator(np.random.PCG64(9))
+    for t in range(30):
+        h, w = (int(v) for v in r.integers(4, 40, 2))
+        I = r.integers(0, 50, (h, w))
+        J = np.where(r.random((h, w)) < 0.1, r.integers(0, 60, (h, w)), 0)
+        R = oracle.recon(J, I)
+        assert (R >= np.minimum(J, I)).all() and (R <= I).all()
+        assert np.array_equal(oracle.recon(R, I), R)               # idempotent
+        J2 = np.maximum(J, np.where(r.random((h, w)) < 0.05, 40, 0))
+        assert (oracle.recon(J2, I) >= R).all()                    # monotone in the marker
+        assert (oracle.recon(J, I + 3) >= R).all()                 # monotone in the mask
+
+
+def test_recon_binary_is_components_meeting_marker(oracle):
+    r = np.random.Generator(np.random.PCG64(10))
+    for t in range(30):
+        I = (r.random((30, 37)) < 0.55).astype(np.int32)
+        J = ((r.random((30, 37)) < 0.02) & (I > 0)).astype(np.int32)
+        lab, n = ndi.label(I, structure=np.ones((3, 3)))
+        hit = np.zeros(n + 1, bool)
+        hit[np.unique(lab[J > 0])] = True
+        hit[0] = False
+        assert np.array_equal(oracle.recon(J, I), hit[lab].astype(np.int32))
+
+
+def test_recon_spiral_long_chain(oracle):
+    s = synth.spiral(61, 67).astype(np.int32) * 9
+    J = np.zeros_like(s)
+    J[0, 0] = 9
+    R = oracle.recon(J, s, None, 4)
+    assert np.array_equal(R, s)        # the whole corridor is one path from (0, 0)
+
+
+# ----------------------------------------------------------------------------
+# FillHoles, BWLabel, AreaThreshold
+# ----------------------------------------------------------------------------
+
+def test_fill_holes_vs_scipy_and_bfs(oracle):
+    r = np.random.Generator(np.random.PCG64(11))
+    for t in range(60):
+        h, w = (int(v) for v in r.integers(1, 40, 2))
+        b = (r.random((h, w)) < r.uniform(0.2, 0.8)).astype(np.uint8)
+        ref = ndi.binary_fill_holes(b).astype(np.uint8)      # 4-connected background
+        assert np.array_equal(oracle.fill_holes(b, 4), ref)
+        assert np.array_equal(oracle.fill_holes(b, 8), B.bfs_fill_holes(b, 8))
+    rings = synth.nested_rings(33, 33)
+    assert np.array_equal(oracle.fill_holes(rings), ndi.binary_fill_holes(rings).astype(np.uint8))
+
+
+def test_fill_holes_diagonal_gap(oracle):
+    """A hole closed for the 4-connected background but open diagonally is filled."""
+    b = np.array([[0, 0, 0, 0, 0],
+                  [0, 1, 1, 0, 0],
+                  [0, 1, 0, 1, 0],
+                  [0, 0, 1, 1, 0],
+                  [0, 0, 0, 0, 0]], np.uint8)
+    out = oracle.fill_holes(b, 4)
+    assert out[2, 2] == 1
+    assert oracle.fill_holes(b, 8)[2, 2] == 0
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_ccl_vs_scipy(oracle, conn):
+    r = np.random.Generator(np.random.PCG64(12))
+    for t in range(80):
+        h, w = (int(v) for v in r.integers(1, 50, 2))
+        b = (r.random((h, w)) < r.uniform(0.1, 0.9)).astype(np.uint8)
+        lab, n = oracle.ccl(b, conn)
+        ref, nref = B.scipy_ccl(b, conn)
+        assert n == nref and np.array_equal(lab, ref)
+
+
+def test_ccl_special_shapes(oracle):
+    cb = synth.checkerboard(17, 19)
+    lab, n = oracle.ccl(cb, 8)
+    assert n == 1 and (lab[cb > 0] == 1).all()
+    lab4, n4 = oracle.ccl(cb, 4)
+    assert n4 == int(cb.sum())
+    sp = synth.spiral(40, 40)
+    lab, n = oracle.ccl(sp, 4)
+    assert n == 1
+    for shape in [(1, 1), (1, 9), (9, 1)]:
+        b = np.ones(shape, np.uint8)
+        lab, n = oracle.ccl(b, 8)
+        assert n == 1 and (lab == 1).all()
+    lab, n = oracle.ccl(np.zeros((5, 5), np.uint8), 8)
+    assert n == 0 and not lab.any()
+
+
+def test_area_filter_vs_bincount(oracle):
+    r = np.random.Generator(np.random.PCG64(13))
+    b = (r.random((64, 64)) < 0.45).astype(np.uint8)
+    lab, _ = oracle.ccl(b, 8)
+    cnt = np.bincount(lab.ravel(), minlength=lab.size + 1)
+    for lo, hi in [(1, 10 ** 9), (3, 20), (20, 1000), (5, 5)]:
+        out, mask, k = oracle.area_filter(lab, lo, hi)
+        keep = (lab > 0) & (cnt[lab] >= lo) & (cnt[lab] <= hi)
+        assert np.array_equal(out, np.where(keep, lab, 0))
+        assert np.array_equal(mask, keep.astype(np.uint8))
+        assert k == len(np.unique(lab[keep]))
+
+
+# ----------------------------------------------------------------------------
+# distance transform
+# ----------------------------------------------------------------------------
+
+def test_edt_vs_brute(oracle):
+    r = np.random.Generator(np.random.PCG64(14))
+    for t in range(60):
+        h, w = (int(v) for v in r.integers(1, 30, 2))
+        fg = (r.random((h, w)) < r.uniform(0.5, 0.99)).astype(np.uint8)
+        assert np.array_equal(oracle.edt_sq(fg), B.edt_sq_brute(fg))
+
+
+def test_edt_vs_scipy(oracle):
+    r = np.random.Generator(np.random.PCG64(15))
+    fg = (r.random((300, 257)) < 0.97).astype(np.uint8)
+    d = ndi.distance_transform_edt(fg)
+    assert np.array_equal(oracle.edt_sq(fg), np.rint(d * d).astype(np.int64))
+
+
+def test_edt_no_zero_and_single_zero(oracle):
+    assert (oracle.edt_sq(np.ones((7, 9), np.uint8)) == -1).all()
+    assert (oracle.dq(np.ones((7, 9), np.uint8)) == oracle.DQ_MAX).all()
+    fg = np.ones((9, 11), np.uint8)
+    fg[4, 5] = 0
+    yy, xx = np.mgrid[0:9, 0:11]
+    assert np.array_equal(oracle.edt_sq(fg), (yy - 4) ** 2 + (xx - 5) ** 2)
+
+
+def test_isqrt_boundaries(oracle):
+    top = 2 * 4 * 4095 ** 2
+    ks = list(range(0, 200)) + list(range(int(np.sqrt(top)) - 200, int(np.sqrt(top)) + 3))
+    ks += [int(v) for v in np.random.Generator(np.random.PCG64(16)).integers(0, int(np.sqrt(top)), 3000)]
+    for k in ks:
+        for n in (k * k - 1, k * k, k * k + 1, (k + 1) * (k + 1) - 1):
+            if n < 0:
+                continue
+            r = oracle.isqrt(n)
+            assert r * r <= n < (r + 1) * (r + 1)
+
+
+# ----------------------------------------------------------------------------
+# Pre-Watershed (seeds) and Watershed
+# ----------------------------------------------------------------------------
+
+def _blob_cases(n, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    for t in range(n):
+        h, w = (int(v) for v in r.integers(6, 22, 2))
+        yy, xx = np.mgrid[0:h, 0:w]
+        fg = np.zeros((h, w), bool)
+        for _ in range(int(r.integers(1, 4))):
+            cy, cx = r.uniform(0, h), r.uniform(0, w)
+            rad = r.uniform(2, 7)
+            fg |= (yy - cy) ** 2 + (xx - cx) ** 2 <= rad * rad
+        if t % 4 == 0:
+            fg |= r.random((h, w)) < 0.15
+        yield fg.astype(np.uint8)
+
+
+def test_dq_definition(oracle):
+    for fg in _blob_cases(40, 17):
+        d2 = B.edt_sq_brute(fg)
+        exp = np.where(fg > 0, np.floor(np.sqrt(4.0 * np.maximum(d2, 0))).astype(np.int64), 0)
+        if (d2 < 0).any():
+            exp = np.where(fg > 0, 65535, 0)
+        assert np.array_equal(oracle.dq(fg), exp)
+
+
+def test_seeds_are_regional_maxima_of_hmaxima(oracle):
+    for fg in _blob_cases(60, 18):
+        lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
+        dq = I["dq"]
+        g = B.recon_iterate(dq - 3, dq, fg, 8)
+        rm = B.regional_maxima(g, fg, 8)
+        assert np.array_equal(I["seeds"] > 0, rm)
+        ref, _ = B.scipy_ccl(rm, 8)
+        assert np.array_equal(I["seeds"], ref)
+        # every component of the foreground holds at least one seed
+        cl, n = B.scipy_ccl(fg, 8)
+        for c in np.unique(cl[cl > 0]):
+            assert (I["seeds"][cl == c] > 0).any()
+
+
+def test_lambda_is_widest_path(oracle):
+    for fg in _blob_cases(40, 19):
+        lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
+        dq = I["dq"]
+        mu = np.where(I["seeds"] > 0, dq, np.iinfo(np.int32).min)
+        assert np.array_equal(I["lam"], B.widest_path(mu, dq, fg, 8))
+
+
+def test_flood_by_definition_and_properties(oracle):
+    for fg in _blob_cases(40, 20):
+        lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
+        fl = I["flood"]
+        ref = B.flood_by_definition(fg, I["seeds"], I["lam"])
+        assert np.array_equal(fl, ref)
+        assert ((fl > 0) == (fg > 0)).all()                      # every foreground pixel labelled
+        for l in np.unique(fl[fl > 0]):
+            reg = fl == l
+            _, n = ndi.label(reg, structure=np.ones((3, 3)))
+            assert n == 1                                        # each region is 8-connected
+            assert len(np.unique(I["seeds"][reg & (I["seeds"] > 0)])) == 1   # and holds one seed
+
+
+def test_cut_separates_labels(oracle):
+    for fg in _blob_cases(40, 21):
+        lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
+        fl = I["flood"]
+        h, w = fl.shape
+        pad = np.pad(fl, 1)
+        keep = fl > 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                q = pad[1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
+                keep &= ~((q > 0) & (q < fl))
+        assert np.array_equal(mask, keep.astype(np.uint8))
+        ref, _ = B.scipy_ccl(keep, 8)
+        assert np.array_equal(lab, ref)
+
+
+def test_watershed_two_discs_split(oracle):
+    yy, xx = np.mgrid[0:40, 0:60]
+    fg = (((yy - 20) ** 2 + (xx - 20) ** 2 <= 100) | ((yy - 20) ** 2 + (xx - 37) ** 2 <= 100)).astype(np.uint8)
+    lab, mask = oracle.watershed(fg)
+    ids = np.unique(lab[lab > 0])
+    assert len(ids) == 2
+    left = lab[20, 15]
+    right = lab[20, 42]
+    assert left != right and left > 0 and right > 0
+    one, _ = oracle.watershed((((yy - 20) ** 2 + (xx - 30) ** 2) <= 144).astype(np.uint8))
+    assert len(np.unique(one[one > 0])) == 1
+
+
+def test_watershed_external_seeds_leftovers(oracle):
+    fg = np.zeros((20, 30), np.uint8)
+    fg[2:8, 2:10] = 1
+    fg[12:18, 15:28] = 1
+    seeds = np.zeros_like(fg)
+    seeds[4, 4] = 1
+    lab, mask, I = oracle.watershed(fg, seeds, 3, intermediates=True)
+    fl = I["flood"]
+    assert (fl[2:8, 2:10] == 4 * 30 + 4 + 1).all()               # flooded from the one seed
+    assert (fl[12:18, 15:28] == 12 * 30 + 15 + 1).all()          # seedless component: ccl label
+
+
+# ----------------------------------------------------------------------------
+# whole pipeline (sanity only: no per-tile values are printed in the paper)
+# ----------------------------------------------------------------------------
+
+def test_pipeline_sanity_small_tile(oracle):
+    rgb, gt, info = synth.make_tile(synth.spec_small(0))
+    hq, mask, lab, n = oracle.segment_rgb(rgb)
+    fgt = gt > 0
+    dice = 2 * (mask.astype(bool) & fgt).sum() / (mask.sum() + fgt.sum())
+    assert dice > 0.93
+    assert 70 <= n <= 110
+    ids, cnt = np.unique(lab[lab > 0], return_counts=True)
+    assert n == len(ids) and (cnt >= 20).all() and (cnt <= 1000).all()
+    # labels are canonical
+    assert np.array_equal(lab, B.canon_labels(lab))
