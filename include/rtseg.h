@@ -1,0 +1,172 @@
+/*
+ * rtseg.h -- C ABI of the MI355X (gfx950) per-tile nucleus segmentation
+ * library librtseg.so.
+ *
+ * What is computed: the segmentation stage of the example application of
+ * Teodoro et al., "Region Templates" (Sec. 5.1, Example Application): a stage
+ * receives an RGB tile and produces a mask of segmented nuclei (the
+ * RGB-in / Mask-out stage boundary of Fig. 8b, Sec. 3.4).  The paper names the
+ * operations -- colour deconvolution, ReconToNuclei, FillHoles,
+ * AreaThreshold, BWLabel (union-find CCL), Pre-Watershed and Watershed
+ * (Sec. 5.1; the operation list of the PATS discussion, Sec. 3.2.1) -- but
+ * defines none of them; the definitions each entry point implements are
+ * stated below.
+ *
+ * Conventions for every entry point
+ *   - Image pointers are DEVICE pointers (e.g. PyTorch CUDA/HIP tensors).  The
+ *     caller owns every buffer; the library never frees caller memory.
+ *   - Images are row-major.  Pixel (x, y) of an image with pitch P (in
+ *     elements, P >= w; for RGB the pitch is in bytes, >= 3*w) is element
+ *     y*P + x.  Label values use the WIDTH, never the pitch:
+ *     label = 1 + y*w + x of the component's first pixel in row-major order.
+ *   - Connectivity 8 = the 3x3 neighbourhood, 4 = the cross.  Only in-tile
+ *     pixels exist (no virtual padding beyond the tile edge).
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *     is the default stream) unless noted.  A few calls must read a small
+ *     device counter to decide how many propagation rounds to launch; they
+ *     synchronise `stream` for that and say so.
+ *   - Scratch memory comes from the context and is reused by later calls on
+ *     the same context: one context must not be used by two host threads (or
+ *     two streams) at once.
+ *   - Return value 0 = RT_OK; a negative value is an error code and
+ *     rt_last_error() returns a thread-local message.  Asynchronous kernel
+ *     faults surface on a later call or in rt_sync().
+ */
+#ifndef RTSEG_H
+#define RTSEG_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_OK 0
+#define RT_EINVAL (-1)       /* bad argument: null pointer, w/h <= 0, pitch < w, w*h >= 2^31, bad conn/dtype, min > max */
+#define RT_ENOMEM (-2)       /* scratch allocation failed */
+#define RT_EDEVICE (-3)      /* HIP runtime error */
+#define RT_EUNSUPPORTED (-4) /* valid request this build does not implement */
+
+#define RT_U8 1
+#define RT_I32 2
+
+#define RT_DQ_MAX 65535
+
+typedef struct rt_ctx rt_ctx;
+
+/* Creates a context on HIP device `device`.  *out receives the handle. */
+int rt_ctx_create(int device, rt_ctx **out);
+/* Frees the context's scratch memory (synchronises the device first). */
+int rt_ctx_destroy(rt_ctx *ctx);
+/* Message of the last error on the calling thread ("" if none). */
+const char *rt_last_error(void);
+/* Waits for `stream`, then reports any pending asynchronous device error. */
+int rt_sync(rt_ctx *ctx, void *stream);
+
+/*
+ * Colour deconvolution (Sec. 5.1; Ruifrok-Johnston stain separation).
+ * stain_rows: 3 optical-density row vectors (hematoxylin, eosin, third); each
+ * is L2-normalised and a zero third row is replaced by normalize(H x E).  With
+ * M = [H; E; third], OD = c * M, so c_H = sum_k OD_k * inv(M)[k][0], with
+ * OD_k = -ln((I_k + 1) / 256).  The sum is evaluated in FP64 as
+ * (R-term + G-term) + B-term without contraction, and
+ * hq = clamp(floor(c_H * hq_scale + 0.5), 0, 255).
+ * rgb: interleaved RGB bytes, row pitch rgb_pitch_bytes.  cH_out (nullable):
+ * float c_H, pitch cH_pitch elements.  hq_out: uint8, pitch hq_pitch.
+ * Errors: RT_EINVAL for a singular stain matrix or bad sizes.
+ */
+int rt_deconv(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, int32_t w, int32_t h,
+              const double stain_rows[9], double hq_scale, float *cH_out, int64_t cH_pitch,
+              uint8_t *hq_out, int64_t hq_pitch, void *stream);
+
+/*
+ * Grayscale reconstruction by dilation (the IWPP operation behind
+ * ReconToNuclei, Sec. 5.1).  dtype RT_U8 (uint8 images) or RT_I32 (int32).
+ * out(p) = max over paths p0..pn = p inside the graph of
+ *          min(min(marker,mask)(p0), mask(p1), ..., mask(pn)).
+ * Graph nodes are the pixels with domain != 0 (all pixels if domain is NULL);
+ * pixels outside the domain get min(marker, mask) and take no part.
+ * marker, mask, out and domain share `pitch` (elements).  out may alias
+ * marker.  conn is 4 or 8.  Synchronises `stream` between propagation rounds.
+ */
+int rt_morph_recon(rt_ctx *ctx, int dtype, const void *marker, const void *mask, void *out,
+                   const uint8_t *domain, int32_t w, int32_t h, int64_t pitch, int conn, void *stream);
+
+/*
+ * FillHoles (Sec. 5.1): a 0-pixel of `in` stays 0 iff it is
+ * bg_conn-connected through 0-pixels to a 0-pixel on the tile frame; every
+ * other pixel becomes 1.  bg_conn is 4 (default) or 8.  out may alias in.
+ */
+int rt_fill_holes(rt_ctx *ctx, const uint8_t *in, uint8_t *out, int32_t w, int32_t h, int64_t pitch,
+                  int bg_conn, void *stream);
+
+/*
+ * BWLabel (Sec. 5.1; union-find forest, merge, flatten).  Labels the nonzero
+ * pixels of `mask`: label(p) = 1 + min{ y*w + x : (x, y) in the component of p },
+ * 0 for background.  labels is int32 with pitch `pitch`.  n_out_dev (nullable,
+ * device int32) receives the number of components.
+ */
+int rt_ccl(rt_ctx *ctx, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
+           int32_t *n_out_dev, void *stream);
+
+/*
+ * AreaThreshold (Sec. 5.1): a component (pixels sharing one positive label)
+ * with min_area <= area <= max_area keeps its label; other pixels become 0.
+ * Labels must be < w*h + 1 (e.g. produced by rt_ccl).  mask_out (nullable,
+ * uint8) = labels_out != 0.  labels_out may alias labels_in.
+ */
+int rt_area_filter(rt_ctx *ctx, const int32_t *labels_in, int32_t *labels_out, uint8_t *mask_out,
+                   int32_t w, int32_t h, int64_t pitch, int32_t min_area, int32_t max_area, void *stream);
+
+/*
+ * Pre-Watershed + Watershed (Sec. 5.1) on the foreground A = (fg != 0):
+ *   Dq = floor(sqrt(4 d2)), d2 = squared distance to the nearest in-tile
+ *        0-pixel of A (RT_DQ_MAX if A has no 0-pixel);
+ *   seeds (seeds == NULL): regional maxima of the h-maxima transform
+ *        g = recon_A(Dq - h_seed under Dq), labelled by 8-connected CCL;
+ *        otherwise the 8-connected components of (seeds != 0) AND A;
+ *   lambda = recon_A(Dq on seed pixels under Dq);
+ *   flood from high to low lambda: a breadth-first search into each level set
+ *        from everything labelled so far, where a pixel takes the smallest
+ *        label among its neighbours in the previous search layer; pixels never
+ *        reached (possible only with external seeds) are labelled by CCL;
+ *   cut: p is kept iff no 8-neighbour carries a smaller nonzero label;
+ *   labels_out = 8-connected CCL of the kept pixels, mask_out = kept pixels.
+ * fg, seeds, mask_out (uint8) and labels_out (int32) share `pitch`.
+ */
+int rt_watershed(rt_ctx *ctx, const uint8_t *fg, const uint8_t *seeds, int32_t h_seed, int32_t *labels_out,
+                 uint8_t *mask_out, int32_t w, int32_t h, int64_t pitch, void *stream);
+
+/* Parameters of the whole plain pipeline.  size must be sizeof(rt_seg_params). */
+typedef struct {
+    uint32_t size;
+    double stain_rows[9]; /* H, E, third (zero row = H x E) optical-density vectors */
+    double hq_scale;      /* 85.0 */
+    int32_t t_fg;         /* top-hat threshold, 16 */
+    int32_t min_area;     /* 20 */
+    int32_t max_area;     /* 1000 */
+    int32_t h_seed;       /* 3 (half-pixel units) */
+    int32_t conn;         /* foreground connectivity, 8 */
+} rt_seg_params;
+
+/* Fills p with the defaults above (Ruifrok-Johnston H&E vectors). */
+void rt_seg_params_default(rt_seg_params *p);
+
+/*
+ * Segmentation stage of one tile (RGB in, mask + labels out):
+ *   Hq = deconvolution; R = recon8(J under Hq) with J = Hq on the 1-px tile
+ *   frame and 0 inside (ReconToNuclei); F0 = [Hq - R >= t_fg];
+ *   F = FillHoles(F0, 4); L1 = CCL8(F); A = components of L1 with
+ *   area >= min_area; watershed(A, h_seed); labels = components of its
+ *   CCL8 with min_area <= area <= max_area; mask = labels != 0.
+ * mask_out (uint8) and labels_out (int32) share out_pitch.  n_objects_dev
+ * (nullable, device int32) receives the number of kept objects.  hq_out
+ * (nullable, uint8, pitch out_pitch) receives the quantised hematoxylin
+ * channel.  Synchronises `stream` between reconstruction rounds.
+ */
+int rt_segment_tile(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, int32_t w, int32_t h,
+                    const rt_seg_params *params, uint8_t *mask_out, int32_t *labels_out, int64_t out_pitch,
+                    int32_t *n_objects_dev, uint8_t *hq_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,249 @@
+"""Python binding of librtseg.so (C ABI in include/rtseg.h).
+
+Argument marshalling only: every step of the segmentation runs in the HIP
+kernels of librtseg.so.  Tensors must be HIP device tensors (torch ``cuda``
+tensors on ROCm) of the stated dtype; 2-D images may be row-pitched (last
+stride 1).  Calls are enqueued on torch's current stream.  If the library is
+not built, every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtseg.so")
+
+RT_OK = 0
+RT_EINVAL = -1
+RT_ENOMEM = -2
+RT_EDEVICE = -3
+RT_EUNSUPPORTED = -4
+RT_U8 = 1
+RT_I32 = 2
+DQ_MAX = 65535
+
+
+class RtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rtseg error {code}: {msg}")
+        self.code = code
+
+
+class rt_seg_params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("stain_rows", C.c_double * 9), ("hq_scale", C.c_double),
+                ("t_fg", C.c_int32), ("min_area", C.c_int32), ("max_area", C.c_int32),
+                ("h_seed", C.c_int32), ("conn", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.rt_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.rt_ctx_destroy.argtypes = [vp]
+        L.rt_last_error.restype = C.c_char_p
+        L.rt_sync.argtypes = [vp, vp]
+        L.rt_deconv.argtypes = [vp, vp, i64, i32, i32, C.POINTER(C.c_double), C.c_double, vp, i64, vp, i64, vp]
+        L.rt_morph_recon.argtypes = [vp, C.c_int, vp, vp, vp, vp, i32, i32, i64, C.c_int, vp]
+        L.rt_fill_holes.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp]
+        L.rt_ccl.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp, vp]
+        L.rt_area_filter.argtypes = [vp, vp, vp, vp, i32, i32, i64, i32, i32, vp]
+        L.rt_watershed.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, i64, vp]
+        L.rt_seg_params_default.argtypes = [C.POINTER(rt_seg_params)]
+        L.rt_segment_tile.argtypes = [vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), vp, vp, i64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RT_OK:
+        raise RtError(rc, lib().rt_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _img(t, dtype, name, channels=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if channels is None:
+        if t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{name}: expected a 2-D row-major image")
+    else:
+        if t.dim() != 3 or t.shape[2] != channels or t.stride(2) != 1 or t.stride(1) != channels:
+            raise ValueError(f"{name}: expected an (H, W, {channels}) interleaved image")
+    return t
+
+
+class Context:
+    """Owns an rt_ctx (scratch memory) on one device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().rt_ctx_create(device, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().rt_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(lib().rt_sync(self.h, _stream()))
+
+
+_default = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def default_params(**over):
+    p = rt_seg_params()
+    lib().rt_seg_params_default(C.byref(p))
+    for k, v in over.items():
+        if k == "stain_rows":
+            for i in range(9):
+                p.stain_rows[i] = float(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+STAIN_HE = (0.650, 0.704, 0.286, 0.072, 0.990, 0.105, 0.0, 0.0, 0.0)
+
+
+def rt_deconv(rgb, stain=STAIN_HE, hq_scale=85.0, want_ch=False, ctx=None, hq_out=None):
+    ctx = ctx or default_context(rgb.device.index)
+    _img(rgb, torch.uint8, "rgb", 3)
+    h, w = rgb.shape[:2]
+    hq = hq_out if hq_out is not None else torch.empty((h, w), dtype=torch.uint8, device=rgb.device)
+    ch = torch.empty((h, w), dtype=torch.float32, device=rgb.device) if want_ch else None
+    st = (C.c_double * 9)(*[float(v) for v in stain])
+    _check(lib().rt_deconv(ctx.h, _ptr(rgb), rgb.stride(0), w, h, st, float(hq_scale), _ptr(ch),
+                           ch.stride(0) if ch is not None else 0, _ptr(hq), hq.stride(0), _stream()))
+    return (hq, ch) if want_ch else hq
+
+
+def rt_morph_recon(marker, mask, domain=None, conn=8, out=None, ctx=None):
+    ctx = ctx or default_context(mask.device.index)
+    if mask.dtype == torch.uint8:
+        dt = RT_U8
+    elif mask.dtype == torch.int32:
+        dt = RT_I32
+    else:
+        raise TypeError("rt_morph_recon: uint8 or int32 images")
+    _img(mask, mask.dtype, "mask")
+    _img(marker, mask.dtype, "marker")
+    if marker.shape != mask.shape or marker.stride(0) != mask.stride(0):
+        raise ValueError("marker and mask must share shape and pitch")
+    if domain is not None:
+        _img(domain, torch.uint8, "domain")
+        if domain.shape != mask.shape or domain.stride(0) != mask.stride(0):
+            raise ValueError("domain must share shape and pitch with mask")
+    h, w = mask.shape
+    if out is None:
+        out = torch.empty_strided(mask.shape, mask.stride(), dtype=mask.dtype, device=mask.device)
+    _check(lib().rt_morph_recon(ctx.h, dt, _ptr(marker), _ptr(mask), _ptr(out), _ptr(domain), w, h,
+                                mask.stride(0), conn, _stream()))
+    return out
+
+
+def rt_fill_holes(binary, bg_conn=4, out=None, ctx=None):
+    ctx = ctx or default_context(binary.device.index)
+    _img(binary, torch.uint8, "binary")
+    h, w = binary.shape
+    if out is None:
+        out = torch.empty_strided(binary.shape, binary.stride(), dtype=torch.uint8, device=binary.device)
+    _check(lib().rt_fill_holes(ctx.h, _ptr(binary), _ptr(out), w, h, binary.stride(0), bg_conn, _stream()))
+    return out
+
+
+def rt_ccl(binary, conn=8, ctx=None):
+    """Returns (labels int32, n_components as a 1-element device tensor)."""
+    ctx = ctx or default_context(binary.device.index)
+    _img(binary, torch.uint8, "binary")
+    h, w = binary.shape
+    lab = torch.empty_strided(binary.shape, binary.stride(), dtype=torch.int32, device=binary.device)
+    n = torch.zeros(1, dtype=torch.int32, device=binary.device)
+    _check(lib().rt_ccl(ctx.h, _ptr(binary), _ptr(lab), w, h, binary.stride(0), conn, _ptr(n), _stream()))
+    return lab, n
+
+
+def rt_area_filter(labels, min_area, max_area, ctx=None):
+    ctx = ctx or default_context(labels.device.index)
+    _img(labels, torch.int32, "labels")
+    h, w = labels.shape
+    out = torch.empty_strided(labels.shape, labels.stride(), dtype=torch.int32, device=labels.device)
+    mask = torch.empty_strided(labels.shape, labels.stride(), dtype=torch.uint8, device=labels.device)
+    _check(lib().rt_area_filter(ctx.h, _ptr(labels), _ptr(out), _ptr(mask), w, h, labels.stride(0),
+                                int(min_area), int(max_area), _stream()))
+    return out, mask
+
+
+def rt_watershed(fg, seeds=None, h_seed=3, ctx=None):
+    ctx = ctx or default_context(fg.device.index)
+    _img(fg, torch.uint8, "fg")
+    if seeds is not None:
+        _img(seeds, torch.uint8, "seeds")
+        if seeds.shape != fg.shape or seeds.stride(0) != fg.stride(0):
+            raise ValueError("seeds must share shape and pitch with fg")
+    h, w = fg.shape
+    lab = torch.empty_strided(fg.shape, fg.stride(), dtype=torch.int32, device=fg.device)
+    mask = torch.empty_strided(fg.shape, fg.stride(), dtype=torch.uint8, device=fg.device)
+    _check(lib().rt_watershed(ctx.h, _ptr(fg), _ptr(seeds), int(h_seed), _ptr(lab), _ptr(mask), w, h,
+                              fg.stride(0), _stream()))
+    return lab, mask
+
+
+def rt_segment_tile(rgb, params=None, want_hq=False, ctx=None, out=None):
+    """Returns (mask uint8, labels int32, n_objects 1-element device tensor[, hq])."""
+    ctx = ctx or default_context(rgb.device.index)
+    _img(rgb, torch.uint8, "rgb", 3)
+    h, w = rgb.shape[:2]
+    p = params if params is not None else default_params()
+    if out is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=rgb.device)
+        lab = torch.empty((h, w), dtype=torch.int32, device=rgb.device)
+        n = torch.zeros(1, dtype=torch.int32, device=rgb.device)
+        hq = torch.empty((h, w), dtype=torch.uint8, device=rgb.device) if want_hq else None
+    else:
+        mask, lab, n, hq = out
+    _check(lib().rt_segment_tile(ctx.h, _ptr(rgb), rgb.stride(0), w, h, C.byref(p), _ptr(mask), _ptr(lab),
+                                 lab.stride(0), _ptr(n), _ptr(hq), _stream()))
+    return (mask, lab, n, hq) if want_hq else (mask, lab, n)
+
+
+EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
+           "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
+           "rt_segment_tile")
