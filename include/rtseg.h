@@ -166,6 +166,42 @@ int rt_segment_tile(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, in
                     const rt_seg_params *params, uint8_t *mask_out, int32_t *labels_out, int64_t out_pitch,
                     int32_t *n_objects_dev, uint8_t *hq_out, void *stream);
 
+/*
+ * Tuning knobs of a context (set by the autotuner; results never depend on
+ * them, only speed does):
+ *   "recon_levels"      0..8  threshold levels of the frame-connectivity lower
+ *                             bound that starts ReconToNuclei (0 = start from
+ *                             the frame marker alone); default 8
+ *   "recon_round_batch" 1..64 propagation rounds launched between two reads of
+ *                             the worklist counter; default 4
+ *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;
+ *                             default 64
+ * Errors: RT_EINVAL for an unknown name or a value out of range.
+ */
+int rt_set_knob(rt_ctx *ctx, const char *name, int value);
+int rt_get_knob(rt_ctx *ctx, const char *name, int *value);
+
+/*
+ * Stage timing, for benchmarks.  While enabled, rt_segment_tile records HIP
+ * events on its own stream at the boundaries of its stages:
+ *   0 deconv       colour deconvolution (table, histogram, pixels)
+ *   1 level_bound  frame connectivity of the upper level sets (CCL, 8 levels)
+ *   2 recon        reconstruction rounds (one launch per round)
+ *   3 fill_holes   FillHoles (background CCL)
+ *   4 ccl          BWLabel with component area and bounding box
+ *   5 objects      per-object Pre-Watershed + Watershed + relabel + area
+ *   6 objects_big  the same for components larger than the LDS budget
+ * Recording adds no synchronisation.  rt_profile_read synchronises the
+ * recorded events, adds the elapsed milliseconds of each stage over all
+ * calls since the last read into ms[i] and the number of kernel launches
+ * into launches[i] (i < max_stages), clears the record and returns the number
+ * of profiled calls.
+ */
+#define RT_PROF_STAGES 7
+int rt_profile_enable(rt_ctx *ctx, int enable);
+int rt_profile_read(rt_ctx *ctx, double *ms, int64_t *launches, int max_stages);
+const char *rt_profile_stage_name(int stage);
+
 #ifdef __cplusplus
 }
 #endif

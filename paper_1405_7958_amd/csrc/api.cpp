@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <string>
 
 #include "rt_internal.h"
 
@@ -70,8 +71,6 @@ int ensure_stamps(rt_ctx_impl *c, size_t ntiles) {
     return RT_OK;
 }
 
-size_t big_object_bytes(size_t n);
-
 }  // namespace rtseg
 
 using namespace rtseg;
@@ -119,24 +118,48 @@ bool stain_ok(const double r[9]) {
 
 int set_dev(rt_ctx *c) { return hip_fail(hipSetDevice(c->device), "hipSetDevice"); }
 
+const char *kStageNames[RT_PROF_STAGES] = {"deconv", "level_bound", "recon", "fill_holes", "ccl", "objects",
+                                           "objects_big"};
+
+// Records the boundary event `k` (0..RT_PROF_STAGES) of the current profiled call.
+int prof_mark(rt_ctx *c, int k, hipStream_t s) {
+    if (!c->prof_on) return RT_OK;
+    size_t idx = c->prof_used + (size_t)k;
+    while (c->prof_events.size() <= idx) {
+        hipEvent_t ev;
+        RT_HIP(hipEventCreate(&ev));
+        c->prof_events.push_back(ev);
+    }
+    RT_HIP(hipEventRecord(c->prof_events[idx], s));
+    if (k == RT_PROF_STAGES) {
+        c->prof_used += RT_PROF_STAGES + 1;
+        c->prof_calls++;
+    }
+    return RT_OK;
+}
+
 // Scratch layout of one CCL: ids (w*h+1) per level.
 size_t ccl_ids_bytes(int w, int h, int nlev) { return al(sizeof(int32_t) * ((size_t)w * h + 1) * nlev); }
 
 struct CompScratch {
-    int32_t *ids, *area, *x0, *x1, *y0, *y1, *obj, *n_obj, *big, *n_big, *n_kept;
-    int32_t *big_scratch;
-    size_t big_elems;
+    int32_t *ids, *area, *x0, *x1, *y0, *y1, *obj, *list_m, *big;
+    int32_t *n_obj, *n_m, *n_big, *n_kept;
+    void *big_scratch;
+    size_t big_bytes;
     size_t max_obj;
 };
 
-size_t comp_scratch_bytes(int w, int h, size_t big_bytes) {
+// Scratch of BWLabel + the per-object stage: component ids, statistics and
+// lists, plus slices for crops too large for LDS (4 slices of the largest
+// possible crop).
+size_t comp_scratch_bytes(int w, int h) {
     size_t n1 = (size_t)w * h + 1;
     size_t max_obj = ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
-    return ccl_ids_bytes(w, h, 1) + 5 * al(sizeof(int32_t) * n1) + 2 * al(sizeof(int32_t) * max_obj) +
-           al(sizeof(int32_t) * 8) + al(big_bytes);
+    return ccl_ids_bytes(w, h, 1) + 5 * al(sizeof(int32_t) * n1) + 3 * al(sizeof(int32_t) * max_obj) +
+           al(sizeof(int32_t) * 8) + 4 * al(big_object_bytes(w, h));
 }
 
-int carve_comp(rt_ctx *c, int w, int h, size_t big_bytes, CompScratch &cs) {
+int carve_comp(rt_ctx *c, int w, int h, CompScratch &cs) {
     size_t n1 = (size_t)w * h + 1;
     cs.max_obj = ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
     cs.ids = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
@@ -146,40 +169,38 @@ int carve_comp(rt_ctx *c, int w, int h, size_t big_bytes, CompScratch &cs) {
     cs.y0 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
     cs.y1 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
     cs.obj = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
+    cs.list_m = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
     cs.big = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
     int32_t *ctr = (int32_t *)c->arena.take(sizeof(int32_t) * 8);
-    cs.big_scratch = (int32_t *)c->arena.take(big_bytes);
-    cs.big_elems = big_bytes / sizeof(int32_t);
-    if (!cs.ids || !cs.area || !cs.x0 || !cs.x1 || !cs.y0 || !cs.y1 || !cs.obj || !cs.big || !ctr ||
+    cs.big_bytes = 4 * al(big_object_bytes(w, h));
+    cs.big_scratch = c->arena.take(cs.big_bytes);
+    if (!cs.ids || !cs.area || !cs.x0 || !cs.x1 || !cs.y0 || !cs.y1 || !cs.obj || !cs.list_m || !cs.big || !ctr ||
         !cs.big_scratch) {
         set_error("scratch arena too small");
         return RT_ENOMEM;
     }
     cs.n_obj = ctr;
-    cs.n_big = ctr + 1;
-    cs.n_kept = ctr + 2;
+    cs.n_m = ctr + 1;
+    cs.n_big = ctr + 2;
+    cs.n_kept = ctr + 3;
     return RT_OK;
 }
 
-// CCL of `fg` (8-connected) with statistics, then the per-object watershed.
-int components_and_watershed(rt_ctx *c, const uint8_t *fg_a, const uint8_t *fg_b, CclPred pred, int t,
-                             int64_t pitch_a, int64_t pitch_b, const uint8_t *seeds, int h_seed,
+// BWLabel (8-connected) with statistics, then the per-object watershed.
+int components_and_watershed(rt_ctx *c, const uint8_t *fg, int64_t pitch_fg, const uint8_t *seeds, int h_seed,
                              int min_area_pre, int min_area, int max_area, int32_t *labels, uint8_t *mask,
                              int64_t pitch, int w, int h, CompScratch &cs, int32_t *n_kept_out, hipStream_t s) {
-    int e = launch_fill_i32(cs.n_obj, 0, 3, s);
+    int e = launch_fill_i32(cs.n_obj, 0, 4, s);
     if (e) return e;
     CclArgs A{};
-    A.pred = pred;
+    A.pred = CclPred::NonZero;
     A.out = CclOut::Labels;
     A.conn = 8;
     A.frame_virtual = false;
     A.w = w;
     A.h = h;
-    A.a = fg_a;
-    A.b = fg_b;
-    A.pitch_a = pitch_a;
-    A.pitch_b = pitch_b;
-    A.t = t;
+    A.a = fg;
+    A.pitch_a = pitch_fg;
     A.ids = cs.ids;
     A.labels = labels;
     A.pitch_l = pitch;
@@ -194,13 +215,15 @@ int components_and_watershed(rt_ctx *c, const uint8_t *fg_a, const uint8_t *fg_b
     A.n_obj = cs.n_obj;
     e = launch_ccl(A, s);
     if (e) return e;
+    e = prof_mark(c, 5, s);
+    if (e) return e;
+    c->prof_launches[4] += 4;
     ObjArgs o{};
     o.w = w;
     o.h = h;
     o.pitch = pitch;
     o.obj_list = cs.obj;
     o.n_obj = cs.n_obj;
-    o.max_obj = std::max(1, c->n_cu * 8);
     o.st_area = cs.area;
     o.st_x0 = cs.x0;
     o.st_x1 = cs.x1;
@@ -214,20 +237,19 @@ int components_and_watershed(rt_ctx *c, const uint8_t *fg_a, const uint8_t *fg_b
     o.min_area = min_area;
     o.max_area = max_area;
     o.n_kept = cs.n_kept;
-    o.tile_has_zero = 1;
-    o.big_scratch = cs.big_scratch;
-    o.big_scratch_elems = cs.big_elems;
+    o.list_m = cs.list_m;
+    o.n_m = cs.n_m;
     o.big_list = cs.big;
     o.n_big = cs.n_big;
-    e = launch_objects(o, s);
+    o.big_scratch = cs.big_scratch;
+    o.big_scratch_bytes = cs.big_bytes;
+    e = launch_objects(o, c->n_cu, s);
     if (e) return e;
-    RT_HIP(hipMemcpyAsync(c->pinned, cs.n_big, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    RT_HIP(hipStreamSynchronize(s));
-    int nbig = c->pinned[0];
-    if (nbig > 0) {
-        e = launch_objects_big(o, nbig, s);
-        if (e) return e;
-    }
+    e = prof_mark(c, 6, s);
+    if (e) return e;
+    c->prof_launches[5] += 3;
+    e = prof_mark(c, 7, s);
+    if (e) return e;
     if (n_kept_out) RT_HIP(hipMemcpyAsync(n_kept_out, cs.n_kept, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     return RT_OK;
 }
@@ -283,6 +305,7 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->stamps) (void)hipFree(c->stamps);
     if (c->lut) (void)hipFree(c->lut);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
     delete c;
     return RT_OK;
 }
@@ -324,7 +347,7 @@ int rt_morph_recon(rt_ctx *c, int dtype, const void *marker, const void *mask, v
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    int64_t ntiles = ((w + 63) / 64) * (int64_t)((h + 63) / 64);
+    int64_t ntiles = recon_tiles(w, h);
     e = ensure_arena(c, al(sizeof(int32_t) * (2 * ntiles + 4)) + 4096);
     if (e) return e;
     e = recon_init(dtype, marker, mask, out, domain, w, h, pitch, s);
@@ -410,14 +433,17 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    size_t big = big_object_bytes((size_t)w * h) * 2;
-    e = ensure_arena(c, comp_scratch_bytes(w, h, big) + 8192);
+    e = ensure_arena(c, comp_scratch_bytes(w, h) + 8192);
     if (e) return e;
     CompScratch cs;
-    e = carve_comp(c, w, h, big, cs);
+    e = carve_comp(c, w, h, cs);
     if (e) return e;
-    return components_and_watershed(c, fg, nullptr, CclPred::NonZero, 0, pitch, 0, seeds, h_seed, 0, 0, -1,
-                                    labels_out, mask_out, pitch, w, h, cs, nullptr, s);
+    const bool prof = c->prof_on;
+    c->prof_on = false;  // stage events belong to rt_segment_tile
+    e = components_and_watershed(c, fg, pitch, seeds, h_seed, 0, 0, -1, labels_out, mask_out, pitch, w, h, cs,
+                                 nullptr, s);
+    c->prof_on = prof;
+    return e;
 }
 
 int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h,
@@ -439,10 +465,10 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
     hipStream_t s = as_stream(stream);
     const size_t N = (size_t)w * h;
     const int nlev = c->knobs.recon_levels;
-    const int64_t ntiles = ((w + 63) / 64) * (int64_t)((h + 63) / 64);
-    size_t big = big_object_bytes(N) * 2;
-    size_t need = 3 * al(N) + al(256 * 4) + al(64) + ccl_ids_bytes(w, h, nlev) + comp_scratch_bytes(w, h, big) +
-                  al(sizeof(int32_t) * (2 * ntiles + 4)) + 16384;
+    const int64_t ntiles = recon_tiles(w, h);
+    size_t need = 3 * al(N) + al(256 * 4) + al(64) +
+                  std::max(ccl_ids_bytes(w, h, std::max(nlev, 1)) + al(sizeof(int32_t) * (2 * ntiles + 4)),
+                           comp_scratch_bytes(w, h)) + 16384;
     e = ensure_arena(c, need);
     if (e) return e;
     uint8_t *hq = hq_out ? hq_out : (uint8_t *)c->arena.take(N);
@@ -452,11 +478,20 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
     uint32_t *hist = (uint32_t *)c->arena.take(256 * 4);
     int32_t *levels = (int32_t *)c->arena.take(64);
     const size_t mark = c->arena.off;  // the later CCL scratch reuses the level ids
-    int32_t *lev_ids = (int32_t *)c->arena.take(sizeof(int32_t) * (N + 1) * nlev);
+    int32_t *lev_ids = (int32_t *)c->arena.take(sizeof(int32_t) * (N + 1) * std::max(nlev, 1));
     if (!hq || !R || !F || !hist || !levels || !lev_ids) {
         set_error("rt_segment_tile: scratch arena too small");
         return RT_ENOMEM;
     }
+    // only rt_segment_tile records stage events
+    const bool prof = c->prof_on;
+    struct ProfGuard {
+        rt_ctx *c;
+        bool on;
+        ~ProfGuard() { c->prof_on = on; }
+    } guard{c, prof};
+    e = prof_mark(c, 0, s);
+    if (e) return e;
     // 1. colour deconvolution + histogram of Hq
     StainParams sp;
     std::memcpy(sp.rows, p->stain_rows, sizeof sp.rows);
@@ -468,11 +503,14 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
     e = launch_deconv(c->lut, p->hq_scale, rgb, rgb_pitch, w, h, nullptr, 0, hq, hq_pitch, nullptr, 0, hist,
                       c->n_cu, s);
     if (e) return e;
+    e = prof_mark(c, 1, s);
+    if (e) return e;
+    c->prof_launches[0] += 3;
     // 2. ReconToNuclei: start from the frame marker raised by the frame
     //    connectivity of a few upper level sets, then propagate
-    e = launch_select_levels(hist, nlev, levels, s);
-    if (e) return e;
-    {
+    if (nlev > 0) {
+        e = launch_select_levels(hist, nlev, levels, s);
+        if (e) return e;
         CclArgs A{};
         A.pred = CclPred::Level;
         A.out = CclOut::LevelBound;
@@ -489,11 +527,22 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
         A.pitch_r = w;
         e = launch_ccl(A, s);
         if (e) return e;
+        c->prof_launches[1] += 4 + nlev;
+    } else {
+        e = launch_frame_marker(hq, hq_pitch, R, w, w, h, s);
+        if (e) return e;
+        c->prof_launches[1] += 1;
     }
+    e = prof_mark(c, 2, s);
+    if (e) return e;
     {
         ReconArgs ra{RT_U8, 8, w, h, (int64_t)w, hq, R, nullptr};
-        e = recon_rounds(c, ra, s);
+        int rounds = 0;
+        e = recon_rounds(c, ra, s, &rounds);
         if (e) return e;
+        e = prof_mark(c, 3, s);
+        if (e) return e;
+        c->prof_launches[2] += rounds;
     }
     // 3. F0 = [Hq - R >= t]; FillHoles through the 4-connected background
     {
@@ -516,15 +565,87 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
         A.pitch_f = w;
         e = launch_ccl(A, s);
         if (e) return e;
+        e = prof_mark(c, 4, s);
+        if (e) return e;
+        c->prof_launches[3] += 4;
     }
     // 4-8. BWLabel + AreaThreshold + Pre-Watershed/Watershed + relabel + AreaThreshold
     c->arena.off = mark;
     CompScratch cs;
-    e = carve_comp(c, w, h, big, cs);
+    e = carve_comp(c, w, h, cs);
     if (e) return e;
-    return components_and_watershed(c, F, nullptr, CclPred::NonZero, 0, w, 0, nullptr, p->h_seed, p->min_area,
-                                    p->min_area, p->max_area, labels_out, mask_out, out_pitch, w, h, cs,
-                                    n_objects_dev, s);
+    return components_and_watershed(c, F, w, nullptr, p->h_seed, p->min_area, p->min_area, p->max_area, labels_out,
+                                    mask_out, out_pitch, w, h, cs, n_objects_dev, s);
+}
+
+int rt_set_knob(rt_ctx *c, const char *name, int value) {
+    CHECK(c && name, "rt_set_knob: null argument");
+    std::string n(name);
+    if (n == "recon_levels") {
+        CHECK(value >= 0 && value <= 8, "rt_set_knob: recon_levels must be 0..8");
+        c->knobs.recon_levels = value;
+    } else if (n == "recon_round_batch") {
+        CHECK(value >= 1 && value <= 64, "rt_set_knob: recon_round_batch must be 1..64");
+        c->knobs.recon_round_batch = value;
+    } else if (n == "recon_max_sweeps") {
+        CHECK(value >= 1 && value <= 1024, "rt_set_knob: recon_max_sweeps must be 1..1024");
+        c->knobs.recon_max_sweeps = value;
+    } else {
+        set_error("rt_set_knob: unknown knob '%s'", name);
+        return RT_EINVAL;
+    }
+    return RT_OK;
+}
+
+int rt_get_knob(rt_ctx *c, const char *name, int *value) {
+    CHECK(c && name && value, "rt_get_knob: null argument");
+    std::string n(name);
+    if (n == "recon_levels")
+        *value = c->knobs.recon_levels;
+    else if (n == "recon_round_batch")
+        *value = c->knobs.recon_round_batch;
+    else if (n == "recon_max_sweeps")
+        *value = c->knobs.recon_max_sweeps;
+    else {
+        set_error("rt_get_knob: unknown knob '%s'", name);
+        return RT_EINVAL;
+    }
+    return RT_OK;
+}
+
+int rt_profile_enable(rt_ctx *c, int enable) {
+    CHECK(c, "rt_profile_enable: ctx is NULL");
+    c->prof_on = enable != 0;
+    return RT_OK;
+}
+
+const char *rt_profile_stage_name(int stage) {
+    return (stage >= 0 && stage < RT_PROF_STAGES) ? kStageNames[stage] : "";
+}
+
+int rt_profile_read(rt_ctx *c, double *ms, int64_t *launches, int max_stages) {
+    CHECK(c && ms && launches, "rt_profile_read: null argument");
+    int e = set_dev(c);
+    if (e) return e;
+    const int ns = std::min(max_stages, (int)RT_PROF_STAGES);
+    for (int i = 0; i < ns; ++i) {
+        ms[i] = 0.0;
+        launches[i] = c->prof_launches[i];
+    }
+    const size_t per = RT_PROF_STAGES + 1;
+    for (size_t b = 0; b + per <= c->prof_used; b += per) {
+        RT_HIP(hipEventSynchronize(c->prof_events[b + per - 1]));
+        for (int i = 0; i < ns; ++i) {
+            float t = 0.f;
+            RT_HIP(hipEventElapsedTime(&t, c->prof_events[b + i], c->prof_events[b + i + 1]));
+            ms[i] += t;
+        }
+    }
+    int calls = c->prof_calls;
+    c->prof_used = 0;
+    c->prof_calls = 0;
+    for (int i = 0; i < RT_PROF_STAGES; ++i) c->prof_launches[i] = 0;
+    return calls;
 }
 
 }  // extern "C"

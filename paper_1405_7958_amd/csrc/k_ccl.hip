@@ -2,38 +2,47 @@
 // in which every pixel starts as its own tree, adjacent trees are merged, and
 // labels are read off by flattening the trees).
 //
-// Three launches over 32 x 32 tiles (one 256-thread workgroup per tile):
-//   local : the tile's predicate is staged in LDS and a union-find forest is
-//           built there with LDS atomicMin (a root is always the smallest
-//           index of its tree, so labels are canonical by construction).
-//           Only the tile's roots and its edge pixels are published to the
-//           global id array (id 0 = virtual node, pixel p = id p + 1).
-//   merge : one thread per pair of pixels facing each other across a tile
-//           edge unites their global trees with atomicMin.
-//   flatten: the tile's forest is rebuilt in LDS (1 byte/pixel of input
-//           instead of storing 4 bytes/pixel of local roots), each local root
-//           finds its global root once, and the per-pixel result is written.
-//
-// The same engine serves FillHoles (background components joined to a virtual
-// frame node), BWLabel with per-component area and bounding box, and the
-// multi-level frame-connectivity lower bound used to start the grayscale
-// reconstruction.
+// One wavefront per 64 x 64 tile.  A row of the tile is one 64-bit ballot
+// mask, so the forest is built over horizontal runs instead of pixels: the
+// pixels of a run share its first pixel as parent by construction (bit
+// arithmetic, no atomics), and only runs of adjacent rows that touch are
+// united (LDS atomicMin, the root is always the smallest index, so labels are
+// canonical by construction).  Three launches:
+//   local  : build the tile forest; publish only its roots and its edge
+//            pixels to the global id array (id 0 = virtual node, pixel p has
+//            id p + 1);
+//   merge  : one wave per tile unites, across its right and bottom edges,
+//            each pair of touching edge runs once (global atomicMin);
+//   flatten: rebuild the tile forest (it costs 1 byte/pixel of input instead
+//            of 4 bytes/pixel of stored local roots), find each local root's
+//            global root once, and write the per-pixel result.
+// Modes: BWLabel (labels, per-component area and bounding box, component
+// list), FillHoles (background components joined to a virtual frame node),
+// and the multi-level frame-connectivity lower bound that starts the
+// grayscale reconstruction.
 #include "rt_internal.h"
 
 namespace rtseg {
 
-constexpr int TW = 32, TH = 32, TN = TW * TH, NT = 256;
+constexpr int CT = 64;                 // tile edge = wavefront size
 constexpr int MAXLEV = 8;
+constexpr int FRAME_BIT = 1 << 30;     // tags a local root whose component touches the image frame
+constexpr int LIDX = 0xfff;
 
 __device__ __forceinline__ int ld_agent(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int lfind(volatile int *P, int x) {
-    int p = P[x];
+// Finds with path halving: a node is re-pointed to its grandparent with
+// atomicMin, so parent pointers only ever move to a smaller ancestor and a
+// concurrent link can never be undone.
+__device__ __forceinline__ int lfind(int *P, int x) {
+    int p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     while (p != x) {
+        const int gp = __hip_atomic_load(P + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gp != p) atomicMin(P + x, gp);
         x = p;
-        p = P[x];
+        p = gp;
     }
     return x;
 }
@@ -48,7 +57,7 @@ __device__ __forceinline__ void lunite(int *P, int a, int b) {
             a = b;
             b = t;
         }
-        int old = atomicMin(&P[a], b);
+        int old = atomicMin(P + a, b);
         if (old == a) return;
         a = old;
     }
@@ -57,8 +66,10 @@ __device__ __forceinline__ void lunite(int *P, int a, int b) {
 __device__ __forceinline__ int gfind(int32_t *ids, int x) {
     int p = ld_agent(ids + x);
     while (p != x) {
+        const int gp = ld_agent(ids + p);
+        if (gp != p) atomicMin(ids + x, gp);
         x = p;
-        p = ld_agent(ids + x);
+        p = gp;
     }
     return x;
 }
@@ -79,6 +90,19 @@ __device__ __forceinline__ void gunite(int32_t *ids, int a, int b) {
     }
 }
 
+// ---- 64-bit run arithmetic -------------------------------------------------
+__device__ __forceinline__ uint64_t run_starts(uint64_t m) { return m & ~(m << 1); }
+__device__ __forceinline__ int run_len(uint64_t m, int s) {   // m has bit s set
+    uint64_t z = ~(m >> s);
+    return z ? __builtin_ctzll(z) : 64 - s;
+}
+__device__ __forceinline__ int run_start_of(uint64_t m, int b) {   // m has bit b set
+    uint64_t z = ~m & ((1ull << b) - 1);
+    return z ? 64 - __builtin_clzll(z) : 0;
+}
+__device__ __forceinline__ uint64_t bits_upto(int e) { return e >= 63 ? ~0ull : (2ull << e) - 1; }
+
+// ---- predicate --------------------------------------------------------------
 __device__ __forceinline__ bool eval_pred(const CclArgs &A, int x, int y, int level) {
     switch (A.pred) {
         case CclPred::NonZero: return A.a[(int64_t)y * A.pitch_a + x] != 0;
@@ -90,255 +114,360 @@ __device__ __forceinline__ bool eval_pred(const CclArgs &A, int x, int y, int le
     return false;
 }
 
-struct TileCtx {
-    int x0, y0, tw, th;
+struct Tile {
+    int tx, ty, x0, y0, tw, th;
 };
 
-// Builds the LDS forest of the tile for predicate bits `pr` (1 = member).
-// Non-members get P = -1.  Ends with P[i] = local root for every member.
-__device__ void tile_forest(const uint8_t *pr, int *P, int conn, const TileCtx &tc) {
-    for (int i = threadIdx.x; i < TN; i += NT) P[i] = pr[i] ? i : -1;
+__device__ __forceinline__ Tile tile_of(const CclArgs &A, int b) {
+    const int ntx = (A.w + CT - 1) / CT;
+    Tile t;
+    t.tx = b % ntx;
+    t.ty = b / ntx;
+    t.x0 = t.tx * CT;
+    t.y0 = t.ty * CT;
+    t.tw = min(CT, A.w - t.x0);
+    t.th = min(CT, A.h - t.y0);
+    return t;
+}
+
+__device__ __forceinline__ int gid(const CclArgs &A, const Tile &t, int x, int y) {
+    return (t.y0 + y) * A.w + t.x0 + x + 1;
+}
+
+// Column `lane` of the tile, held by that lane: predicate bits (non-Level
+// modes) or the packed uint8 values (Level mode), 4 per word.
+struct Col {
+    uint32_t v[16];
+};
+
+__device__ void load_col(const CclArgs &A, const Tile &t, Col &c) {
+    const int lane = threadIdx.x;
+    const int x = t.x0 + lane;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c.v[k] = 0;
+    if (lane >= t.tw) return;
+#pragma unroll
+    for (int y = 0; y < CT; ++y) {
+        if (y < t.th) {
+            uint32_t v;
+            if (A.pred == CclPred::Level)
+                v = A.a[(int64_t)(t.y0 + y) * A.pitch_a + x];
+            else
+                v = eval_pred(A, x, t.y0 + y, 0) ? 1u : 0u;
+            c.v[y >> 2] |= v << ((y & 3) * 8);
+        }
+    }
+}
+
+__device__ __forceinline__ bool col_bit(const CclArgs &A, const Col &c, int y, int level) {
+    uint32_t v = (c.v[y >> 2] >> ((y & 3) * 8)) & 255u;
+    return A.pred == CclPred::Level ? (int)v >= level : v != 0;
+}
+
+// rows[y] = ballot over lanes (= columns) of the member bit at row y
+__device__ void make_rows(const CclArgs &A, const Tile &t, const Col &c, int level, uint64_t *rows) {
+    const int lane = threadIdx.x;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int y = 0; y < CT; ++y) {
+        bool b = y < t.th && lane < t.tw && col_bit(A, c, y, level);
+        uint64_t m = __ballot(b);
+        if (lane == y) mine = m;
+    }
+    rows[lane] = mine;
     __syncthreads();
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        if (!pr[i]) continue;
-        int lx = i % TW, ly = i / TW;
-        if (lx > 0 && pr[i - 1]) lunite(P, i, i - 1);
-        if (ly > 0) {
-            if (pr[i - TW]) lunite(P, i, i - TW);
-            if (conn == 8) {
-                if (lx > 0 && pr[i - TW - 1]) lunite(P, i, i - TW - 1);
-                if (lx < TW - 1 && pr[i - TW + 1]) lunite(P, i, i - TW + 1);
+}
+
+// Tile forest over runs: after the call, P[y*64+s] = local root (index of a
+// run start) for every run start s of row y.  Lane = row.
+__device__ void run_forest(const uint64_t *rows, int *P, int conn) {
+    const int y = threadIdx.x;
+    const uint64_t m = rows[y];
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        int s = __builtin_ctzll(st);
+        P[y * CT + s] = y * CT + s;
+    }
+    __syncthreads();
+    if (y > 0) {
+        const uint64_t pm = rows[y - 1];
+        if (m && pm) {
+            for (uint64_t st = run_starts(m); st; st &= st - 1) {
+                int s = __builtin_ctzll(st);
+                int e = s + run_len(m, s) - 1;
+                int lo = conn == 8 ? max(s - 1, 0) : s;
+                int hi = conn == 8 ? min(e + 1, 63) : e;
+                uint64_t ov = pm & bits_upto(hi) & ~((1ull << lo) - 1);
+                while (ov) {
+                    int b = __builtin_ctzll(ov);
+                    int s2 = run_start_of(pm, b);
+                    int e2 = s2 + run_len(pm, s2) - 1;
+                    lunite(P, y * CT + s, (y - 1) * CT + s2);
+                    ov &= ~bits_upto(e2);
+                }
             }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < TN; i += NT)
-        if (pr[i]) P[i] = lfind(P, i);
-    __syncthreads();
-}
-
-__device__ __forceinline__ int pix_id(const CclArgs &A, const TileCtx &tc, int i) {
-    return (tc.y0 + i / TW) * A.w + tc.x0 + i % TW + 1;
-}
-
-// Stages the predicate (or, for Level, the Hq tile) into LDS.  Pixels beyond
-// the image edge are non-members.
-__device__ void stage_tile(const CclArgs &A, const TileCtx &tc, uint8_t *raw) {
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        int lx = i % TW, ly = i / TW;
-        uint8_t v = 0;
-        if (lx < tc.tw && ly < tc.th) {
-            int x = tc.x0 + lx, y = tc.y0 + ly;
-            if (A.pred == CclPred::Level)
-                v = A.a[(int64_t)y * A.pitch_a + x];
-            else
-                v = eval_pred(A, x, y, 0) ? 1 : 0;
-        }
-        raw[i] = v;
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        int s = __builtin_ctzll(st);
+        P[y * CT + s] = lfind(P, y * CT + s);
     }
     __syncthreads();
 }
 
-__device__ void level_bits(const uint8_t *raw, uint8_t *pr, int level, const TileCtx &tc) {
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        int lx = i % TW, ly = i / TW;
-        pr[i] = (lx < tc.tw && ly < tc.th && (int)raw[i] >= level) ? 1 : 0;
-    }
-    __syncthreads();
+__device__ __forceinline__ int root_of(const uint64_t *rows, const int *P, int x, int y) {
+    return P[y * CT + run_start_of(rows[y], x)] & LIDX;
 }
 
-__device__ __forceinline__ bool on_frame(const CclArgs &A, int x, int y) {
-    return x == 0 || y == 0 || x == A.w - 1 || y == A.h - 1;
-}
-
-// --------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
 // local phase
-// --------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_ccl_local(CclArgs A) {
-    __shared__ uint8_t raw[TN];
-    __shared__ uint8_t pr[TN];
-    __shared__ uint8_t fr[TN];
-    __shared__ int P[TN];
-    const int ntx = (A.w + TW - 1) / TW;
-    TileCtx tc;
-    tc.x0 = (blockIdx.x % ntx) * TW;
-    tc.y0 = (blockIdx.x / ntx) * TH;
-    tc.tw = min(TW, A.w - tc.x0);
-    tc.th = min(TH, A.h - tc.y0);
-    stage_tile(A, tc, raw);
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CT) void k_ccl_local(CclArgs A) {
+    __shared__ uint64_t rows[CT];
+    __shared__ int P[CT * CT];
+    const Tile t = tile_of(A, blockIdx.x);
+    const int lane = threadIdx.x;
+    Col c;
+    load_col(A, t, c);
     const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
     const int64_t nid = (int64_t)A.w * A.h + 1;
+    const bool tile_on_frame = t.x0 == 0 || t.y0 == 0 || t.x0 + t.tw == A.w || t.y0 + t.th == A.h;
     for (int lev = 0; lev < nlev; ++lev) {
-        const uint8_t *bits = raw;
-        if (A.pred == CclPred::Level) {
-            level_bits(raw, pr, A.levels[lev], tc);
-            bits = pr;
-        }
-        tile_forest(bits, P, A.conn, tc);
+        const int level = A.pred == CclPred::Level ? A.levels[lev] : 0;
         int32_t *ids = A.ids + lev * nid;
-        for (int i = threadIdx.x; i < TN; i += NT) fr[i] = 0;
-        __syncthreads();
-        if (A.frame_virtual) {
-            for (int i = threadIdx.x; i < TN; i += NT) {
-                if (!bits[i]) continue;
-                if (on_frame(A, tc.x0 + i % TW, tc.y0 + i / TW)) fr[P[i]] = 1;
+        make_rows(A, t, c, level, rows);
+        run_forest(rows, P, A.conn);
+        const int y = lane;
+        const uint64_t m = rows[y];
+        if (A.frame_virtual && tile_on_frame) {
+            if (y < t.th && m) {
+                if (t.y0 + y == 0 || t.y0 + y == A.h - 1) {
+                    for (uint64_t st = run_starts(m); st; st &= st - 1)
+                        atomicOr(P + (P[y * CT + __builtin_ctzll(st)] & LIDX), FRAME_BIT);
+                } else {
+                    if (t.x0 == 0 && (m & 1ull)) atomicOr(P + root_of(rows, P, 0, y), FRAME_BIT);
+                    if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
+                        atomicOr(P + root_of(rows, P, t.tw - 1, y), FRAME_BIT);
+                }
             }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < TN; i += NT) {
-            if (!bits[i]) continue;
-            int lx = i % TW, ly = i / TW;
-            int r = P[i];
-            int id = pix_id(A, tc, i);
-            if (r == i) {
-                ids[id] = fr[i] ? 0 : id;
-                if (A.st_area) {
-                    A.st_area[id] = 0;
-                    A.st_x0[id] = 0x7fffffff;
-                    A.st_y0[id] = 0x7fffffff;
-                    A.st_x1[id] = -1;
-                    A.st_y1[id] = -1;
-                }
-            } else if (lx == 0 || ly == 0 || lx == tc.tw - 1 || ly == tc.th - 1) {
-                ids[id] = pix_id(A, tc, r);
+        // roots (lane = row)
+        for (uint64_t st = run_starts(m); st; st &= st - 1) {
+            int s = __builtin_ctzll(st);
+            int li = y * CT + s;
+            int pv = P[li];
+            if ((pv & LIDX) != li) continue;
+            int id = gid(A, t, s, y);
+            ids[id] = (pv & FRAME_BIT) ? 0 : id;
+            if (A.st_area) {
+                A.st_area[id] = 0;
+                A.st_x0[id] = 0x7fffffff;
+                A.st_y0[id] = 0x7fffffff;
+                A.st_x1[id] = -1;
+                A.st_y1[id] = -1;
+            }
+        }
+        // edge pixels that are not roots: left / right columns (lane = row)
+        if (m & 1ull) {
+            int r = root_of(rows, P, 0, y);
+            if (r != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r & 63, r >> 6);
+        }
+        if (t.tw > 1 && ((m >> (t.tw - 1)) & 1ull)) {
+            int r = root_of(rows, P, t.tw - 1, y);
+            int li = y * CT + t.tw - 1;
+            if (r != li) ids[gid(A, t, t.tw - 1, y)] = gid(A, t, r & 63, r >> 6);
+        }
+        // top / bottom rows (lane = column)
+        {
+            const int x = lane;
+            if ((rows[0] >> x) & 1ull) {
+                int r = root_of(rows, P, x, 0);
+                if (r != x) ids[gid(A, t, x, 0)] = gid(A, t, r & 63, r >> 6);
+            }
+            const int yb = t.th - 1;
+            if (yb > 0 && ((rows[yb] >> x) & 1ull)) {
+                int r = root_of(rows, P, x, yb);
+                if (r != yb * CT + x) ids[gid(A, t, x, yb)] = gid(A, t, r & 63, r >> 6);
             }
         }
         __syncthreads();
     }
 }
 
-// --------------------------------------------------------------------------
-// merge phase: pairs across tile edges
-// --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ccl_merge(CclArgs A, int64_t n_vert) {
-    const int ntx = (A.w + TW - 1) / TW, nty = (A.h + TH - 1) / TH;
-    int64_t n_hor = (int64_t)(nty - 1) * A.w;
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_vert + n_hor) return;
-    const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
-    const int64_t nid = (int64_t)A.w * A.h + 1;
-    int px, py, qx[3], qy[3], nq = 0;
-    if (t < n_vert) {
-        int bx = (int)(t / A.h) + 1;
-        py = (int)(t % A.h);
-        px = bx * TW - 1;
-        if (A.conn == 8) {
-            for (int d = -1; d <= 1; ++d)
-                if (py + d >= 0 && py + d < A.h) { qx[nq] = px + 1; qy[nq] = py + d; ++nq; }
-        } else {
-            qx[0] = px + 1; qy[0] = py; nq = 1;
-        }
-    } else {
-        int64_t u = t - n_vert;
-        int by = (int)(u / A.w) + 1;
-        px = (int)(u % A.w);
-        py = by * TH - 1;
-        if (A.conn == 8) {
-            for (int d = -1; d <= 1; ++d)
-                if (px + d >= 0 && px + d < A.w) { qx[nq] = px + d; qy[nq] = py + 1; ++nq; }
-        } else {
-            qx[0] = px; qy[0] = py + 1; nq = 1;
-        }
+// ---------------------------------------------------------------------------
+// merge phase: one wave per tile, its right and bottom edges
+// ---------------------------------------------------------------------------
+// unites the pairs (a(i), b(i+d)), d in {-1,0,1} (8-conn) or {0} (4-conn),
+// along an edge; a/b bit i = member at position i (b has two extra members
+// at i = -1 and i = 64, passed as bm1 / b64; they lie in the diagonal
+// neighbour tiles).  About one union per pair of touching runs: a pair is
+// skipped when a pair with a lower position, together with an adjacency
+// inside one tile (always joined by that tile's forest), implies it.
+__device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bool b64, int conn, int i,
+                            int ida, int idb_base, int idb_stride) {
+    if (!((am >> i) & 1ull)) return;
+    auto bset = [&](int j) -> bool {
+        if (j == -1) return bm1;
+        if (j == 64) return b64;
+        if (j < -1 || j > 64) return false;
+        return (bm >> j) & 1ull;
+    };
+    auto aset = [&](int j) -> bool { return j >= 0 && j < 64 && ((am >> j) & 1ull); };
+    if (conn == 4) {
+        if (!bset(i)) return;
+        if (aset(i - 1) && bset(i - 1)) return;
+        gunite(ids, ida, idb_base + i * idb_stride);
+        return;
     }
-    (void)ntx;
-    for (int lev = 0; lev < nlev; ++lev) {
-        int level = A.pred == CclPred::Level ? A.levels[lev] : 0;
-        if (!eval_pred(A, px, py, level)) continue;
-        int32_t *ids = A.ids + lev * nid;
-        int pid = py * A.w + px + 1;
-        for (int k = 0; k < nq; ++k)
-            if (eval_pred(A, qx[k], qy[k], level)) gunite(ids, pid, qy[k] * A.w + qx[k] + 1);
+    for (int d = -1; d <= 1; ++d) {
+        int j = i + d;
+        if (!bset(j)) continue;
+        // implied by a(i-1) (same tile as a(i)) united with b(j)
+        if (aset(i - 1) && j - (i - 1) <= 1 && j - (i - 1) >= -1) continue;
+        // implied by a(i) united with b(j-1), when b(j-1) and b(j) lie in the
+        // same tile (positions 0..63); across a tile corner the two edges
+        // could otherwise each rely on the other's skipped union
+        if (j >= 1 && j <= 63 && bset(j - 1) && (j - 1) - i <= 1 && (j - 1) - i >= -1) continue;
+        gunite(ids, ida, idb_base + j * idb_stride);
     }
 }
 
-// --------------------------------------------------------------------------
-// flatten phase + outputs
-// --------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_ccl_flatten(CclArgs A) {
-    __shared__ uint8_t raw[TN];
-    __shared__ uint8_t pr[TN];
-    __shared__ uint8_t best[TN];
-    __shared__ int P[TN];
-    __shared__ int G[TN];
-    __shared__ int cnt[TN];
-    __shared__ uint32_t cmask[TN];
-    __shared__ uint32_t rmask[TN];
-    const int ntx = (A.w + TW - 1) / TW;
-    TileCtx tc;
-    tc.x0 = (blockIdx.x % ntx) * TW;
-    tc.y0 = (blockIdx.x / ntx) * TH;
-    tc.tw = min(TW, A.w - tc.x0);
-    tc.th = min(TH, A.h - tc.y0);
-    stage_tile(A, tc, raw);
+__global__ __launch_bounds__(CT) void k_ccl_merge(CclArgs A) {
+    const Tile t = tile_of(A, blockIdx.x);
+    const int lane = threadIdx.x;
+    const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
     const int64_t nid = (int64_t)A.w * A.h + 1;
+    const bool right = t.x0 + CT < A.w;
+    const bool bottom = t.y0 + CT < A.h;
+    if (!right && !bottom) return;
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int level = A.pred == CclPred::Level ? A.levels[lev] : 0;
+        int32_t *ids = A.ids + lev * nid;
+        if (right) {   // a = column x0+63, b = column x0+64, position = row
+            const int xa = t.x0 + CT - 1, xb = t.x0 + CT;
+            bool a = lane < t.th && eval_pred(A, xa, t.y0 + lane, level);
+            bool b = lane < t.th && eval_pred(A, xb, t.y0 + lane, level);
+            uint64_t am = __ballot(a), bm = __ballot(b);
+            bool bm1 = t.y0 > 0 && eval_pred(A, xb, t.y0 - 1, level);
+            bool b64 = t.y0 + CT < A.h && eval_pred(A, xb, t.y0 + CT, level);
+            if (lane < t.th)
+                edge_unions(ids, am, bm, bm1, b64, A.conn, lane, (t.y0 + lane) * A.w + xa + 1,
+                            t.y0 * A.w + xb + 1, A.w);
+        }
+        if (bottom) {  // a = row y0+63, b = row y0+64, position = column
+            const int ya = t.y0 + CT - 1, yb = t.y0 + CT;
+            bool a = lane < t.tw && eval_pred(A, t.x0 + lane, ya, level);
+            bool b = lane < t.tw && eval_pred(A, t.x0 + lane, yb, level);
+            uint64_t am = __ballot(a), bm = __ballot(b);
+            bool bm1 = t.x0 > 0 && eval_pred(A, t.x0 - 1, yb, level);
+            bool b64 = t.x0 + CT < A.w && eval_pred(A, t.x0 + CT, yb, level);
+            if (lane < t.tw)
+                edge_unions(ids, am, bm, bm1, b64, A.conn, lane, ya * A.w + t.x0 + lane + 1, yb * A.w + t.x0 + 1, 1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// flatten phase + outputs
+// ---------------------------------------------------------------------------
+// Replaces, for every local root r, P[r] by -(global root id) - 1.
+__device__ void resolve_roots(const CclArgs &A, const Tile &t, const uint64_t *rows, int *P, int32_t *ids) {
+    const int y = threadIdx.x;
+    const uint64_t m = rows[y];
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        int s = __builtin_ctzll(st);
+        int li = y * CT + s;
+        if (P[li] != li) continue;
+        P[li] = -gfind(ids, gid(A, t, s, y)) - 1;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int global_of(const uint64_t *rows, const int *P, int x, int y) {
+    int r = P[y * CT + run_start_of(rows[y], x)];
+    if (r < 0) return -r - 1;
+    return -P[r] - 1;
+}
+
+__global__ __launch_bounds__(CT) void k_ccl_flatten(CclArgs A) {
+    __shared__ uint64_t rows[CT];
+    __shared__ int P[CT * CT];
+    const Tile t = tile_of(A, blockIdx.x);
+    const int lane = threadIdx.x;
+    Col c;
+    load_col(A, t, c);
+    const int64_t nid = (int64_t)A.w * A.h + 1;
+    const int x = lane;
 
     if (A.out == CclOut::LevelBound) {
-        for (int i = threadIdx.x; i < TN; i += NT) best[i] = 0;
-        __syncthreads();
+        uint32_t best[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) best[k] = 0;
         for (int lev = 0; lev < A.n_levels; ++lev) {
-            int level = A.levels[lev];
-            level_bits(raw, pr, level, tc);
-            tile_forest(pr, P, A.conn, tc);
-            int32_t *ids = A.ids + lev * nid;
-            for (int i = threadIdx.x; i < TN; i += NT)
-                if (pr[i] && P[i] == i) G[i] = gfind(ids, pix_id(A, tc, i));
-            __syncthreads();
-            for (int i = threadIdx.x; i < TN; i += NT)
-                if (pr[i] && G[P[i]] == 0 && level > best[i]) best[i] = (uint8_t)level;
+            const int level = A.levels[lev];
+            make_rows(A, t, c, level, rows);
+            run_forest(rows, P, A.conn);
+            resolve_roots(A, t, rows, P, A.ids + lev * nid);
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                if (y >= t.th || !((rows[y] >> x) & 1ull)) continue;
+                if (global_of(rows, P, x, y) != 0) continue;
+                const uint32_t cur = (best[y >> 2] >> ((y & 3) * 8)) & 255u;
+                if ((uint32_t)level > cur)
+                    best[y >> 2] = (best[y >> 2] & ~(255u << ((y & 3) * 8))) | ((uint32_t)level << ((y & 3) * 8));
+            }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < TN; i += NT) {
-            int lx = i % TW, ly = i / TW;
-            if (lx >= tc.tw || ly >= tc.th) continue;
-            int x = tc.x0 + lx, y = tc.y0 + ly;
-            int j = on_frame(A, x, y) ? raw[i] : 0;
-            int v = best[i] > j ? best[i] : j;
-            A.bound[(int64_t)y * A.pitch_r + x] = (uint8_t)v;
+        if (x < t.tw) {
+            const int gx = t.x0 + x;
+#pragma unroll
+            for (int y = 0; y < CT; ++y) {
+                if (y >= t.th) continue;
+                const int gy = t.y0 + y;
+                int v = (best[y >> 2] >> ((y & 3) * 8)) & 255;
+                if (gx == 0 || gy == 0 || gx == A.w - 1 || gy == A.h - 1) {
+                    int j = (c.v[y >> 2] >> ((y & 3) * 8)) & 255;   // frame marker J = Hq
+                    v = v > j ? v : j;
+                }
+                A.bound[(int64_t)gy * A.pitch_r + gx] = (uint8_t)v;
+            }
         }
         return;
     }
 
-    tile_forest(raw, P, A.conn, tc);
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        if (raw[i] && P[i] == i) G[i] = gfind(A.ids, pix_id(A, tc, i));
-        cnt[i] = 0;
-        cmask[i] = 0;
-        rmask[i] = 0;
-    }
-    __syncthreads();
-    const bool stats = A.out == CclOut::Labels && A.st_area != nullptr;
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        int lx = i % TW, ly = i / TW;
-        if (lx >= tc.tw || ly >= tc.th) continue;
-        int x = tc.x0 + lx, y = tc.y0 + ly;
-        if (A.out == CclOut::Labels) {
-            int lab = raw[i] ? G[P[i]] : 0;
-            A.labels[(int64_t)y * A.pitch_l + x] = lab;
-            if (!raw[i] && A.bg_zero_mask) A.bg_zero_mask[(int64_t)y * A.pitch_m + x] = 0;
-            if (stats && raw[i]) {
-                int r = P[i];
-                atomicAdd(&cnt[r], 1);
-                atomicOr(&cmask[r], 1u << lx);
-                atomicOr(&rmask[r], 1u << ly);
+    make_rows(A, t, c, 0, rows);
+    run_forest(rows, P, A.conn);
+    resolve_roots(A, t, rows, P, A.ids);
+    if (x < t.tw) {
+        const int gx = t.x0 + x;
+        for (int y = 0; y < t.th; ++y) {
+            const int64_t gy = t.y0 + y;
+            const bool mem = (rows[y] >> x) & 1ull;
+            if (A.out == CclOut::Labels) {
+                A.labels[gy * A.pitch_l + gx] = mem ? global_of(rows, P, x, y) : 0;
+                if (!mem && A.bg_zero_mask) A.bg_zero_mask[gy * A.pitch_m + gx] = 0;
+            } else {  // FillHoles: members are background pixels of the input
+                A.fill[gy * A.pitch_f + gx] = mem ? (global_of(rows, P, x, y) != 0 ? 1 : 0) : 1;
             }
-        } else {  // FillHoles: members are background pixels of F0
-            uint8_t f = raw[i] ? (G[P[i]] != 0 ? 1 : 0) : 1;
-            A.fill[(int64_t)y * A.pitch_f + x] = f;
         }
     }
-    if (!stats && !(A.out == CclOut::Labels && A.obj_list)) return;
-    __syncthreads();
-    for (int i = threadIdx.x; i < TN; i += NT) {
-        if (!raw[i] || P[i] != i) continue;
-        int g = G[i];
-        if (stats) {
-            atomicAdd(A.st_area + g, cnt[i]);
-            atomicMin(A.st_x0 + g, tc.x0 + __builtin_ctz(cmask[i]));
-            atomicMax(A.st_x1 + g, tc.x0 + 31 - __builtin_clz(cmask[i]));
-            atomicMin(A.st_y0 + g, tc.y0 + __builtin_ctz(rmask[i]));
-            atomicMax(A.st_y1 + g, tc.y0 + 31 - __builtin_clz(rmask[i]));
+    if (A.out != CclOut::Labels || (!A.st_area && !A.obj_list)) return;
+    // per-run statistics and component registration (lane = row)
+    const int y = lane;
+    const uint64_t m = rows[y];
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        const int s = __builtin_ctzll(st);
+        const int len = run_len(m, s);
+        const int g = global_of(rows, P, s, y);
+        if (A.st_area) {
+            atomicAdd(A.st_area + g, len);
+            atomicMin(A.st_x0 + g, t.x0 + s);
+            atomicMax(A.st_x1 + g, t.x0 + s + len - 1);
+            atomicMin(A.st_y0 + g, t.y0 + y);
+            atomicMax(A.st_y1 + g, t.y0 + y);
         }
-        if (A.obj_list && g == pix_id(A, tc, i)) A.obj_list[atomicAdd(A.n_obj, 1)] = g;
+        if (A.obj_list && P[y * CT + s] < 0 && g == gid(A, t, s, y)) A.obj_list[atomicAdd(A.n_obj, 1)] = g;
     }
 }
 
@@ -347,23 +476,20 @@ int launch_ccl(const CclArgs &a, hipStream_t s) {
         set_error("ccl: bad level count %d", a.n_levels);
         return RT_EINVAL;
     }
-    const int ntx = (a.w + TW - 1) / TW, nty = (a.h + TH - 1) / TH;
+    const int ntx = (a.w + CT - 1) / CT, nty = (a.h + CT - 1) / CT;
     const int nlev = a.pred == CclPred::Level ? a.n_levels : 1;
     const int64_t nid = (int64_t)a.w * a.h + 1;
-    // the virtual node id 0 of every level is its own root
-    for (int l = 0; l < nlev; ++l) {
+    for (int l = 0; l < nlev; ++l) {   // the virtual node id 0 of every level is its own root
         int e = launch_fill_i32(a.ids + l * nid, 0, 1, s);
         if (e) return e;
     }
-    hipLaunchKernelGGL(k_ccl_local, dim3(ntx * nty), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(k_ccl_local, dim3(ntx * nty), dim3(CT), 0, s, a);
     RT_HIP(hipGetLastError());
-    int64_t n_vert = (int64_t)(ntx - 1) * a.h;
-    int64_t n_pairs = n_vert + (int64_t)(nty - 1) * a.w;
-    if (n_pairs > 0) {
-        hipLaunchKernelGGL(k_ccl_merge, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, a, n_vert);
+    if (ntx > 1 || nty > 1) {
+        hipLaunchKernelGGL(k_ccl_merge, dim3(ntx * nty), dim3(CT), 0, s, a);
         RT_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(ntx * nty), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(ntx * nty), dim3(CT), 0, s, a);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

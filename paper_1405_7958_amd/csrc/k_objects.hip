@@ -1,57 +1,64 @@
-// Pre-Watershed + Watershed, one workgroup per connected component.
+// Pre-Watershed + Watershed, one wavefront per connected component.
 //
 // The paper restructures feature computation into one bounding box per
 // nucleus, one GPU block per box (Sec. 5.1); the same decomposition serves
-// the watershed stage here.  Everything after the area filter (distance
-// transform, h-maxima seeds, flood, cut, relabelling, final area filter)
-// depends only on the component itself:
+// the watershed stage here.  Everything after the first area filter
+// (distance transform, h-maxima seeds, flood, cut, relabelling, final area
+// filter) depends only on the component itself:
 //   * the nearest background pixel of a component pixel lies in the
 //     component's bounding box grown by one pixel (the open disc of radius d
 //     around p holds no background pixel, so it is a connected foreground set
-//     and belongs to the component; the background pixel that ends the disc
-//     is 8-adjacent to the component), so the distance transform computed in
-//     that crop with "not in the component" as background is exact;
-//   * the reconstructions run on the graph of the component's pixels, and
-//     components are not 8-adjacent to each other.
-// The crop state (flags, Dq, two work planes and the flood keys) lives in LDS
-// when it fits; larger crops run the same code on a global scratch slice.
+//     inside the component, and the background pixel that ends the disc is
+//     8-adjacent to the component), so the distance transform of the crop with
+//     "not in the component" as background is exact;
+//   * the reconstructions run on the graph of the component's own pixels, and
+//     different components are never 8-adjacent.
+// A component with at most one seed is labelled whole (every pixel can only
+// take that seed's label), so the flood runs only for touching nuclei.
+//
+// Crop planes (row stride odd, so a column walk does not hit one LDS bank):
+//   fl  flags: in component / seed / kept
+//   dq  Dq, later the level-sorted list of unlabelled pixels, later areas
+//   A   g (h-maxima), then lambda, then CCL roots of the kept pixels
+//   B   recon of g-1 under g, then labels; during one flood level a pixel of
+//       that level holds -(key) - 2 with key = (BFS distance << SH) | label
+// Size classes: crops of <= 1024 and <= 4096 pixels live in LDS (one wave per
+// component, many components per CU); larger crops use a global scratch slice
+// with 64-bit keys.  All three launches read their work lists from device
+// counters, so no host round trip is needed.
 #include "rt_internal.h"
 
 #include <climits>
 
 namespace rtseg {
 
-constexpr int OBJ_THREADS = 256;
-constexpr int LDS_CAP = 3072;  // crop pixels held in LDS
+constexpr int WAVE = 64;
+constexpr int CAP_S = 1024;
+constexpr int CAP_M = 4096;
+constexpr int HBINS = 256;
 constexpr int NEGV = INT_MIN;
 constexpr int GINF = 1 << 28;
 
 enum : uint8_t { F_IN = 1, F_RM = 2, F_M = 4 };
 
-template <typename KeyT>
-struct KeyTraits;
+template <typename L>
+struct KeyPack;
 template <>
-struct KeyTraits<uint32_t> {  // crop < 4096 pixels: dist and label fit in 12 bits each
-    static constexpr int SH = 12;
-    static constexpr uint32_t INF = 0xffffffffu;
+struct KeyPack<int32_t> {  // crop plane < 65536 pixels: distance and label in 16 bits each
+    static constexpr int SH = 16;
 };
 template <>
-struct KeyTraits<uint64_t> {
+struct KeyPack<int64_t> {
     static constexpr int SH = 32;
-    static constexpr uint64_t INF = ~0ull;
 };
 
-template <typename KeyT>
+template <typename L>
 struct Crop {
     uint8_t *fl;
     int32_t *dq;
     int32_t *A;
-    int32_t *B;
-    KeyT *K;
-};
-
-struct Shape {
-    int cx0, cy0, cw, ch, n;
+    L *B;
+    int st, cw, ch, cx0, cy0, n;
 };
 
 __device__ __forceinline__ int isqrt_exact(int64_t v) {
@@ -62,84 +69,9 @@ __device__ __forceinline__ int isqrt_exact(int64_t v) {
     return (int)r;
 }
 
-// union-find on a crop plane (LDS or global); roots are the smallest index
-__device__ __forceinline__ int cfind(int32_t *P, int x) {
-    int p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    while (p != x) {
-        x = p;
-        p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    return x;
-}
-__device__ __forceinline__ void cunite(int32_t *P, int a, int b) {
-    for (;;) {
-        a = cfind(P, a);
-        b = cfind(P, b);
-        if (a == b) return;
-        if (a < b) {
-            int t = a;
-            a = b;
-            b = t;
-        }
-        int old = atomicMin(P + a, b);
-        if (old == a) return;
-        a = old;
-    }
-}
+__device__ __forceinline__ bool wave_or(bool b) { return __syncthreads_or(b) != 0; }
 
-// Labels the pixels whose flag bit `bit` is set by 8-connected components:
-// P[i] = smallest crop index of the component, -1 elsewhere.
-__device__ void crop_ccl(const Shape &s, const uint8_t *fl, uint8_t bit, int32_t *P) {
-    for (int i = threadIdx.x; i < s.n; i += blockDim.x) P[i] = (fl[i] & bit) ? i : -1;
-    __syncthreads();
-    for (int i = threadIdx.x; i < s.n; i += blockDim.x) {
-        if (!(fl[i] & bit)) continue;
-        int c = i % s.cw, r = i / s.cw;
-        if (c > 0 && (fl[i - 1] & bit)) cunite(P, i, i - 1);
-        if (r > 0) {
-            if (fl[i - s.cw] & bit) cunite(P, i, i - s.cw);
-            if (c > 0 && (fl[i - s.cw - 1] & bit)) cunite(P, i, i - s.cw - 1);
-            if (c < s.cw - 1 && (fl[i - s.cw + 1] & bit)) cunite(P, i, i - s.cw + 1);
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < s.n; i += blockDim.x)
-        if (fl[i] & bit) P[i] = cfind(P, i);
-    __syncthreads();
-}
-
-// V <- reconstruction of V under M on the graph of in-component pixels
-// (8-connected), by in-place relaxation until nothing changes.
-__device__ void crop_recon(const Shape &s, const uint8_t *fl, int32_t *V, const int32_t *M) {
-    for (int it = 0;; ++it) {
-        bool ch = false;
-        const bool fwd = (it & 1) == 0;
-        for (int k = threadIdx.x; k < s.n; k += blockDim.x) {
-            int i = fwd ? k : s.n - 1 - k;
-            if (!(fl[i] & F_IN)) continue;
-            int c = i % s.cw, r = i / s.cw;
-            int m = NEGV;
-            for (int dy = -1; dy <= 1; ++dy) {
-                int rr = r + dy;
-                if (rr < 0 || rr >= s.ch) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    int cc = c + dx;
-                    if ((dx | dy) == 0 || cc < 0 || cc >= s.cw) continue;
-                    int j = rr * s.cw + cc;
-                    if (fl[j] & F_IN) m = max(m, V[j]);
-                }
-            }
-            int nv = min(m, M[i]);
-            if (nv > V[i]) {
-                V[i] = nv;
-                ch = true;
-            }
-        }
-        if (!__syncthreads_or(ch)) break;
-    }
-}
-
-__device__ int block_max(int v, int *red) {
+__device__ int wave_max(int v, int *red) {
     if (threadIdx.x == 0) *red = NEGV;
     __syncthreads();
     if (v != NEGV) atomicMax(red, v);
@@ -148,53 +80,231 @@ __device__ int block_max(int v, int *red) {
     __syncthreads();
     return r;
 }
+__device__ int wave_min(int v, int *red) {
+    if (threadIdx.x == 0) *red = INT_MAX;
+    __syncthreads();
+    if (v != INT_MAX) atomicMin(red, v);
+    __syncthreads();
+    int r = *red;
+    __syncthreads();
+    return r;
+}
 
-template <typename KeyT>
-__device__ void process_object(const ObjArgs &a, int g, const Shape &s, Crop<KeyT> m, int *red) {
-    using KT = KeyTraits<KeyT>;
-    const int n = s.n;
-    // ---- load the component's pixels
-    bool zero = false;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int px = s.cx0 + i % s.cw, py = s.cy0 + i / s.cw;
-        bool in = a.labels[(int64_t)py * a.pitch + px] == g;
-        m.fl[i] = in ? F_IN : 0;
-        zero |= !in;
+// ---- union-find on a crop plane (roots are the smallest index) -----------
+// path halving with atomicMin: parents only move to smaller ancestors
+template <typename T>
+__device__ __forceinline__ T pfind(T *P, T x) {
+    T p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (p != x) {
+        const T gp = __hip_atomic_load(P + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gp != p) __hip_atomic_fetch_min(P + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = p;
+        p = gp;
     }
-    const bool has_zero = __syncthreads_or(zero) && a.tile_has_zero;
+    return x;
+}
+template <typename T>
+__device__ __forceinline__ void punite(T *P, T a, T b) {
+    for (;;) {
+        a = pfind(P, a);
+        b = pfind(P, b);
+        if (a == b) return;
+        if (a < b) {
+            T t = a;
+            a = b;
+            b = t;
+        }
+        T old = __hip_atomic_fetch_min(P + a, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == a) return;
+        a = old;
+    }
+}
 
-    // ---- exact distance transform inside the crop
-    for (int c = threadIdx.x; c < s.cw; c += blockDim.x) {
+// P[i] = smallest index of the 8-connected component of flagged pixels, -1 elsewhere
+template <typename L, typename T>
+__device__ void crop_ccl(const Crop<L> &m, uint8_t bit, T *P) {
+    for (int i = threadIdx.x; i < m.n; i += blockDim.x) P[i] = (m.fl[i] & bit) ? (T)i : (T)-1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < m.n; i += blockDim.x) {
+        if (!(m.fl[i] & bit)) continue;
+        int c = i % m.st, r = i / m.st;
+        if (c > 0 && (m.fl[i - 1] & bit)) punite<T>(P, i, i - 1);
+        if (r > 0) {
+            if (m.fl[i - m.st] & bit) punite<T>(P, i, i - m.st);
+            if (c > 0 && (m.fl[i - m.st - 1] & bit)) punite<T>(P, i, i - m.st - 1);
+            if (c < m.cw - 1 && (m.fl[i - m.st + 1] & bit)) punite<T>(P, i, i - m.st + 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m.n; i += blockDim.x)
+        if (m.fl[i] & bit) P[i] = pfind<T>(P, (T)i);
+    __syncthreads();
+}
+
+// ---- reconstruction by directional scans -----------------------------------
+// V <- recon of V under M on the component's 8-connected graph.  Pixels
+// outside the component hold NEGV in V and never change.  One sweep is four
+// scans (down, up with lane = column; right, left with lane = row); within a
+// scan each row/column reads its predecessor already updated.
+template <typename L, typename V>
+__device__ __forceinline__ bool relax1(const Crop<L> &m, V *val, const int32_t *M, int r, int c) {
+    const int i = r * m.st + c;
+    if (!(m.fl[i] & F_IN)) return false;
+    // neighbours outside the crop are clamped onto in-crop pixels: repeating
+    // a value (or the pixel itself) cannot change a maximum
+    const int up = r > 0 ? -m.st : 0, dn = r < m.ch - 1 ? m.st : 0;
+    const int lf = c > 0 ? -1 : 0, rt = c < m.cw - 1 ? 1 : 0;
+    const V v0 = val[i + up + lf], v1 = val[i + up], v2 = val[i + up + rt];
+    const V v3 = val[i + lf], v4 = val[i + rt];
+    const V v5 = val[i + dn + lf], v6 = val[i + dn], v7 = val[i + dn + rt];
+    const V vi = val[i];
+    const V mv = (V)M[i];
+    V mm = v0 > v1 ? v0 : v1;
+    mm = mm > v2 ? mm : v2;
+    mm = mm > v3 ? mm : v3;
+    mm = mm > v4 ? mm : v4;
+    mm = mm > v5 ? mm : v5;
+    mm = mm > v6 ? mm : v6;
+    mm = mm > v7 ? mm : v7;
+    V nv = mm < mv ? mm : mv;
+    if (nv > vi) {
+        val[i] = nv;
+        return true;
+    }
+    return false;
+}
+
+template <typename L, typename V>
+__device__ void recon_scans(const Crop<L> &m, V *val, const int32_t *M) {
+    const int lane = threadIdx.x;
+    for (;;) {
+        bool ch = false;
+        for (int r = 0; r < m.ch; ++r) {
+            for (int c = lane; c < m.cw; c += WAVE) ch |= relax1(m, val, M, r, c);
+            __syncthreads();
+        }
+        for (int r = m.ch - 1; r >= 0; --r) {
+            for (int c = lane; c < m.cw; c += WAVE) ch |= relax1(m, val, M, r, c);
+            __syncthreads();
+        }
+        for (int c = 0; c < m.cw; ++c) {
+            for (int r = lane; r < m.ch; r += WAVE) ch |= relax1(m, val, M, r, c);
+            __syncthreads();
+        }
+        for (int c = m.cw - 1; c >= 0; --c) {
+            for (int r = lane; r < m.ch; r += WAVE) ch |= relax1(m, val, M, r, c);
+            __syncthreads();
+        }
+        if (!wave_or(ch)) break;
+    }
+}
+
+// ---- one flood level ---------------------------------------------------------
+// list[b..e) = the unlabelled pixels of level L.  Keys (distance, label) are
+// relaxed from the pixels labelled before L (distance 1) and from pixels of
+// the level already reached (distance + 1), in any order, to the fixpoint:
+// breadth-first distances with the smallest label at the smallest distance.
+template <typename L>
+__device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e) {
+    using K = KeyPack<L>;
+    const L one = (L)1 << K::SH;
+    const L lmask = one - 1;
+    for (;;) {
+        bool ch = false;
+        for (int pos = b + threadIdx.x; pos < e; pos += WAVE) {
+            const int i = list[pos];
+            const L cur = m.B[i];
+            L best = cur <= -2 ? -cur - 2 : (L)-1;  // -1 = none yet (as unsigned compare below)
+            const int c = i % m.st, r = i / m.st;
+            const int up = r > 0 ? -m.st : 0, dn = r < m.ch - 1 ? m.st : 0;
+            const int lf = c > 0 ? -1 : 0, rt = c < m.cw - 1 ? 1 : 0;
+            const int nb[8] = {i + up + lf, i + up, i + up + rt, i + lf, i + rt, i + dn + lf, i + dn, i + dn + rt};
+            L bv[8];
+            uint8_t fv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                bv[k] = m.B[nb[k]];
+                fv[k] = m.fl[nb[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                // a clamped neighbour is the pixel itself (a current-level pixel:
+                // its own key + 1 never beats its key) or a repeated neighbour
+                if (!(fv[k] & F_IN)) continue;
+                const L bj = bv[k];
+                L cand;
+                if (bj >= 0)
+                    cand = one | bj;
+                else if (bj <= -2)
+                    cand = (-bj - 2) + one;
+                else
+                    continue;
+                if (best < 0 || cand < best) best = cand;
+            }
+            if (best >= 0 && (cur > -2 || best < -cur - 2)) {
+                m.B[i] = -best - 2;
+                ch = true;
+            }
+        }
+        if (!wave_or(ch)) break;
+    }
+    for (int pos = b + threadIdx.x; pos < e; pos += WAVE) {
+        const int i = list[pos];
+        const L cur = m.B[i];
+        if (cur <= -2) m.B[i] = (-cur - 2) & lmask;
+    }
+    __syncthreads();
+}
+
+// ---- the whole per-component stage ---------------------------------------------
+template <typename L>
+__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist) {
+    const int lane = threadIdx.x;
+    const int area = a.st_area[g];
+    // ---- load the component
+    bool zero = false;
+    for (int i = lane; i < m.n; i += WAVE) {
+        const int c = i % m.st, r = i / m.st;
+        bool in = false;
+        if (c < m.cw) {
+            in = a.labels[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c] == g;
+            zero |= !in;
+        }
+        m.fl[i] = in ? F_IN : 0;
+    }
+    const bool has_zero = wave_or(zero);
+    // ---- exact distance transform: column distances, then a pruned row search
+    for (int c = lane; c < m.cw; c += WAVE) {
         int run = GINF;
-        for (int r = 0; r < s.ch; ++r) {
-            int i = r * s.cw + c;
+        for (int r = 0; r < m.ch; ++r) {
+            const int i = r * m.st + c;
             run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
             m.A[i] = run;
         }
         run = GINF;
-        for (int r = s.ch - 1; r >= 0; --r) {
-            int i = r * s.cw + c;
+        for (int r = m.ch - 1; r >= 0; --r) {
+            const int i = r * m.st + c;
             run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
             if (run < m.A[i]) m.A[i] = run;
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        if (!(m.fl[i] & F_IN)) {
+    for (int i = lane; i < m.n; i += WAVE) {
+        const int c = i % m.st, r = i / m.st;
+        if (c >= m.cw || !(m.fl[i] & F_IN)) {
             m.dq[i] = 0;
             continue;
         }
-        if (!has_zero) {
+        if (!has_zero) {  // the crop is the whole tile and all foreground
             m.dq[i] = RT_DQ_MAX;
             continue;
         }
-        int c = i % s.cw, r = i / s.cw;
-        const int32_t *row = m.A + r * s.cw;
+        const int32_t *row = m.A + r * m.st;
         int64_t best = row[c] < GINF ? (int64_t)row[c] * row[c] : INT64_MAX;
         for (int dx = 1;; ++dx) {
-            int64_t dd = (int64_t)dx * dx;
+            const int64_t dd = (int64_t)dx * dx;
             if (dd >= best) break;
-            bool lo = c - dx >= 0, hi = c + dx < s.cw;
+            const bool lo = c - dx >= 0, hi = c + dx < m.cw;
             if (!lo && !hi) break;
             if (lo && row[c - dx] < GINF) best = min(best, dd + (int64_t)row[c - dx] * row[c - dx]);
             if (hi && row[c + dx] < GINF) best = min(best, dd + (int64_t)row[c + dx] * row[c + dx]);
@@ -202,140 +312,160 @@ __device__ void process_object(const ObjArgs &a, int g, const Shape &s, Crop<Key
         m.dq[i] = isqrt_exact(4 * best);
     }
     __syncthreads();
-
     // ---- seeds
     if (a.seeds) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            int px = s.cx0 + i % s.cw, py = s.cy0 + i / s.cw;
-            if ((m.fl[i] & F_IN) && a.seeds[(int64_t)py * a.pitch + px]) m.fl[i] |= F_RM;
+        for (int i = lane; i < m.n; i += WAVE) {
+            const int c = i % m.st, r = i / m.st;
+            if ((m.fl[i] & F_IN) && a.seeds[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c]) m.fl[i] |= F_RM;
         }
         __syncthreads();
     } else {
-        // g = recon(Dq - h under Dq)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
+        for (int i = lane; i < m.n; i += WAVE) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
         __syncthreads();
-        crop_recon(s, m.fl, m.A, m.dq);
-        // regional maxima: g - recon(g - 1 under g) > 0
-        for (int i = threadIdx.x; i < n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? m.A[i] - 1 : NEGV;
+        recon_scans<L, int32_t>(m, m.A, m.dq);  // g = h-maxima of Dq
+        for (int i = lane; i < m.n; i += WAVE) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
         __syncthreads();
-        crop_recon(s, m.fl, m.B, m.A);
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            if ((m.fl[i] & F_IN) && m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
+        recon_scans<L, L>(m, m.B, m.A);         // recon of g-1 under g
+        for (int i = lane; i < m.n; i += WAVE)
+            if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
         __syncthreads();
     }
-    crop_ccl(s, m.fl, F_RM, m.B);  // B = seed label (crop index of the seed component root) or -1
-
-    // ---- lambda = recon(Dq on seeds under Dq)
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
-    __syncthreads();
-    crop_recon(s, m.fl, m.A, m.dq);
-
-    // ---- flood, level by level from the highest lambda
-    for (;;) {
-        int lv = NEGV;
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) lv = max(lv, m.A[i]);
-        const int L = block_max(lv, red);
-        if (L == NEGV) break;
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] == L) m.K[i] = KT::INF;
+    crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
+    int nroots = 0;
+    for (int i = lane; i < m.n; i += WAVE) nroots += (m.B[i] == (L)i);
+    int tot = 0;
+    {
+        if (lane == 0) *red = 0;
         __syncthreads();
-        for (int it = 0;; ++it) {
-            bool ch = false;
-            const bool fwd = (it & 1) == 0;
-            for (int k = threadIdx.x; k < n; k += blockDim.x) {
-                int i = fwd ? k : n - 1 - k;
-                if (!((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] == L)) continue;
-                int c = i % s.cw, r = i / s.cw;
-                KeyT best = m.K[i];
-                for (int dy = -1; dy <= 1; ++dy) {
-                    int rr = r + dy;
-                    if (rr < 0 || rr >= s.ch) continue;
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        int cc = c + dx;
-                        if ((dx | dy) == 0 || cc < 0 || cc >= s.cw) continue;
-                        int j = rr * s.cw + cc;
-                        if (!(m.fl[j] & F_IN)) continue;
-                        KeyT cand = KT::INF;
-                        if (m.B[j] >= 0)
-                            cand = ((KeyT)1 << KT::SH) | (KeyT)m.B[j];
-                        else if (m.A[j] == L && m.K[j] != KT::INF)
-                            cand = m.K[j] + ((KeyT)1 << KT::SH);
-                        if (cand < best) best = cand;
-                    }
-                }
-                if (best < m.K[i]) {
-                    m.K[i] = best;
-                    ch = true;
-                }
-            }
-            if (!__syncthreads_or(ch)) break;
+        if (nroots) atomicAdd(red, nroots);
+        __syncthreads();
+        tot = *red;
+        __syncthreads();
+    }
+    const bool area_ok = area >= a.min_area && (a.max_area < 0 || area <= a.max_area);
+    if (tot <= 1) {
+        // one seed (or none with external seeds): the whole component gets one
+        // label, nothing is cut, and the relabelled component is the component
+        for (int i = lane; i < m.n; i += WAVE) {
+            if (!(m.fl[i] & F_IN)) continue;
+            const int c = i % m.st, r = i / m.st;
+            const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+            a.labels[o] = area_ok ? g : 0;
+            a.mask[o] = area_ok ? 1 : 0;
         }
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] == L)
-                m.B[i] = (int32_t)(m.K[i] & (((KeyT)1 << KT::SH) - 1));
+        if (lane == 0 && area_ok && a.n_kept) atomicAdd(a.n_kept, 1);
         __syncthreads();
+        return;
+    }
+    // ---- lambda = recon of (Dq on seeds) under Dq
+    for (int i = lane; i < m.n; i += WAVE) m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
+    __syncthreads();
+    recon_scans<L, int32_t>(m, m.A, m.dq);
+    // ---- flood, level by level from the highest lambda
+    int lmax = NEGV, lmin = INT_MAX;
+    for (int i = lane; i < m.n; i += WAVE)
+        if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) {
+            lmax = max(lmax, m.A[i]);
+            lmin = min(lmin, m.A[i]);
+        }
+    lmax = wave_max(lmax, red);
+    lmin = wave_min(lmin, red);
+    int32_t *list = m.dq;  // Dq is no longer needed
+    if (lmax != NEGV) {
+        const int range = lmax - lmin + 1;
+        if (range <= HBINS) {
+            // counting sort of the unlabelled pixels by decreasing lambda
+            for (int k = lane; k <= HBINS; k += WAVE) hist[k] = 0;
+            __syncthreads();
+            for (int i = lane; i < m.n; i += WAVE)
+                if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) atomicAdd(hist + 1 + (lmax - m.A[i]), 1);
+            __syncthreads();
+            if (lane == 0)
+                for (int k = 1; k <= HBINS; ++k) hist[k] += hist[k - 1];
+            __syncthreads();
+            // hist[k] = start of bin k; scatter with a moving cursor per bin
+            for (int i = lane; i < m.n; i += WAVE)
+                if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) {
+                    const int pos = atomicAdd(hist + (lmax - m.A[i]), 1);
+                    list[pos] = i;
+                }
+            __syncthreads();
+            // after the scatter hist[k] = end of bin k
+            int b = 0;
+            for (int k = 0; k < range; ++k) {
+                const int e = hist[k];
+                if (e > b) flood_level<L>(m, list, b, e);
+                b = e;
+            }
+        } else {
+            // wide range: find each level, compact its pixels, flood it
+            for (int L0 = lmax; L0 != NEGV;) {
+                if (lane == 0) *red = 0;
+                __syncthreads();
+                for (int i = lane; i < m.n; i += WAVE)
+                    if ((m.fl[i] & F_IN) && m.B[i] == -1 && m.A[i] == L0) list[atomicAdd(red, 1)] = i;
+                __syncthreads();
+                const int cnt = *red;
+                __syncthreads();
+                flood_level<L>(m, list, 0, cnt);
+                int nxt = NEGV;
+                for (int i = lane; i < m.n; i += WAVE)
+                    if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV && m.A[i] < L0) nxt = max(nxt, m.A[i]);
+                L0 = wave_max(nxt, red);
+            }
+        }
     }
     // ---- leftovers (external seeds only): their own components
     if (a.seeds) {
         bool left = false;
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
+        for (int i = lane; i < m.n; i += WAVE)
             if ((m.fl[i] & F_IN) && m.B[i] < 0) {
-                m.fl[i] |= F_M;  // temporary use of the M bit
+                m.fl[i] |= F_M;
                 left = true;
             }
-        if (__syncthreads_or(left)) {
-            crop_ccl(s, m.fl, F_M, m.A);
-            for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (wave_or(left)) {
+            crop_ccl<L, int32_t>(m, F_M, m.A);
+            for (int i = lane; i < m.n; i += WAVE)
                 if (m.fl[i] & F_M) m.B[i] = m.A[i];
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < n; i += blockDim.x) m.fl[i] &= (uint8_t)~F_M;
+        for (int i = lane; i < m.n; i += WAVE) m.fl[i] &= (uint8_t)~F_M;
         __syncthreads();
     }
-
     // ---- cut: keep p iff no neighbour in the component has a smaller label
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = lane; i < m.n; i += WAVE) {
         if (!(m.fl[i] & F_IN)) continue;
-        int c = i % s.cw, r = i / s.cw;
-        int lab = m.B[i];
+        const int c = i % m.st, r = i / m.st;
+        const L lab = m.B[i];
+        const int up = r > 0 ? -m.st : 0, dn = r < m.ch - 1 ? m.st : 0;
+        const int lf = c > 0 ? -1 : 0, rt = c < m.cw - 1 ? 1 : 0;
+        const int nb[8] = {i + up + lf, i + up, i + up + rt, i + lf, i + rt, i + dn + lf, i + dn, i + dn + rt};
         bool keep = true;
-        for (int dy = -1; dy <= 1 && keep; ++dy) {
-            int rr = r + dy;
-            if (rr < 0 || rr >= s.ch) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int cc = c + dx;
-                if ((dx | dy) == 0 || cc < 0 || cc >= s.cw) continue;
-                int j = rr * s.cw + cc;
-                if ((m.fl[j] & F_IN) && m.B[j] < lab) {
-                    keep = false;
-                    break;
-                }
-            }
-        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((m.fl[nb[k]] & F_IN) && m.B[nb[k]] < lab) keep = false;
         if (keep) m.fl[i] |= F_M;
     }
     __syncthreads();
-    // ---- relabel the kept pixels, count areas
-    crop_ccl(s, m.fl, F_M, m.A);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m.dq[i] = 0;
+    // ---- relabel the kept pixels, area of each piece, write out
+    crop_ccl<L, int32_t>(m, F_M, m.A);
+    int32_t *cnt = m.dq;
+    for (int i = lane; i < m.n; i += WAVE) cnt[i] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        if (m.fl[i] & F_M) atomicAdd(m.dq + m.A[i], 1);
+    for (int i = lane; i < m.n; i += WAVE)
+        if (m.fl[i] & F_M) atomicAdd(cnt + m.A[i], 1);
     __syncthreads();
     int kept = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = lane; i < m.n; i += WAVE) {
         if (!(m.fl[i] & F_IN)) continue;
-        int px = s.cx0 + i % s.cw, py = s.cy0 + i / s.cw;
-        int64_t o = (int64_t)py * a.pitch + px;
+        const int c = i % m.st, r = i / m.st;
+        const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
         int lab = 0;
         if (m.fl[i] & F_M) {
-            int root = m.A[i];
-            int ar = m.dq[root];
-            bool ok = ar >= a.min_area && (a.max_area < 0 || ar <= a.max_area);
-            if (ok) {
-                lab = (s.cy0 + root / s.cw) * a.w + s.cx0 + root % s.cw + 1;
+            const int root = m.A[i];
+            const int ar = cnt[root];
+            if (ar >= a.min_area && (a.max_area < 0 || ar <= a.max_area)) {
+                lab = (m.cy0 + root / m.st) * a.w + m.cx0 + root % m.st + 1;
                 if (root == i) ++kept;
             }
         }
@@ -346,20 +476,26 @@ __device__ void process_object(const ObjArgs &a, int g, const Shape &s, Crop<Key
     __syncthreads();
 }
 
-__device__ bool object_shape(const ObjArgs &a, int g, Shape &s) {
-    s.cx0 = max(0, a.st_x0[g] - 1);
-    s.cy0 = max(0, a.st_y0[g] - 1);
-    int cx1 = min(a.w - 1, a.st_x1[g] + 1), cy1 = min(a.h - 1, a.st_y1[g] + 1);
-    s.cw = cx1 - s.cx0 + 1;
-    s.ch = cy1 - s.cy0 + 1;
-    s.n = s.cw * s.ch;
-    return true;
+struct CropGeom {
+    int cx0, cy0, cw, ch, st, n;
+};
+
+__device__ __forceinline__ CropGeom crop_geom(const ObjArgs &a, int g) {
+    CropGeom q;
+    q.cx0 = max(0, a.st_x0[g] - 1);
+    q.cy0 = max(0, a.st_y0[g] - 1);
+    const int cx1 = min(a.w - 1, a.st_x1[g] + 1), cy1 = min(a.h - 1, a.st_y1[g] + 1);
+    q.cw = cx1 - q.cx0 + 1;
+    q.ch = cy1 - q.cy0 + 1;
+    q.st = q.cw | 1;
+    q.n = q.st * q.ch;
+    return q;
 }
 
-__device__ void erase_object(const ObjArgs &a, int g, const Shape &s) {
-    for (int i = threadIdx.x; i < s.n; i += blockDim.x) {
-        int px = s.cx0 + i % s.cw, py = s.cy0 + i / s.cw;
-        int64_t o = (int64_t)py * a.pitch + px;
+__device__ void erase_object(const ObjArgs &a, int g, const CropGeom &q) {
+    for (int i = threadIdx.x; i < q.cw * q.ch; i += blockDim.x) {
+        const int c = i % q.cw, r = i / q.cw;
+        const int64_t o = (int64_t)(q.cy0 + r) * a.pitch + q.cx0 + c;
         if (a.labels[o] == g) {
             a.labels[o] = 0;
             a.mask[o] = 0;
@@ -367,141 +503,101 @@ __device__ void erase_object(const ObjArgs &a, int g, const Shape &s) {
     }
 }
 
-__global__ __launch_bounds__(OBJ_THREADS) void k_objects(ObjArgs a) {
+template <int CAP>
+__device__ __forceinline__ Crop<int32_t> lds_crop(unsigned char *smem, const CropGeom &q) {
+    Crop<int32_t> m;
+    m.dq = (int32_t *)smem;
+    m.A = m.dq + CAP;
+    m.B = m.A + CAP;
+    m.fl = (uint8_t *)(m.B + CAP);
+    m.st = q.st;
+    m.cw = q.cw;
+    m.ch = q.ch;
+    m.cx0 = q.cx0;
+    m.cy0 = q.cy0;
+    m.n = q.n;
+    return m;
+}
+
+// small class: reads the component list, erases components below the first
+// area threshold, defers crops above CAP_S
+__global__ __launch_bounds__(WAVE) void k_objects_s(ObjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
-    Crop<uint32_t> m;
-    m.dq = (int32_t *)smem;
-    m.A = m.dq + LDS_CAP;
-    m.B = m.A + LDS_CAP;
-    m.K = (uint32_t *)(m.B + LDS_CAP);
-    m.fl = (uint8_t *)(m.K + LDS_CAP);
+    __shared__ int hist[HBINS + 1];
     const int nobj = *a.n_obj;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int g = a.obj_list[o];
-        Shape s;
-        object_shape(a, g, s);
+        const CropGeom q = crop_geom(a, g);
         if (a.st_area[g] < a.min_area_pre) {
-            erase_object(a, g, s);
+            erase_object(a, g, q);
             continue;
         }
-        if (s.n > LDS_CAP) {
-            if (threadIdx.x == 0) a.big_list[atomicAdd(a.n_big, 1)] = g;
+        if (q.n > CAP_S) {
+            if (threadIdx.x == 0) a.list_m[atomicAdd(a.n_m, 1)] = g;
             continue;
         }
-        process_object<uint32_t>(a, g, s, m, &red);
+        process_object<int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist);
     }
 }
 
-__global__ __launch_bounds__(OBJ_THREADS) void k_objects_big(ObjArgs a, size_t per_block) {
+__global__ __launch_bounds__(WAVE) void k_objects_m(ObjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
+    __shared__ int hist[HBINS + 1];
+    const int nobj = *a.n_m;
+    for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
+        const int g = a.list_m[o];
+        const CropGeom q = crop_geom(a, g);
+        if (q.n > CAP_M) {
+            if (threadIdx.x == 0) a.big_list[atomicAdd(a.n_big, 1)] = g;
+            continue;
+        }
+        process_object<int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist);
+    }
+}
+
+__global__ __launch_bounds__(WAVE) void k_objects_big(ObjArgs a, size_t per_block) {
+    __shared__ int red;
+    __shared__ int hist[HBINS + 1];
     const int nbig = *a.n_big;
     char *base = (char *)a.big_scratch + per_block * blockIdx.x;
     for (int o = blockIdx.x; o < nbig; o += gridDim.x) {
         const int g = a.big_list[o];
-        Shape s;
-        object_shape(a, g, s);
-        Crop<uint64_t> m;
-        m.K = (uint64_t *)base;
-        m.dq = (int32_t *)(m.K + s.n);
-        m.A = m.dq + s.n;
-        m.B = m.A + s.n;
-        m.fl = (uint8_t *)(m.B + s.n);
-        process_object<uint64_t>(a, g, s, m, &red);
+        const CropGeom q = crop_geom(a, g);
+        Crop<int64_t> m;
+        m.B = (int64_t *)base;
+        m.dq = (int32_t *)(m.B + q.n);
+        m.A = m.dq + q.n;
+        m.fl = (uint8_t *)(m.A + q.n);
+        m.st = q.st;
+        m.cw = q.cw;
+        m.ch = q.ch;
+        m.cx0 = q.cx0;
+        m.cy0 = q.cy0;
+        m.n = q.n;
+        process_object<int64_t>(a, g, m, &red, hist);
     }
 }
 
-int launch_objects(const ObjArgs &a, hipStream_t s) {
-    size_t lds = (size_t)LDS_CAP * (4 * 4 + 1);
-    int grid = a.max_obj;
-    hipLaunchKernelGGL(k_objects, dim3(grid), dim3(OBJ_THREADS), lds, s, a);
-    return hip_fail(hipGetLastError(), "k_objects");
-}
+// bytes of global scratch one block needs for the largest crop of a w x h tile
+size_t big_object_bytes(int w, int h) { return (size_t)h * (size_t)(w | 1) * (8 + 4 + 4 + 1) + 256; }
 
-// bytes of global scratch one big object of `n` crop pixels needs
-size_t big_object_bytes(size_t n) { return n * (8 + 4 * 3 + 1) + 256; }
-
-int launch_objects_big(const ObjArgs &a, int n_big_host, hipStream_t s) {
-    if (n_big_host <= 0) return RT_OK;
-    size_t per = big_object_bytes((size_t)a.w * a.h);
-    per = (per + 255) & ~size_t(255);
-    size_t cap_blocks = a.big_scratch_elems * sizeof(int32_t) / per;
-    int grid = (int)std::min<size_t>((size_t)n_big_host, cap_blocks);
+int launch_objects(const ObjArgs &a, int n_cu, hipStream_t s) {
+    const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
+    hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, a);
+    RT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 2), dim3(WAVE), lds_m, s, a);
+    RT_HIP(hipGetLastError());
+    size_t per = (big_object_bytes(a.w, a.h) + 255) & ~size_t(255);
+    int grid = (int)std::min<size_t>(a.big_scratch_bytes / per, 4);
     if (grid < 1) {
         set_error("objects: big-object scratch too small");
         return RT_ENOMEM;
     }
-    hipLaunchKernelGGL(k_objects_big, dim3(grid), dim3(OBJ_THREADS), 0, s, a, per);
-    return hip_fail(hipGetLastError(), "k_objects_big");
-}
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__global__ void k_fill_i32(int32_t *p, int32_t v, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
-}
-int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s) {
-    if (!n) return RT_OK;
-    int grid = (int)std::min<size_t>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(256), 0, s, p, v, n);
-    return hip_fail(hipGetLastError(), "k_fill_i32");
-}
-
-__global__ void k_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out) {
-    int64_t n = (int64_t)w * h;
-    int c = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        c += m[y * pitch + x] == 0;
-    }
-    if (__syncthreads_or(c > 0) && threadIdx.x == 0) atomicAdd(out, 1);
-}
-int launch_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out, hipStream_t s) {
-    int64_t n = (int64_t)w * h;
-    int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_count_zero, dim3(grid), dim3(256), 0, s, m, w, h, pitch, out);
-    return hip_fail(hipGetLastError(), "k_count_zero");
-}
-
-// area filter on labels (root ids); area_scratch has w*h+1 entries
-__global__ void k_area_zero(const int32_t *lab, int w, int h, int64_t pitch, int32_t *area) {
-    int64_t n = (int64_t)w * h;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        int l = lab[y * pitch + x];
-        if (l > 0 && l <= n) area[l] = 0;
-    }
-}
-__global__ void k_area_count(const int32_t *lab, int w, int h, int64_t pitch, int32_t *area) {
-    int64_t n = (int64_t)w * h;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        int l = lab[y * pitch + x];
-        if (l > 0 && l <= n) atomicAdd(area + l, 1);
-    }
-}
-__global__ void k_area_apply(const int32_t *lab, int32_t *out, uint8_t *mask, int w, int h, int64_t pitch,
-                             const int32_t *area, int lo, int hi) {
-    int64_t n = (int64_t)w * h;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        int64_t o = y * pitch + x;
-        int l = lab[o];
-        int v = (l > 0 && l <= n && area[l] >= lo && area[l] <= hi) ? l : 0;
-        out[o] = v;
-        if (mask) mask[o] = v ? 1 : 0;
-    }
-}
-int launch_area_filter(const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int w, int h, int64_t pitch,
-                       int min_area, int max_area, int32_t *area, hipStream_t s) {
-    int64_t n = (int64_t)w * h;
-    int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_area_zero, dim3(grid), dim3(256), 0, s, lab_in, w, h, pitch, area);
-    hipLaunchKernelGGL(k_area_count, dim3(grid), dim3(256), 0, s, lab_in, w, h, pitch, area);
-    hipLaunchKernelGGL(k_area_apply, dim3(grid), dim3(256), 0, s, lab_in, lab_out, mask_out, w, h, pitch, area,
-                       min_area, max_area);
-    return hip_fail(hipGetLastError(), "k_area");
+    hipLaunchKernelGGL(k_objects_big, dim3(grid), dim3(WAVE), 0, s, a, per);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
 }
 
 }  // namespace rtseg

@@ -2,14 +2,16 @@
 // (IWPP) behind ReconToNuclei (Sec. 5.1).
 //
 // The paper's GPU version keeps a queue of active pixels; here the unit of
-// activity is a 64 x 64 tile handled by one wavefront:
-//   * the tile's current values live in 64 VGPRs per lane (lane = column),
-//     the mask in LDS;
+// activity is a 62 x 62 tile handled by one wavefront:
+//   * the wave holds the tile and its one-pixel ring of neighbour values as a
+//     64 x 64 block, 64 registers per lane, with the mask in registers too
+//     (both orientations, packed for uint8), so a scan step touches no memory
+//     and ring lanes feed the DPP shifts like any other lane;
 //   * a sweep is four directional scans: down and up with lane = column, then
-//     (after a transpose through LDS) right and left with lane = row.  Each
-//     scan step takes the 3 neighbours of the previous row/column from the
-//     lane's own register and its two neighbour lanes via DPP wave shifts,
-//     so a value can travel 64 pixels in one scan;
+//     (after an LDS transpose) right and left with lane = row.  Each scan step
+//     takes the 3 neighbours of the previous row/column from the lane's own
+//     register and its two neighbour lanes via DPP wave shifts, so a value can
+//     travel 64 pixels in one scan;
 //   * sweeps repeat until the tile reaches its local fixpoint; values of the
 //     one-pixel halo come from the neighbouring tiles as they are in memory;
 //   * a tile whose edge changed puts the neighbours that read that edge on
@@ -24,7 +26,7 @@
 
 namespace rtseg {
 
-constexpr int RTILE = 64;
+constexpr int RIN = 62;   // interior edge of a tile (the 64-lane block adds a 1-px ring)
 constexpr int NEG = INT_MIN;
 
 struct RoundArgs {
@@ -44,12 +46,6 @@ struct RoundArgs {
     int max_sweeps;
 };
 
-__device__ __forceinline__ int shr1(int v, int old) {  // lane i <- lane i-1; lane 0 <- old
-    return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
-}
-__device__ __forceinline__ int shl1(int v, int old) {  // lane i <- lane i+1; lane 63 <- old
-    return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
-}
 
 template <typename T>
 __device__ __forceinline__ int gval(const RoundArgs &a, const T *p, int x, int y) {
@@ -61,29 +57,44 @@ __device__ __forceinline__ int gval(const RoundArgs &a, const T *p, int x, int y
 
 __device__ __forceinline__ bool wave_any(bool c) { return __ballot(c) != 0; }
 
-// One directional scan over the 64 rows held in r[] (lane = column).
-// prev*: values of the row before the first one; edgeL/edgeR: the halo
-// column values used by lanes 0 / 63 for each row.
-template <int CONN, bool DOWN>
-__device__ __forceinline__ bool scan_v(int (&r)[64], const int (*Is)[65], int lane, int pc, int pl, int pr,
-                                       const int *edgeL, const int *edgeR) {
-    bool ch = false;
+// The mask of one tile in registers, for one orientation (64 entries per
+// lane).  uint8 masks are packed four per register; non-members (outside the
+// image or the domain) read as NEG, so they neither rise nor propagate.
+template <typename T>
+struct MaskRegs;
+template <>
+struct MaskRegs<uint8_t> {
+    uint32_t p[16];
+    uint64_t mem;
+    __device__ void clear() {
 #pragma unroll
-    for (int s = 0; s < 64; ++s) {
-        const int y = DOWN ? s : 63 - s;
-        int m = pc;
-        if (CONN == 8) m = max(m, max(pl, pr));
-        int iv = Is[y][lane];
-        int nv = max(r[y], min(m, iv));
-        ch |= nv != r[y];
-        r[y] = nv;
-        pc = nv;
-        if (CONN == 8) {
-            pl = shr1(nv, edgeL[y]);
-            pr = shl1(nv, edgeR[y]);
+        for (int k = 0; k < 16; ++k) p[k] = 0;
+        mem = 0;
+    }
+    __device__ void set(int k, int v) {  // k compile-time after unrolling
+        if (v != NEG) {
+            p[k >> 2] |= (uint32_t)(v & 255) << ((k & 3) * 8);
+            mem |= 1ull << k;
         }
     }
-    return ch;
+    __device__ int eff(int k) const { return ((mem >> k) & 1ull) ? (int)((p[k >> 2] >> ((k & 3) * 8)) & 255u) : NEG; }
+};
+template <>
+struct MaskRegs<int32_t> {
+    int v[64];
+    __device__ void clear() {}
+    __device__ void set(int k, int x) { v[k] = x; }
+    __device__ int eff(int k) const { return v[k]; }
+};
+
+// one scan step: value of this pixel given the three predecessors' maximum m
+__device__ __forceinline__ int step_val(int rv, int m, int mv) { return max(rv, min(m, mv)); }
+
+__device__ __forceinline__ int shr0(int v) {  // lane i <- lane i-1 (lane 0: don't care)
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int shl0(int v) {  // lane i <- lane i+1 (lane 63: don't care)
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
 }
 
 template <typename T, int CONN>
@@ -98,98 +109,124 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
     if ((int)blockIdx.x >= n_in) return;
     const int tile = a.first ? (int)blockIdx.x : a.list_in[blockIdx.x];
     const int tx = tile % a.ntx, ty = tile / a.ntx;
-    const int x0 = tx * RTILE, y0 = ty * RTILE;
+    // the register block covers the interior [x0, x0+62) x [y0, y0+62) and a
+    // one-pixel ring: block coordinate (i, j) is image pixel (x0-1+i, y0-1+j)
+    const int x0 = tx * RIN, y0 = ty * RIN;
     const T *mask = static_cast<const T *>(a.mask);
     T *rr = static_cast<T *>(a.r);
 
-    __shared__ int Is[64][65];
     __shared__ int Ts[64][65];
-    __shared__ int hT[66], hB[66], hL[64], hR[64];
-    __shared__ int oL[64], oR[64];
 
     int r[64];
-    const int x = x0 + lane;
+    MaskRegs<T> mc, mr;
+    mc.clear();
+    mr.clear();
+    const int gx = x0 - 1 + lane;
+    const bool col_inner = lane >= 1 && lane <= 62;
 #pragma unroll
-    for (int y = 0; y < 64; ++y) {
-        r[y] = gval<T>(a, rr, x, y0 + y);
-        Is[y][lane] = gval<T>(a, mask, x, y0 + y);
+    for (int j = 0; j < 64; ++j) {
+        const int gy = y0 - 1 + j;
+        r[j] = gval<T>(a, rr, gx, gy);
+        // ring pixels are read-only: they carry mask NEG
+        const int mv = (col_inner && j >= 1 && j <= 62) ? gval<T>(a, mask, gx, gy) : NEG;
+        mc.set(j, mv);
+        Ts[j][lane] = mv;
     }
-    hT[lane + 1] = gval<T>(a, rr, x, y0 - 1);
-    hB[lane + 1] = gval<T>(a, rr, x, y0 + 64);
-    if (lane == 0) {
-        hT[0] = gval<T>(a, rr, x0 - 1, y0 - 1);
-        hB[0] = gval<T>(a, rr, x0 - 1, y0 + 64);
-        hT[65] = gval<T>(a, rr, x0 + 64, y0 - 1);
-        hB[65] = gval<T>(a, rr, x0 + 64, y0 + 64);
-    }
-    hL[lane] = gval<T>(a, rr, x0 - 1, y0 + lane);
-    hR[lane] = gval<T>(a, rr, x0 + 64, y0 + lane);
-    const int oT = r[0], oB = r[63];
-#pragma unroll
-    for (int y = 0; y < 64; ++y) Ts[y][lane] = r[y];
     __syncthreads();
-    oL[lane] = Ts[lane][0];
-    oR[lane] = Ts[lane][63];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) mr.set(i, Ts[lane][i]);
+    __syncthreads();
+    // original interior edge values (row 1 / row 62 per lane = column,
+    // column 1 / column 62 per lane = row, through the transpose below)
+    const int oT = r[1], oB = r[62];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) Ts[j][lane] = r[j];
+    __syncthreads();
+    const int oL = Ts[lane][1], oR = Ts[lane][62];
     __syncthreads();
 
     bool any_change = false;
     bool converged = false;
     for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
         bool ch = false;
-        // down / up, lane = column
-        ch |= scan_v<CONN, true>(r, Is, lane, hT[lane + 1], hT[lane], hT[lane + 2], hL, hR);
-        ch |= scan_v<CONN, false>(r, Is, lane, hB[lane + 1], hB[lane], hB[lane + 2], hL, hR);
+        // down and up, lane = column; ring lanes never change and feed their
+        // values to the DPP shifts like any other lane
+        {
+            int pc = r[0];
+            int pl = shr0(pc), pr = shl0(pc);
+#pragma unroll
+            for (int j = 1; j < 64; ++j) {
+                const int m = CONN == 8 ? max(pc, max(pl, pr)) : pc;
+                const int nv = step_val(r[j], m, mc.eff(j));
+                ch |= nv != r[j];
+                r[j] = nv;
+                pc = nv;
+                if (CONN == 8) {
+                    pl = shr0(nv);
+                    pr = shl0(nv);
+                }
+            }
+            pc = r[63];
+            pl = shr0(pc);
+            pr = shl0(pc);
+#pragma unroll
+            for (int j = 62; j >= 0; --j) {
+                const int m = CONN == 8 ? max(pc, max(pl, pr)) : pc;
+                const int nv = step_val(r[j], m, mc.eff(j));
+                ch |= nv != r[j];
+                r[j] = nv;
+                pc = nv;
+                if (CONN == 8) {
+                    pl = shr0(nv);
+                    pr = shl0(nv);
+                }
+            }
+        }
         // transpose: lane = row
 #pragma unroll
-        for (int y = 0; y < 64; ++y) Ts[y][lane] = r[y];
+        for (int j = 0; j < 64; ++j) Ts[j][lane] = r[j];
         __syncthreads();
 #pragma unroll
-        for (int xx = 0; xx < 64; ++xx) r[xx] = Ts[lane][xx];
+        for (int i = 0; i < 64; ++i) r[i] = Ts[lane][i];
         __syncthreads();
-        // right / left: previous column comes from the left/right halo
+        // right and left, lane = row
         {
-            bool c2 = false;
-            int pc = hL[lane];
-            int pl = lane > 0 ? hL[lane - 1] : hT[0];
-            int pr = lane < 63 ? hL[lane + 1] : hB[0];
+            int pc = r[0];
+            int pl = shr0(pc), pr = shl0(pc);
 #pragma unroll
-            for (int xx = 0; xx < 64; ++xx) {
-                int m = pc;
-                if (CONN == 8) m = max(m, max(pl, pr));
-                int nv = max(r[xx], min(m, Is[lane][xx]));
-                c2 |= nv != r[xx];
-                r[xx] = nv;
+            for (int i = 1; i < 64; ++i) {
+                const int m = CONN == 8 ? max(pc, max(pl, pr)) : pc;
+                const int nv = step_val(r[i], m, mr.eff(i));
+                ch |= nv != r[i];
+                r[i] = nv;
                 pc = nv;
                 if (CONN == 8) {
-                    pl = shr1(nv, hT[xx + 1]);
-                    pr = shl1(nv, hB[xx + 1]);
+                    pl = shr0(nv);
+                    pr = shl0(nv);
                 }
             }
-            pc = hR[lane];
-            pl = lane > 0 ? hR[lane - 1] : hT[65];
-            pr = lane < 63 ? hR[lane + 1] : hB[65];
+            pc = r[63];
+            pl = shr0(pc);
+            pr = shl0(pc);
 #pragma unroll
-            for (int s = 0; s < 64; ++s) {
-                const int xx = 63 - s;
-                int m = pc;
-                if (CONN == 8) m = max(m, max(pl, pr));
-                int nv = max(r[xx], min(m, Is[lane][xx]));
-                c2 |= nv != r[xx];
-                r[xx] = nv;
+            for (int i = 62; i >= 0; --i) {
+                const int m = CONN == 8 ? max(pc, max(pl, pr)) : pc;
+                const int nv = step_val(r[i], m, mr.eff(i));
+                ch |= nv != r[i];
+                r[i] = nv;
                 pc = nv;
                 if (CONN == 8) {
-                    pl = shr1(nv, hT[xx + 1]);
-                    pr = shl1(nv, hB[xx + 1]);
+                    pl = shr0(nv);
+                    pr = shl0(nv);
                 }
             }
-            ch |= c2;
         }
-        // transpose back: lane = column
+        // transpose back: lane = column (Ts keeps the row-major copy)
 #pragma unroll
-        for (int xx = 0; xx < 64; ++xx) Ts[lane][xx] = r[xx];
+        for (int i = 0; i < 64; ++i) Ts[lane][i] = r[i];
         __syncthreads();
 #pragma unroll
-        for (int y = 0; y < 64; ++y) r[y] = Ts[y][lane];
+        for (int j = 0; j < 64; ++j) r[j] = Ts[j][lane];
         __syncthreads();
         if (!wave_any(ch)) {
             converged = true;
@@ -199,21 +236,19 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
     }
     if (!any_change) return;
 
-    // write back (own column), only real graph nodes
+    // write back the interior members (own column)
 #pragma unroll
-    for (int y = 0; y < 64; ++y) {
-        int gy = y0 + y;
-        if (x < a.w && gy < a.h && r[y] != NEG) {
-            int64_t o = (int64_t)gy * a.pitch + x;
-            rr[o] = (T)r[y];
-        }
+    for (int j = 1; j < 63; ++j) {
+        const int gy = y0 - 1 + j;
+        if (mc.eff(j) != NEG) rr[(int64_t)gy * a.pitch + gx] = (T)r[j];
     }
-    // which edges changed?  (Ts holds the final tile, row-major)
-    const bool cT = r[0] != oT, cB = r[63] != oB;
-    const bool cL = Ts[lane][0] != oL[lane], cR = Ts[lane][63] != oR[lane];
+    // which interior edges changed?
+    const bool cT = col_inner && r[1] != oT, cB = col_inner && r[62] != oB;
+    const bool row_inner = lane >= 1 && lane <= 62;
+    const bool cL = row_inner && Ts[lane][1] != oL, cR = row_inner && Ts[lane][62] != oR;
     const uint64_t mT = __ballot(cT), mB = __ballot(cB), mL = __ballot(cL), mR = __ballot(cR);
     if (lane == 0) {
-        int nb[8];
+        int nb[9];
         int nn = 0;
         auto add = [&](int dx, int dy) {
             int nx = tx + dx, ny = ty + dy;
@@ -224,10 +259,10 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
         if (mL) add(-1, 0);
         if (mR) add(1, 0);
         if (CONN == 8) {
-            if (mT & 1ull) add(-1, -1);
-            if (mT >> 63) add(1, -1);
-            if (mB & 1ull) add(-1, 1);
-            if (mB >> 63) add(1, 1);
+            if ((mT >> 1) & 1ull) add(-1, -1);   // interior corner (1, 1)
+            if ((mT >> 62) & 1ull) add(1, -1);   // (62, 1)
+            if ((mB >> 1) & 1ull) add(-1, 1);    // (1, 62)
+            if ((mB >> 62) & 1ull) add(1, 1);    // (62, 62)
         }
         if (!converged) nb[nn++] = tile;  // sweep budget exhausted: continue next round
         for (int k = 0; k < nn; ++k) {
@@ -261,21 +296,44 @@ int recon_init(int dtype, const void *marker, const void *mask, void *out, const
     return hip_fail(hipGetLastError(), "k_recon_init");
 }
 
-// Level choice for the connectivity lower bound: the smallest levels whose
-// upper-set density drops to each of the target fractions (the bound helps
-// most around the density at which the upper set stops percolating).
+// Level choice for the connectivity lower bound: the bound helps most around
+// the density at which the upper level set {v >= l} stops percolating (about
+// 0.41 for 8-connected sites), so the n levels are the smallest values whose
+// upper-set density drops to n targets spread over [0.33, 0.75].
 __global__ void k_select_levels(const uint32_t *hist, int n_levels, int32_t *levels) {
     if (threadIdx.x != 0) return;
-    const double q[8] = {0.80, 0.70, 0.60, 0.52, 0.46, 0.41, 0.36, 0.30};
     double total = 0;
     for (int v = 0; v < 256; ++v) total += hist[v];
     double above = total;  // pixels with value >= v
     int k = 0;
     for (int v = 0; v < 256 && k < n_levels; ++v) {
-        while (k < n_levels && above <= q[k] * total) levels[k++] = v > 0 ? v : 1;
+        for (;;) {
+            if (k >= n_levels) break;
+            const double q = n_levels == 1 ? 0.5 : 0.75 - 0.42 * k / (n_levels - 1);
+            if (above > q * total) break;
+            levels[k++] = v > 0 ? v : 1;
+        }
         above -= hist[v];
     }
     while (k < n_levels) levels[k++] = 255;
+}
+
+// R0 = J: the frame marker (Hq on the 1-pixel tile frame, 0 inside)
+__global__ void k_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h) {
+    const int64_t n = (int64_t)w * h;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / w, x = i - y * w;
+        const bool fr = x == 0 || y == 0 || x == w - 1 || y == h - 1;
+        r[y * pitch_r + x] = fr ? hq[y * pitch_hq + x] : 0;
+    }
+}
+
+int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h,
+                        hipStream_t s) {
+    const int64_t n = (int64_t)w * h;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_frame_marker, dim3(grid), dim3(256), 0, s, hq, pitch_hq, r, pitch_r, w, h);
+    return hip_fail(hipGetLastError(), "k_frame_marker");
 }
 
 int launch_select_levels(const uint32_t *hist, int n_levels, int32_t *levels, hipStream_t s) {
@@ -288,8 +346,10 @@ static void launch_round(const RoundArgs &ra, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_recon_round<T, CONN>), dim3(grid), dim3(64), 0, s, ra);
 }
 
-int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s) {
-    const int ntx = (a.w + RTILE - 1) / RTILE, nty = (a.h + RTILE - 1) / RTILE;
+int64_t recon_tiles(int w, int h) { return (int64_t)((w + RIN - 1) / RIN) * ((h + RIN - 1) / RIN); }
+
+int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s, int *rounds_out) {
+    const int ntx = (a.w + RIN - 1) / RIN, nty = (a.h + RIN - 1) / RIN;
     const int ntiles = ntx * nty;
     int e = ensure_stamps(c, (size_t)ntiles);
     if (e) return e;
@@ -349,6 +409,7 @@ int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s) {
         }
     }
     c->arena.off = mark;
+    if (rounds_out) *rounds_out = k;
     return e;
 }
 

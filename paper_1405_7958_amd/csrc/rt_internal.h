@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/rtseg.h"
 
@@ -55,6 +56,12 @@ struct rt_ctx_impl {
     uint32_t *stamps = nullptr;  // per-tile stamp array (device)
     size_t stamps_cap = 0;
     Knobs knobs;
+    // stage timing
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_events;   // (RT_PROF_STAGES + 1) per profiled call
+    size_t prof_used = 0;                  // events in use
+    int64_t prof_launches[RT_PROF_STAGES] = {};
+    int prof_calls = 0;
 };
 
 int ensure_arena(rt_ctx_impl *c, size_t bytes);
@@ -115,8 +122,11 @@ struct ReconArgs {
 };
 int recon_init(int dtype, const void *marker, const void *mask, void *out, const uint8_t *domain, int w, int h,
                int64_t pitch, hipStream_t s);
-int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s);
+int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s, int *rounds_out = nullptr);
+int64_t recon_tiles(int w, int h);   // number of reconstruction tiles of a w x h image
 int launch_select_levels(const uint32_t *hist, int n_levels, int32_t *levels, hipStream_t s);
+int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h,
+                        hipStream_t s);
 
 // area filter for labels produced by CCL (root ids)
 int launch_area_filter(const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int w, int h, int64_t pitch,
@@ -128,7 +138,6 @@ struct ObjArgs {
     int64_t pitch;
     const int32_t *obj_list;
     const int32_t *n_obj;
-    int max_obj;
     const int32_t *st_area, *st_x0, *st_x1, *st_y0, *st_y1;
     int32_t *labels;               // in: root id of each pixel's component; out: final labels
     uint8_t *mask;                 // out
@@ -137,13 +146,13 @@ struct ObjArgs {
     int min_area_pre;              // components below this area are erased
     int min_area, max_area;        // final area filter (max_area < 0: none)
     int32_t *n_kept;               // nullable: number of kept objects
-    int tile_has_zero;             // 0 if the tile has no background pixel (Dq = DQ_MAX)
-    int32_t *big_scratch;          // global scratch for objects whose crop exceeds LDS
-    size_t big_scratch_elems;
-    int32_t *big_list, *n_big;     // objects deferred to the large-object path
+    int32_t *list_m, *n_m;         // components deferred to the medium LDS class
+    int32_t *big_list, *n_big;     // components deferred to the global-memory class
+    void *big_scratch;             // global scratch slices for the global-memory class
+    size_t big_scratch_bytes;
 };
-int launch_objects(const ObjArgs &a, hipStream_t s);
-int launch_objects_big(const ObjArgs &a, int n_big_host, hipStream_t s);
+int launch_objects(const ObjArgs &a, int n_cu, hipStream_t s);
+size_t big_object_bytes(int w, int h);
 
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
 int launch_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out, hipStream_t s);

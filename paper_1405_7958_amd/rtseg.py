@@ -60,6 +60,12 @@ def lib():
         L.rt_watershed.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, i64, vp]
         L.rt_seg_params_default.argtypes = [C.POINTER(rt_seg_params)]
         L.rt_segment_tile.argtypes = [vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), vp, vp, i64, vp, vp, vp]
+        L.rt_set_knob.argtypes = [vp, C.c_char_p, C.c_int]
+        L.rt_get_knob.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
+        L.rt_profile_enable.argtypes = [vp, C.c_int]
+        L.rt_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+        L.rt_profile_stage_name.argtypes = [C.c_int]
+        L.rt_profile_stage_name.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -244,6 +250,41 @@ def rt_segment_tile(rgb, params=None, want_hq=False, ctx=None, out=None):
     return (mask, lab, n, hq) if want_hq else (mask, lab, n)
 
 
+RT_PROF_STAGES = 7
+KNOBS = ("recon_levels", "recon_round_batch", "recon_max_sweeps")
+
+
+def rt_set_knob(name, value, ctx=None):
+    ctx = ctx or default_context()
+    _check(lib().rt_set_knob(ctx.h, name.encode(), int(value)))
+
+
+def rt_get_knob(name, ctx=None):
+    ctx = ctx or default_context()
+    v = C.c_int()
+    _check(lib().rt_get_knob(ctx.h, name.encode(), C.byref(v)))
+    return v.value
+
+
+
+def rt_profile_enable(enable=True, ctx=None):
+    ctx = ctx or default_context()
+    _check(lib().rt_profile_enable(ctx.h, 1 if enable else 0))
+
+
+def rt_profile_read(ctx=None):
+    """Returns (n_calls, {stage: (ms_total, launches)}) since the last read."""
+    ctx = ctx or default_context()
+    ms = (C.c_double * RT_PROF_STAGES)()
+    ln = (C.c_int64 * RT_PROF_STAGES)()
+    n = lib().rt_profile_read(ctx.h, ms, ln, RT_PROF_STAGES)
+    if n < 0:
+        _check(n)
+    names = [lib().rt_profile_stage_name(i).decode() for i in range(RT_PROF_STAGES)]
+    return n, {names[i]: (ms[i], int(ln[i])) for i in range(RT_PROF_STAGES)}
+
+
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
            "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
-           "rt_segment_tile")
+           "rt_segment_tile", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read",
+           "rt_profile_stage_name")
