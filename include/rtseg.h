@@ -171,9 +171,9 @@ int rt_segment_tile(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, in
  * them, only speed does):
  *   "recon_levels"      0..8  threshold levels of the frame-connectivity lower
  *                             bound that starts ReconToNuclei (0 = start from
- *                             the frame marker alone); default 8
+ *                             the frame marker alone); default 3
  *   "recon_round_batch" 1..64 propagation rounds launched between two reads of
- *                             the worklist counter; default 4
+ *                             the worklist counter; default 8
  *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;
  *                             default 64
  * Errors: RT_EINVAL for an unknown name or a value out of range.

@@ -27,6 +27,7 @@ namespace rtseg {
 constexpr int CT = 64;                 // tile edge = wavefront size
 constexpr int MAXLEV = 8;
 constexpr int FRAME_BIT = 1 << 30;     // tags a local root whose component touches the image frame
+constexpr int TOUCH_BIT = 1 << 29;     // tags a local root whose component touches the tile border
 constexpr int LIDX = 0xfff;
 
 __device__ __forceinline__ int ld_agent(const int32_t *p) {
@@ -219,6 +220,24 @@ __device__ __forceinline__ int root_of(const uint64_t *rows, const int *P, int x
     return P[y * CT + run_start_of(rows[y], x)] & LIDX;
 }
 
+// Tags the roots of components that reach the tile border.  Only those can
+// be joined to other tiles; a component that touches the image frame touches
+// the tile border too.  Lane = row.
+__device__ void mark_touch(const Tile &t, const uint64_t *rows, int *P) {
+    const int y = threadIdx.x;
+    const uint64_t m = rows[y];
+    if (y < t.th && m) {
+        if (y == 0 || y == t.th - 1) {
+            for (uint64_t st = run_starts(m); st; st &= st - 1)
+                atomicOr(P + (P[y * CT + __builtin_ctzll(st)] & LIDX), TOUCH_BIT);
+        } else {
+            if (m & 1ull) atomicOr(P + root_of(rows, P, 0, y), TOUCH_BIT);
+            if ((m >> (t.tw - 1)) & 1ull) atomicOr(P + root_of(rows, P, t.tw - 1, y), TOUCH_BIT);
+        }
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // local phase
 // ---------------------------------------------------------------------------
@@ -237,6 +256,7 @@ __global__ __launch_bounds__(CT) void k_ccl_local(CclArgs A) {
         int32_t *ids = A.ids + lev * nid;
         make_rows(A, t, c, level, rows);
         run_forest(rows, P, A.conn);
+        mark_touch(t, rows, P);
         const int y = lane;
         const uint64_t m = rows[y];
         if (A.frame_virtual && tile_on_frame) {
@@ -259,7 +279,7 @@ __global__ __launch_bounds__(CT) void k_ccl_local(CclArgs A) {
             int pv = P[li];
             if ((pv & LIDX) != li) continue;
             int id = gid(A, t, s, y);
-            ids[id] = (pv & FRAME_BIT) ? 0 : id;
+            if (pv & TOUCH_BIT) ids[id] = (pv & FRAME_BIT) ? 0 : id;
             if (A.st_area) {
                 A.st_area[id] = 0;
                 A.st_x0[id] = 0x7fffffff;
@@ -371,15 +391,20 @@ __global__ __launch_bounds__(CT) void k_ccl_merge(CclArgs A) {
 // ---------------------------------------------------------------------------
 // flatten phase + outputs
 // ---------------------------------------------------------------------------
-// Replaces, for every local root r, P[r] by -(global root id) - 1.
+// Replaces, for every local root r, P[r] by -(global root id) - 1.  A
+// component that does not reach the tile border is complete: its root is
+// its global root.  The others look theirs up.
 __device__ void resolve_roots(const CclArgs &A, const Tile &t, const uint64_t *rows, int *P, int32_t *ids) {
+    mark_touch(t, rows, P);
     const int y = threadIdx.x;
     const uint64_t m = rows[y];
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        int s = __builtin_ctzll(st);
-        int li = y * CT + s;
-        if (P[li] != li) continue;
-        P[li] = -gfind(ids, gid(A, t, s, y)) - 1;
+        const int s = __builtin_ctzll(st);
+        const int li = y * CT + s;
+        const int pv = P[li];
+        if ((pv & LIDX) != li) continue;
+        const int id = gid(A, t, s, y);
+        P[li] = -((pv & TOUCH_BIT) ? gfind(ids, id) : id) - 1;
     }
     __syncthreads();
 }

@@ -22,9 +22,10 @@
 //   A   g (h-maxima), then lambda, then CCL roots of the kept pixels
 //   B   recon of g-1 under g, then labels; during one flood level a pixel of
 //       that level holds -(key) - 2 with key = (BFS distance << SH) | label
-// Size classes: crops of <= 1024 and <= 4096 pixels live in LDS (one wave per
-// component, many components per CU); larger crops use a global scratch slice
-// with 64-bit keys.  All three launches read their work lists from device
+// Size classes: crops of at most 32 x 32 and 64 x 64 pixels live in LDS (one
+// wave per component, many components per CU) and run their reconstructions
+// with the crop in registers; larger crops use a global scratch slice with
+// 64-bit keys.  All three launches read their work lists from device
 // counters, so no host round trip is needed.
 #include "rt_internal.h"
 
@@ -33,8 +34,10 @@
 namespace rtseg {
 
 constexpr int WAVE = 64;
-constexpr int CAP_S = 1024;
-constexpr int CAP_M = 4096;
+constexpr int RS_ = 32;                 // small class: crop <= 32 x 32
+constexpr int RM_ = 64;                 // medium class: crop <= 64 x 64
+constexpr int CAP_S = (RS_ + 1) * RS_;  // plane size with the odd row stride
+constexpr int CAP_M = (RM_ + 1) * RM_;
 constexpr int HBINS = 256;
 constexpr int NEGV = INT_MIN;
 constexpr int GINF = 1 << 28;
@@ -199,6 +202,112 @@ __device__ void recon_scans(const Crop<L> &m, V *val, const int32_t *M) {
     }
 }
 
+// ---- reconstruction with the crop in registers (crops of at most R x R) ----
+// Same sweeps as recon_scans, but the wave holds the crop as an R x R block
+// (lane = column, one register per row), takes the previous row's three
+// values from its own register and its neighbours' through DPP wave shifts,
+// and transposes through LDS for the horizontal scans.  Pixels outside the
+// crop or the component are NEGV in both value and mask, so they neither rise
+// nor propagate.
+// R = 32: lanes 32..63 mirror lanes 0..31 (same column, same work), so no
+// lane is ever masked off; a lane at the crop edge takes NEGV for its outer
+// neighbour.
+template <int R>
+__device__ __forceinline__ bool reg_scan(int (&v)[R], const int (&mk)[R], bool first_col, bool last_col) {
+    bool ch = false;
+    int pc = NEGV, pl = NEGV, pr = NEGV;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int mm = max(pc, max(pl, pr));
+        const int nv = max(v[j], min(mm, mk[j]));
+        ch |= nv != v[j];
+        v[j] = nv;
+        pc = nv;
+        const int sl = __builtin_amdgcn_mov_dpp(nv, 0x138, 0xf, 0xf, true);  // lane i <- lane i-1
+        const int sr = __builtin_amdgcn_mov_dpp(nv, 0x130, 0xf, 0xf, true);  // lane i <- lane i+1
+        pl = first_col ? NEGV : sl;
+        pr = last_col ? NEGV : sr;
+    }
+    pc = pl = pr = NEGV;
+#pragma unroll
+    for (int j = R - 1; j >= 0; --j) {
+        const int mm = max(pc, max(pl, pr));
+        const int nv = max(v[j], min(mm, mk[j]));
+        ch |= nv != v[j];
+        v[j] = nv;
+        pc = nv;
+        const int sl = __builtin_amdgcn_mov_dpp(nv, 0x138, 0xf, 0xf, true);
+        const int sr = __builtin_amdgcn_mov_dpp(nv, 0x130, 0xf, 0xf, true);
+        pl = first_col ? NEGV : sl;
+        pr = last_col ? NEGV : sr;
+    }
+    return ch;
+}
+
+// Tv, Tm: two R x (R+1) LDS arrays of the calling kernel.  The crop is first
+// staged there with a strided copy (NEGV outside the crop and outside the
+// component), so the unrolled register loads use constant LDS offsets.
+template <int R, typename L>
+__device__ __forceinline__ void reg_recon(const Crop<L> &m, int32_t *V, const int32_t *M, int *Tv, int *Tm) {
+    const int lane = threadIdx.x;
+    constexpr int TS = R + 1;
+    for (int k = lane; k < R * R; k += WAVE) {
+        const int j = k / R, c = k % R;
+        int vv = NEGV, mm = NEGV;
+        if (c < m.cw && j < m.ch) {
+            const int i = j * m.st + c;
+            vv = V[i];
+            if (m.fl[i] & F_IN) mm = M[i];
+        }
+        Tv[j * TS + c] = vv;
+        Tm[j * TS + c] = mm;
+    }
+    __syncthreads();
+    const int cl = lane & (R - 1);
+    const bool first = cl == 0, last = cl == R - 1;
+    int v[R], mc[R], mr[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        v[j] = Tv[j * TS + cl];
+        mc[j] = Tm[j * TS + cl];
+        mr[j] = Tm[cl * TS + j];
+    }
+    __syncthreads();
+    for (;;) {
+        bool ch = reg_scan<R>(v, mc, first, last);
+#pragma unroll
+        for (int j = 0; j < R; ++j) Tv[j * TS + cl] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = Tv[cl * TS + i];
+        __syncthreads();
+        ch |= reg_scan<R>(v, mr, first, last);
+#pragma unroll
+        for (int i = 0; i < R; ++i) Tv[cl * TS + i] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = Tv[j * TS + cl];
+        __syncthreads();
+        if (!wave_or(ch)) break;
+    }
+    // Tv holds the result (row-major); copy the crop back
+    for (int k = lane; k < R * R; k += WAVE) {
+        const int j = k / R, c = k % R;
+        if (c < m.cw && j < m.ch) V[j * m.st + c] = Tv[j * TS + c];
+    }
+    __syncthreads();
+}
+
+// V <- recon of V under M: registers when the crop fits R x R, else LDS scans
+template <int R, typename L>
+__device__ __forceinline__ void recon_any(const Crop<L> &m, int32_t *V, const int32_t *M, int *Ts) {
+    if constexpr (R > 0) {
+        reg_recon<R, L>(m, V, M, Ts, Ts + R * (R + 1));
+    } else {
+        recon_scans<L, int32_t>(m, V, M);
+    }
+}
+
 // ---- one flood level ---------------------------------------------------------
 // list[b..e) = the unlabelled pixels of level L.  Keys (distance, label) are
 // relaxed from the pixels labelled before L (distance 1) and from pixels of
@@ -257,12 +366,13 @@ __device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e)
 }
 
 // ---- the whole per-component stage ---------------------------------------------
-template <typename L>
-__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist) {
+template <int R, typename L>
+__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int *Ts) {
     const int lane = threadIdx.x;
     const int area = a.st_area[g];
     // ---- load the component
     bool zero = false;
+#pragma unroll 8
     for (int i = lane; i < m.n; i += WAVE) {
         const int c = i % m.st, r = i / m.st;
         bool in = false;
@@ -322,10 +432,13 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     } else {
         for (int i = lane; i < m.n; i += WAVE) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
         __syncthreads();
-        recon_scans<L, int32_t>(m, m.A, m.dq);  // g = h-maxima of Dq
+        recon_any<R, L>(m, m.A, m.dq, Ts);  // g = h-maxima of Dq
         for (int i = lane; i < m.n; i += WAVE) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
         __syncthreads();
-        recon_scans<L, L>(m, m.B, m.A);         // recon of g-1 under g
+        if constexpr (R > 0)
+            recon_any<R, L>(m, (int32_t *)m.B, m.A, Ts);   // recon of g-1 under g
+        else
+            recon_scans<L, L>(m, m.B, m.A);
         for (int i = lane; i < m.n; i += WAVE)
             if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
         __syncthreads();
@@ -360,7 +473,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // ---- lambda = recon of (Dq on seeds) under Dq
     for (int i = lane; i < m.n; i += WAVE) m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
     __syncthreads();
-    recon_scans<L, int32_t>(m, m.A, m.dq);
+    recon_any<R, L>(m, m.A, m.dq, Ts);
     // ---- flood, level by level from the highest lambda
     int lmax = NEGV, lmin = INT_MAX;
     for (int i = lane; i < m.n; i += WAVE)
@@ -521,10 +634,11 @@ __device__ __forceinline__ Crop<int32_t> lds_crop(unsigned char *smem, const Cro
 
 // small class: reads the component list, erases components below the first
 // area threshold, defers crops above CAP_S
-__global__ __launch_bounds__(WAVE) void k_objects_s(ObjArgs a) {
+__global__ __launch_bounds__(WAVE, 2) void k_objects_s(ObjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
+    __shared__ int Ts[2 * RS_ * (RS_ + 1)];
     const int nobj = *a.n_obj;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int g = a.obj_list[o];
@@ -533,11 +647,11 @@ __global__ __launch_bounds__(WAVE) void k_objects_s(ObjArgs a) {
             erase_object(a, g, q);
             continue;
         }
-        if (q.n > CAP_S) {
+        if (q.cw > RS_ || q.ch > RS_) {
             if (threadIdx.x == 0) a.list_m[atomicAdd(a.n_m, 1)] = g;
             continue;
         }
-        process_object<int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist);
+        process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist, Ts);
     }
 }
 
@@ -545,15 +659,16 @@ __global__ __launch_bounds__(WAVE) void k_objects_m(ObjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
+    __shared__ int Ts[2 * RM_ * (RM_ + 1)];
     const int nobj = *a.n_m;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int g = a.list_m[o];
         const CropGeom q = crop_geom(a, g);
-        if (q.n > CAP_M) {
+        if (q.cw > RM_ || q.ch > RM_) {
             if (threadIdx.x == 0) a.big_list[atomicAdd(a.n_big, 1)] = g;
             continue;
         }
-        process_object<int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist);
+        process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist, Ts);
     }
 }
 
@@ -576,7 +691,7 @@ __global__ __launch_bounds__(WAVE) void k_objects_big(ObjArgs a, size_t per_bloc
         m.cx0 = q.cx0;
         m.cy0 = q.cy0;
         m.n = q.n;
-        process_object<int64_t>(a, g, m, &red, hist);
+        process_object<0, int64_t>(a, g, m, &red, hist, nullptr);
     }
 }
 

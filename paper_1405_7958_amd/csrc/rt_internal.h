@@ -41,8 +41,8 @@ struct Arena {
 };
 
 struct Knobs {
-    int recon_levels = 8;        // threshold levels of the connectivity lower bound
-    int recon_round_batch = 4;   // propagation rounds launched between host checks
+    int recon_levels = 3;        // threshold levels of the connectivity lower bound
+    int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
 };
 
