@@ -19,6 +19,9 @@
  *     elements, P >= w; for RGB the pitch is in bytes, >= 3*w) is element
  *     y*P + x.  Label values use the WIDTH, never the pitch:
  *     label = 1 + y*w + x of the component's first pixel in row-major order.
+ *   - Sizes: w*h <= 2^31 - 2; rt_watershed, rt_segment_tile and
+ *     rt_segment_batch, which pack a tile index and a pixel id into 32 bits,
+ *     take w*h <= 2^25 - 2 (up to 5792 x 5792).
  *   - Connectivity 8 = the 3x3 neighbourhood, 4 = the cross.  Only in-tile
  *     pixels exist (no virtual padding beyond the tile edge).
  *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
@@ -40,7 +43,7 @@ extern "C" {
 #endif
 
 #define RT_OK 0
-#define RT_EINVAL (-1)       /* bad argument: null pointer, w/h <= 0, pitch < w, w*h >= 2^31, bad conn/dtype, min > max */
+#define RT_EINVAL (-1)       /* bad argument: null pointer, w/h <= 0, pitch < w, too many pixels, bad conn/dtype, min > max */
 #define RT_ENOMEM (-2)       /* scratch allocation failed */
 #define RT_EDEVICE (-3)      /* HIP runtime error */
 #define RT_EUNSUPPORTED (-4) /* valid request this build does not implement */
@@ -165,6 +168,29 @@ void rt_seg_params_default(rt_seg_params *p);
 int rt_segment_tile(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, int32_t w, int32_t h,
                     const rt_seg_params *params, uint8_t *mask_out, int32_t *labels_out, int64_t out_pitch,
                     int32_t *n_objects_dev, uint8_t *hq_out, void *stream);
+
+/*
+ * The same segmentation stage on a batch of independent tiles of any sizes
+ * (the data-parallel execution of many tiles of an image, Sec. 3.2 and
+ * Sec. 5.1): each tile's outputs equal those of rt_segment_tile on that tile
+ * alone.  The tiles are processed in launch groups of up to 64; each stage of
+ * a group is one kernel launch over all its tiles, so small and ragged tiles
+ * share the device instead of running one after another.  Every descriptor
+ * follows rt_segment_tile's argument rules; outputs of different tiles must
+ * not overlap.  Synchronises `stream` between reconstruction rounds.
+ * Errors: RT_EINVAL (checked for every tile before any work starts).
+ */
+typedef struct {
+    const uint8_t *rgb;      /* device, interleaved RGB */
+    int64_t rgb_pitch_bytes; /* >= 3*w */
+    int32_t w, h;            /* w*h <= 2^25 - 2 */
+    uint8_t *mask_out;       /* device, pitch out_pitch */
+    int32_t *labels_out;     /* device, pitch out_pitch */
+    int64_t out_pitch;       /* elements, >= w */
+    int32_t *n_objects_dev;  /* nullable device int32 */
+    uint8_t *hq_out;         /* nullable device uint8; needs out_pitch == w */
+} rt_tile_desc;
+int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt_seg_params *params, void *stream);
 
 /*
  * Tuning knobs of a context (set by the autotuner; results never depend on

@@ -1,5 +1,11 @@
-// Host side of the C ABI: argument checks, scratch management and the launch
+// Host side of the C ABI: argument checks, scratch layout and the launch
 // sequence of every entry point.  All arithmetic runs in the HIP kernels.
+//
+// The stage kernels are batch-native.  An entry point plans one scratch
+// layout, writes the per-image argument records into pinned host staging
+// memory, uploads them with asynchronous copies and then launches each stage
+// once for the whole batch.  The single-operation entry points are batches of
+// one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "rt_internal.h"
 
@@ -71,6 +78,27 @@ int ensure_stamps(rt_ctx_impl *c, size_t ntiles) {
     return RT_OK;
 }
 
+// Pinned host buffer of at least `bytes` for argument-record uploads.
+int ensure_staging(rt_ctx_impl *c, size_t bytes) {
+    if (bytes > c->staging_cap) {
+        if (c->staging) {
+            RT_HIP(hipDeviceSynchronize());
+            RT_HIP(hipHostFree(c->staging));
+            c->staging = nullptr;
+            c->staging_cap = 0;
+        }
+        size_t cap = std::max<size_t>(bytes, 64 * 1024);
+        if (hipHostMalloc((void **)&c->staging, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->staging = nullptr;
+            set_error("pinned staging allocation failed");
+            return RT_ENOMEM;
+        }
+        c->staging_cap = cap;
+    }
+    return RT_OK;
+}
+
 }  // namespace rtseg
 
 using namespace rtseg;
@@ -79,7 +107,14 @@ namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-bool bad_size(int32_t w, int32_t h) { return w <= 0 || h <= 0 || (int64_t)w * h >= (int64_t(1) << 31) - 1; }
+// Plain operations: w*h < 2^31 - 1.  The per-object stage packs an image index
+// and a pixel id into one int32 (image << 25 | id), so the segmentation and
+// watershed entry points need w*h + 1 < 2^25.
+constexpr int64_t kMaxPixels = (int64_t(1) << 31) - 2;
+constexpr int64_t kMaxObjPixels = (int64_t(1) << 25) - 2;
+bool bad_size(int32_t w, int32_t h, int64_t max_px = kMaxPixels) {
+    return w <= 0 || h <= 0 || (int64_t)w * h > max_px;
+}
 
 #define CHECK(cond, ...)                 \
     do {                                 \
@@ -90,6 +125,21 @@ bool bad_size(int32_t w, int32_t h) { return w <= 0 || h <= 0 || (int64_t)w * h 
     } while (0)
 
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Offsets of a scratch layout, planned before the arena is sized.
+struct Layout {
+    size_t off = 0;
+    size_t add(size_t bytes) {
+        size_t o = al(off);
+        off = o + bytes;
+        return o;
+    }
+};
+
+template <typename T>
+T *at(rt_ctx *c, size_t off) {
+    return reinterpret_cast<T *>(c->arena.base + off);
+}
 
 // host-side validity check of the stain matrix (argument validation only;
 // the table itself is built on the device)
@@ -116,21 +166,42 @@ bool stain_ok(const double r[9]) {
     return std::fabs(det) > 1e-12;
 }
 
+int check_params(const rt_seg_params *p, const char *fn) {
+    CHECK(p->size == sizeof(rt_seg_params), "%s: params.size mismatch", fn);
+    CHECK(p->conn == 8, "%s: foreground connectivity must be 8", fn);
+    CHECK(p->min_area <= p->max_area, "%s: min_area > max_area", fn);
+    CHECK(p->t_fg >= 0 && p->t_fg <= 256, "%s: t_fg out of range", fn);
+    CHECK(std::isfinite(p->hq_scale), "%s: bad hq_scale", fn);
+    CHECK(stain_ok(p->stain_rows), "%s: singular stain matrix", fn);
+    return RT_OK;
+}
+
 int set_dev(rt_ctx *c) { return hip_fail(hipSetDevice(c->device), "hipSetDevice"); }
 
 const char *kStageNames[RT_PROF_STAGES] = {"deconv", "level_bound", "recon", "fill_holes", "ccl", "objects",
                                            "objects_big"};
 
-// Records the boundary event `k` (0..RT_PROF_STAGES) of the current profiled call.
-int prof_mark(rt_ctx *c, int k, hipStream_t s) {
-    if (!c->prof_on) return RT_OK;
+// Boundary event `k` (0..RT_PROF_STAGES) of the current profiled call, or
+// nullptr when profiling is off.
+hipEvent_t prof_event(rt_ctx *c, int k) {
+    if (!c->prof_on) return nullptr;
     size_t idx = c->prof_used + (size_t)k;
     while (c->prof_events.size() <= idx) {
         hipEvent_t ev;
-        RT_HIP(hipEventCreate(&ev));
+        if (hipEventCreate(&ev) != hipSuccess) return nullptr;
         c->prof_events.push_back(ev);
     }
-    RT_HIP(hipEventRecord(c->prof_events[idx], s));
+    return c->prof_events[idx];
+}
+
+int prof_mark(rt_ctx *c, int k, hipStream_t s) {
+    if (!c->prof_on) return RT_OK;
+    hipEvent_t ev = prof_event(c, k);
+    if (!ev) {
+        set_error("profiling: hipEventCreate failed");
+        return RT_EDEVICE;
+    }
+    RT_HIP(hipEventRecord(ev, s));
     if (k == RT_PROF_STAGES) {
         c->prof_used += RT_PROF_STAGES + 1;
         c->prof_calls++;
@@ -138,119 +209,271 @@ int prof_mark(rt_ctx *c, int k, hipStream_t s) {
     return RT_OK;
 }
 
-// Scratch layout of one CCL: ids (w*h+1) per level.
-size_t ccl_ids_bytes(int w, int h, int nlev) { return al(sizeof(int32_t) * ((size_t)w * h + 1) * nlev); }
-
-struct CompScratch {
-    int32_t *ids, *area, *x0, *x1, *y0, *y1, *obj, *list_m, *big;
-    int32_t *n_obj, *n_m, *n_big, *n_kept;
-    void *big_scratch;
-    size_t big_bytes;
-    size_t max_obj;
+// Pinned staging of argument records.  The records of a call sit back to
+// back in the arena from the first put() offset on; the staging buffer holds
+// a congruent host image of that region, uploaded by flush() in one copy.
+// The previous upload may still be reading the buffer, so the first put()
+// waits for it (an upload is a few KB and finishes quickly).
+struct Stager {
+    rt_ctx *c;
+    size_t dev_lo = SIZE_MAX, dev_hi = 0;
+    template <typename T>
+    int put(const std::vector<T> &recs, size_t dev_off) {
+        if (dev_lo == SIZE_MAX) {
+            if (c->staging_pending) {
+                RT_HIP(hipEventSynchronize(c->staging_done));
+                c->staging_pending = false;
+            }
+            dev_lo = dev_off;
+        }
+        const size_t bytes = recs.size() * sizeof(T);
+        if (dev_off < dev_lo || dev_off - dev_lo + bytes > c->staging_cap) {
+            set_error("internal: staging region too small");
+            return RT_ENOMEM;
+        }
+        std::memcpy(c->staging + (dev_off - dev_lo), recs.data(), bytes);
+        dev_hi = std::max(dev_hi, dev_off + bytes);
+        return RT_OK;
+    }
+    int flush(hipStream_t s) {
+        if (dev_lo == SIZE_MAX) return RT_OK;
+        RT_HIP(hipMemcpyAsync(c->arena.base + dev_lo, c->staging, dev_hi - dev_lo, hipMemcpyHostToDevice, s));
+        if (!c->staging_done) RT_HIP(hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming));
+        RT_HIP(hipEventRecord(c->staging_done, s));
+        c->staging_pending = true;
+        return RT_OK;
+    }
 };
 
-// Scratch of BWLabel + the per-object stage: component ids, statistics and
-// lists, plus slices for crops too large for LDS (4 slices of the largest
-// possible crop).
-size_t comp_scratch_bytes(int w, int h) {
-    size_t n1 = (size_t)w * h + 1;
-    size_t max_obj = ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
-    return ccl_ids_bytes(w, h, 1) + 5 * al(sizeof(int32_t) * n1) + 3 * al(sizeof(int32_t) * max_obj) +
-           al(sizeof(int32_t) * 8) + 4 * al(big_object_bytes(w, h));
-}
+size_t max_obj_of(int w, int h) { return ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1); }
 
-int carve_comp(rt_ctx *c, int w, int h, CompScratch &cs) {
-    size_t n1 = (size_t)w * h + 1;
-    cs.max_obj = ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
-    cs.ids = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.area = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.x0 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.x1 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.y0 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.y1 = (int32_t *)c->arena.take(sizeof(int32_t) * n1);
-    cs.obj = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
-    cs.list_m = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
-    cs.big = (int32_t *)c->arena.take(sizeof(int32_t) * cs.max_obj);
-    int32_t *ctr = (int32_t *)c->arena.take(sizeof(int32_t) * 8);
-    cs.big_bytes = 4 * al(big_object_bytes(w, h));
-    cs.big_scratch = c->arena.take(cs.big_bytes);
-    if (!cs.ids || !cs.area || !cs.x0 || !cs.x1 || !cs.y0 || !cs.y1 || !cs.obj || !cs.list_m || !cs.big || !ctr ||
-        !cs.big_scratch) {
-        set_error("scratch arena too small");
-        return RT_ENOMEM;
+// ---------------------------------------------------------------------------
+// the segmentation pipeline over one launch group of tiles
+// ---------------------------------------------------------------------------
+struct TileIn {
+    const uint8_t *rgb;
+    int64_t rgb_pitch;
+    int w, h;
+    uint8_t *mask;
+    int32_t *labels;
+    int64_t out_pitch;
+    int32_t *n_dev;
+    uint8_t *hq_out;
+};
+
+int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipStream_t s) {
+    const int nlev = c->knobs.recon_levels;
+    // ---- scratch layout
+    struct Per {
+        size_t hq, R, F, hist, levels, regA, kept;
+        int64_t dec0;
+        int ccl0, rec0;
+    };
+    std::vector<Per> per(n);
+    Layout L;
+    int64_t dec_total = 0;
+    int ccl_total = 0, rec_total = 0;
+    size_t obj_cap = 0;
+    int big_w = 1, big_h = 1;
+    for (int i = 0; i < n; ++i) {
+        const TileIn &t = tiles[i];
+        const size_t N = (size_t)t.w * t.h;
+        Per &q = per[i];
+        q.hq = t.hq_out ? 0 : L.add(N);
+        q.R = L.add(N);
+        q.F = L.add(N);
+        q.hist = L.add(256 * sizeof(uint32_t));
+        q.levels = L.add(8 * sizeof(int32_t));
+        // level ids, then fill-holes ids, then component ids + 5 statistics
+        q.regA = L.add(sizeof(int32_t) * (N + 1) * (size_t)std::max(nlev, 6));
+        q.kept = L.add(sizeof(int32_t));
+        q.dec0 = dec_total;
+        q.ccl0 = ccl_total;
+        q.rec0 = rec_total;
+        dec_total += ((int64_t)N + DECONV_CHUNK - 1) / DECONV_CHUNK;
+        ccl_total += ccl_tiles(t.w, t.h);
+        rec_total += (int)recon_tiles(t.w, t.h);
+        obj_cap += max_obj_of(t.w, t.h);
+        big_w = std::max(big_w, t.w);
+        big_h = std::max(big_h, t.h);
     }
-    cs.n_obj = ctr;
-    cs.n_m = ctr + 1;
-    cs.n_big = ctr + 2;
-    cs.n_kept = ctr + 3;
-    return RT_OK;
-}
+    const size_t o_obj = L.add(sizeof(int32_t) * obj_cap);
+    const size_t o_m = L.add(sizeof(int32_t) * obj_cap);
+    const size_t o_big = L.add(sizeof(int32_t) * obj_cap);
+    const size_t o_ctr = L.add(16 * sizeof(int32_t));
+    const size_t slice = al(big_object_bytes(big_w, big_h));
+    const int slices = 4;
+    const size_t o_slices = L.add(slice * slices);
+    // argument records, back to back
+    const size_t o_dec = L.add(sizeof(DeconvImg) * n);
+    const size_t o_cl = L.add(sizeof(CclArgs) * n);
+    const size_t o_rec = L.add(sizeof(ReconImg) * n);
+    const size_t o_cf = L.add(sizeof(CclArgs) * n);
+    const size_t o_cc = L.add(sizeof(CclArgs) * n);
+    const size_t o_ob = L.add(sizeof(ObjArgs) * n);
+    const size_t rec_end = L.off;
+    const size_t recon_lists = al(sizeof(int32_t) * (2 * (size_t)rec_total + 4));
+    int e = ensure_arena(c, al(L.off) + recon_lists + 4096);
+    if (e) return e;
+    if ((e = ensure_staging(c, rec_end - o_dec + 4096))) return e;
+    c->arena.off = L.off;  // the reconstruction worklists are carved after the layout
+    // ---- argument records
+    std::vector<DeconvImg> dec(n);
+    std::vector<CclArgs> cl(n), cf(n), cc(n);
+    std::vector<ReconImg> rec(n);
+    std::vector<ObjArgs> ob(n);
+    for (int i = 0; i < n; ++i) {
+        const TileIn &t = tiles[i];
+        const Per &q = per[i];
+        const size_t n1 = (size_t)t.w * t.h + 1;
+        uint8_t *hq = t.hq_out ? t.hq_out : at<uint8_t>(c, q.hq);
+        uint8_t *R = at<uint8_t>(c, q.R);
+        uint8_t *F = at<uint8_t>(c, q.F);
+        int32_t *regA = at<int32_t>(c, q.regA);
+        // with hq_out the caller guarantees out_pitch == w
+        const int64_t pw = t.w;
+        dec[i] = DeconvImg{t.rgb, t.rgb_pitch, hq, pw, nullptr, 0, at<uint32_t>(c, q.hist), t.w, t.h, q.dec0};
 
-// BWLabel (8-connected) with statistics, then the per-object watershed.
-int components_and_watershed(rt_ctx *c, const uint8_t *fg, int64_t pitch_fg, const uint8_t *seeds, int h_seed,
-                             int min_area_pre, int min_area, int max_area, int32_t *labels, uint8_t *mask,
-                             int64_t pitch, int w, int h, CompScratch &cs, int32_t *n_kept_out, hipStream_t s) {
-    int e = launch_fill_i32(cs.n_obj, 0, 4, s);
-    if (e) return e;
-    CclArgs A{};
-    A.pred = CclPred::NonZero;
-    A.out = CclOut::Labels;
-    A.conn = 8;
-    A.frame_virtual = false;
-    A.w = w;
-    A.h = h;
-    A.a = fg;
-    A.pitch_a = pitch_fg;
-    A.ids = cs.ids;
-    A.labels = labels;
-    A.pitch_l = pitch;
-    A.bg_zero_mask = mask;
-    A.pitch_m = pitch;
-    A.st_area = cs.area;
-    A.st_x0 = cs.x0;
-    A.st_x1 = cs.x1;
-    A.st_y0 = cs.y0;
-    A.st_y1 = cs.y1;
-    A.obj_list = cs.obj;
-    A.n_obj = cs.n_obj;
-    e = launch_ccl(A, s);
-    if (e) return e;
-    e = prof_mark(c, 5, s);
-    if (e) return e;
-    c->prof_launches[4] += 4;
-    ObjArgs o{};
-    o.w = w;
-    o.h = h;
-    o.pitch = pitch;
-    o.obj_list = cs.obj;
-    o.n_obj = cs.n_obj;
-    o.st_area = cs.area;
-    o.st_x0 = cs.x0;
-    o.st_x1 = cs.x1;
-    o.st_y0 = cs.y0;
-    o.st_y1 = cs.y1;
-    o.labels = labels;
-    o.mask = mask;
-    o.seeds = seeds;
-    o.h_seed = h_seed;
-    o.min_area_pre = min_area_pre;
-    o.min_area = min_area;
-    o.max_area = max_area;
-    o.n_kept = cs.n_kept;
-    o.list_m = cs.list_m;
-    o.n_m = cs.n_m;
-    o.big_list = cs.big;
-    o.n_big = cs.n_big;
-    o.big_scratch = cs.big_scratch;
-    o.big_scratch_bytes = cs.big_bytes;
-    e = launch_objects(o, c->n_cu, s);
-    if (e) return e;
-    e = prof_mark(c, 6, s);
-    if (e) return e;
-    c->prof_launches[5] += 3;
-    e = prof_mark(c, 7, s);
-    if (e) return e;
-    if (n_kept_out) RT_HIP(hipMemcpyAsync(n_kept_out, cs.n_kept, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        CclArgs A{};
+        A.pred = CclPred::Level;
+        A.out = CclOut::LevelBound;
+        A.conn = 8;
+        A.frame_virtual = true;
+        A.w = t.w;
+        A.h = t.h;
+        A.a = hq;
+        A.pitch_a = pw;
+        A.levels = at<int32_t>(c, q.levels);
+        A.n_levels = nlev;
+        A.ids = regA;
+        A.bound = R;
+        A.pitch_r = pw;
+        A.img = i;
+        A.unit0 = q.ccl0;
+        cl[i] = A;
+
+        rec[i] = ReconImg{t.w, t.h, pw, hq, R, nullptr, (t.w + 61) / 62, (t.h + 61) / 62, q.rec0};
+
+        CclArgs B{};
+        B.pred = CclPred::TophatBg;
+        B.out = CclOut::FillHoles;
+        B.conn = 4;
+        B.frame_virtual = true;
+        B.w = t.w;
+        B.h = t.h;
+        B.a = hq;
+        B.b = R;
+        B.pitch_a = pw;
+        B.pitch_b = pw;
+        B.t = p->t_fg;
+        B.ids = regA;
+        B.fill = F;
+        B.pitch_f = pw;
+        B.img = i;
+        B.unit0 = q.ccl0;
+        cf[i] = B;
+
+        CclArgs C{};
+        C.pred = CclPred::NonZero;
+        C.out = CclOut::Labels;
+        C.conn = 8;
+        C.w = t.w;
+        C.h = t.h;
+        C.a = F;
+        C.pitch_a = pw;
+        C.ids = regA;
+        C.labels = t.labels;
+        C.pitch_l = t.out_pitch;
+        C.bg_zero_mask = t.mask;
+        C.pitch_m = t.out_pitch;
+        C.st_area = regA + n1;
+        C.st_x0 = regA + 2 * n1;
+        C.st_x1 = regA + 3 * n1;
+        C.st_y0 = regA + 4 * n1;
+        C.st_y1 = regA + 5 * n1;
+        C.obj_list = at<int32_t>(c, o_obj);
+        C.n_obj = at<int32_t>(c, o_ctr);
+        C.img = i;
+        C.unit0 = q.ccl0;
+        cc[i] = C;
+
+        ObjArgs O{};
+        O.w = t.w;
+        O.h = t.h;
+        O.pitch = t.out_pitch;
+        O.st_area = C.st_area;
+        O.st_x0 = C.st_x0;
+        O.st_x1 = C.st_x1;
+        O.st_y0 = C.st_y0;
+        O.st_y1 = C.st_y1;
+        O.labels = t.labels;
+        O.mask = t.mask;
+        O.seeds = nullptr;
+        O.h_seed = p->h_seed;
+        O.min_area_pre = p->min_area;
+        O.min_area = p->min_area;
+        O.max_area = p->max_area;
+        O.n_kept = at<int32_t>(c, q.kept);
+        ob[i] = O;
+    }
+    Stager sg{c};
+    if ((e = sg.put(dec, o_dec)) || (e = sg.put(cl, o_cl)) || (e = sg.put(rec, o_rec)) || (e = sg.put(cf, o_cf)) ||
+        (e = sg.put(cc, o_cc)) || (e = sg.put(ob, o_ob)) || (e = sg.flush(s)))
+        return e;
+    int32_t *ctr = at<int32_t>(c, o_ctr);  // n_obj, n_m, n_big
+    if ((e = prof_mark(c, 0, s))) return e;
+    // ---- 1. colour deconvolution and the histogram of Hq
+    StainParams sp;
+    std::memcpy(sp.rows, p->stain_rows, sizeof sp.rows);
+    sp.scale = p->hq_scale;
+    if ((e = launch_deconv_lut(sp, c->lut, s))) return e;
+    for (int i = 0; i < n; ++i) {
+        if ((e = launch_fill_i32(at<int32_t>(c, per[i].hist), 0, 256, s))) return e;
+        if ((e = launch_fill_i32(at<int32_t>(c, per[i].kept), 0, 1, s))) return e;
+    }
+    if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
+    if ((e = launch_deconv(c->lut, p->hq_scale, at<DeconvImg>(c, o_dec), n, dec_total, c->n_cu, s))) return e;
+    c->prof_launches[0] += 3 + 2 * n;
+    if ((e = prof_mark(c, 1, s))) return e;
+    // ---- 2. ReconToNuclei: the frame marker raised by the frame
+    //         connectivity of a few upper level sets, then propagation rounds
+    if (nlev > 0) {
+        for (int i = 0; i < n; ++i)
+            if ((e = launch_select_levels(at<uint32_t>(c, per[i].hist), nlev, at<int32_t>(c, per[i].levels), s)))
+                return e;
+        if ((e = launch_ccl(at<CclArgs>(c, o_cl), n, ccl_total, c->n_cu, s))) return e;
+        c->prof_launches[1] += 3 + n;
+    } else {
+        for (int i = 0; i < n; ++i) {
+            const TileIn &t = tiles[i];
+            if ((e = launch_frame_marker(cl[i].a, t.w, at<uint8_t>(c, per[i].R), t.w, t.w, t.h, s))) return e;
+        }
+        c->prof_launches[1] += n;
+    }
+    if ((e = prof_mark(c, 2, s))) return e;
+    int rounds = 0;
+    if ((e = recon_rounds(c, at<ReconImg>(c, o_rec), n, RT_U8, 8, rec_total, s, &rounds))) return e;
+    c->prof_launches[2] += rounds;
+    if ((e = prof_mark(c, 3, s))) return e;
+    // ---- 3. F0 = [Hq - R >= t]; FillHoles through the 4-connected background
+    if ((e = launch_ccl(at<CclArgs>(c, o_cf), n, ccl_total, c->n_cu, s))) return e;
+    c->prof_launches[3] += 3;
+    if ((e = prof_mark(c, 4, s))) return e;
+    // ---- 4. BWLabel with area and bounding box of every component
+    if ((e = launch_ccl(at<CclArgs>(c, o_cc), n, ccl_total, c->n_cu, s))) return e;
+    c->prof_launches[4] += 3;
+    if ((e = prof_mark(c, 5, s))) return e;
+    // ---- 5-8. AreaThreshold, Pre-Watershed, Watershed, relabel, AreaThreshold
+    ObjLists OL{at<int32_t>(c, o_obj), ctr, at<int32_t>(c, o_m), ctr + 1, at<int32_t>(c, o_big), ctr + 2,
+                at<void>(c, o_slices), slice, slices};
+    if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, prof_event(c, 6)))) return e;
+    c->prof_launches[5] += 2;
+    c->prof_launches[6] += 1;
+    if ((e = prof_mark(c, 7, s))) return e;
+    for (int i = 0; i < n; ++i)
+        if (tiles[i].n_dev)
+            RT_HIP(hipMemcpyAsync(tiles[i].n_dev, at<int32_t>(c, per[i].kept), sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
     return RT_OK;
 }
 
@@ -305,6 +528,8 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->stamps) (void)hipFree(c->stamps);
     if (c->lut) (void)hipFree(c->lut);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->staging) (void)hipHostFree(c->staging);
+    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
     for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
     delete c;
     return RT_OK;
@@ -329,13 +554,20 @@ int rt_deconv(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
+    Layout L;
+    const size_t o_args = L.add(sizeof(DeconvImg));
+    if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, L.off + 4096))) return e;
     StainParams sp;
     std::memcpy(sp.rows, stain, sizeof sp.rows);
     sp.scale = scale;
-    e = launch_deconv_lut(sp, c->lut, nullptr, s);
-    if (e) return e;
-    return launch_deconv(c->lut, scale, rgb, rgb_pitch, w, h, ch, ch_pitch, hq, hq_pitch, nullptr, 0, nullptr,
-                         c->n_cu, s);
+    if ((e = launch_deconv_lut(sp, c->lut, s))) return e;
+    Stager sg{c};
+    if ((e = sg.put(std::vector<DeconvImg>{DeconvImg{rgb, rgb_pitch, hq, hq_pitch, ch, ch_pitch, nullptr, w, h, 0}},
+                    o_args)) ||
+        (e = sg.flush(s)))
+        return e;
+    const int64_t total = ((int64_t)w * h + DECONV_CHUNK - 1) / DECONV_CHUNK;
+    return launch_deconv(c->lut, scale, at<DeconvImg>(c, o_args), 1, total, c->n_cu, s);
 }
 
 int rt_morph_recon(rt_ctx *c, int dtype, const void *marker, const void *mask, void *out, const uint8_t *domain,
@@ -347,13 +579,20 @@ int rt_morph_recon(rt_ctx *c, int dtype, const void *marker, const void *mask, v
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    int64_t ntiles = recon_tiles(w, h);
-    e = ensure_arena(c, al(sizeof(int32_t) * (2 * ntiles + 4)) + 4096);
-    if (e) return e;
-    e = recon_init(dtype, marker, mask, out, domain, w, h, pitch, s);
-    if (e) return e;
-    ReconArgs ra{dtype, conn, w, h, pitch, mask, out, domain};
-    return recon_rounds(c, ra, s);
+    const int64_t ntiles = recon_tiles(w, h);
+    Layout L;
+    const size_t o_args = L.add(sizeof(ReconImg));
+    if ((e = ensure_arena(c, al(L.off) + al(sizeof(int32_t) * (2 * ntiles + 4)) + 4096)) ||
+        (e = ensure_staging(c, L.off + 4096)))
+        return e;
+    c->arena.off = L.off;
+    if ((e = recon_init(dtype, marker, mask, out, w, h, pitch, s))) return e;
+    Stager sg{c};
+    if ((e = sg.put(std::vector<ReconImg>{ReconImg{w, h, pitch, mask, out, domain, (w + 61) / 62, (h + 61) / 62, 0}},
+                    o_args)) ||
+        (e = sg.flush(s)))
+        return e;
+    return recon_rounds(c, at<ReconImg>(c, o_args), 1, dtype, conn, (int)ntiles, s);
 }
 
 int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t h, int64_t pitch, int bg_conn,
@@ -364,8 +603,10 @@ int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    e = ensure_arena(c, ccl_ids_bytes(w, h, 1) + 4096);
-    if (e) return e;
+    Layout L;
+    const size_t o_args = L.add(sizeof(CclArgs));
+    const size_t o_ids = L.add(sizeof(int32_t) * ((size_t)w * h + 1));
+    if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, sizeof(CclArgs) + 4096))) return e;
     CclArgs A{};
     A.pred = CclPred::Zero;
     A.out = CclOut::FillHoles;
@@ -375,10 +616,12 @@ int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t
     A.h = h;
     A.a = in;
     A.pitch_a = pitch;
-    A.ids = (int32_t *)c->arena.take(sizeof(int32_t) * ((size_t)w * h + 1));
+    A.ids = at<int32_t>(c, o_ids);
     A.fill = out;
     A.pitch_f = pitch;
-    return launch_ccl(A, s);
+    Stager sg{c};
+    if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
+    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s);
 }
 
 int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
@@ -389,9 +632,11 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    size_t max_obj = ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
-    e = ensure_arena(c, ccl_ids_bytes(w, h, 1) + al(sizeof(int32_t) * max_obj) + al(64) + 4096);
-    if (e) return e;
+    Layout L;
+    const size_t o_args = L.add(sizeof(CclArgs));
+    const size_t o_ids = L.add(sizeof(int32_t) * ((size_t)w * h + 1));
+    const size_t o_list = L.add(sizeof(int32_t) * (n_out_dev ? max_obj_of(w, h) : 1));
+    if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, sizeof(CclArgs) + 4096))) return e;
     CclArgs A{};
     A.pred = CclPred::NonZero;
     A.out = CclOut::Labels;
@@ -400,16 +645,17 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     A.h = h;
     A.a = mask;
     A.pitch_a = pitch;
-    A.ids = (int32_t *)c->arena.take(sizeof(int32_t) * ((size_t)w * h + 1));
+    A.ids = at<int32_t>(c, o_ids);
     A.labels = labels;
     A.pitch_l = pitch;
     if (n_out_dev) {
-        A.obj_list = (int32_t *)c->arena.take(sizeof(int32_t) * max_obj);
+        A.obj_list = at<int32_t>(c, o_list);
         A.n_obj = n_out_dev;
-        e = launch_fill_i32(n_out_dev, 0, 1, s);
-        if (e) return e;
+        if ((e = launch_fill_i32(n_out_dev, 0, 1, s))) return e;
     }
-    return launch_ccl(A, s);
+    Stager sg{c};
+    if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
+    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s);
 }
 
 int rt_area_filter(rt_ctx *c, const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int32_t w, int32_t h,
@@ -420,8 +666,7 @@ int rt_area_filter(rt_ctx *c, const int32_t *lab_in, int32_t *lab_out, uint8_t *
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    e = ensure_arena(c, al(sizeof(int32_t) * ((size_t)w * h + 1)) + 4096);
-    if (e) return e;
+    if ((e = ensure_arena(c, al(sizeof(int32_t) * ((size_t)w * h + 1)) + 4096))) return e;
     int32_t *area = (int32_t *)c->arena.take(sizeof(int32_t) * ((size_t)w * h + 1));
     return launch_area_filter(lab_in, lab_out, mask_out, w, h, pitch, min_area, max_area, area, s);
 }
@@ -429,153 +674,113 @@ int rt_area_filter(rt_ctx *c, const int32_t *lab_in, int32_t *lab_out, uint8_t *
 int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_seed, int32_t *labels_out,
                  uint8_t *mask_out, int32_t w, int32_t h, int64_t pitch, void *stream) {
     CHECK(c && fg && labels_out && mask_out, "rt_watershed: null argument");
-    CHECK(!bad_size(w, h) && pitch >= w, "rt_watershed: bad size");
+    CHECK(!bad_size(w, h, kMaxObjPixels) && pitch >= w, "rt_watershed: bad size");
     int e = set_dev(c);
     if (e) return e;
     hipStream_t s = as_stream(stream);
-    e = ensure_arena(c, comp_scratch_bytes(w, h) + 8192);
-    if (e) return e;
-    CompScratch cs;
-    e = carve_comp(c, w, h, cs);
-    if (e) return e;
-    const bool prof = c->prof_on;
-    c->prof_on = false;  // stage events belong to rt_segment_tile
-    e = components_and_watershed(c, fg, pitch, seeds, h_seed, 0, 0, -1, labels_out, mask_out, pitch, w, h, cs,
-                                 nullptr, s);
-    c->prof_on = prof;
-    return e;
+    const size_t n1 = (size_t)w * h + 1;
+    const size_t mo = max_obj_of(w, h);
+    Layout L;
+    const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 3);
+    const size_t o_ctr = L.add(16 * sizeof(int32_t));
+    const size_t slice = al(big_object_bytes(w, h));
+    const size_t o_slices = L.add(slice * 4);
+    const size_t o_cc = L.add(sizeof(CclArgs));
+    const size_t o_ob = L.add(sizeof(ObjArgs));
+    if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, L.off - o_cc + 4096))) return e;
+    int32_t *reg = at<int32_t>(c, o_reg);
+    int32_t *ctr = at<int32_t>(c, o_ctr);
+    int32_t *obj = at<int32_t>(c, o_obj);
+    CclArgs A{};
+    A.pred = CclPred::NonZero;
+    A.out = CclOut::Labels;
+    A.conn = 8;
+    A.w = w;
+    A.h = h;
+    A.a = fg;
+    A.pitch_a = pitch;
+    A.ids = reg;
+    A.labels = labels_out;
+    A.pitch_l = pitch;
+    A.bg_zero_mask = mask_out;
+    A.pitch_m = pitch;
+    A.st_area = reg + n1;
+    A.st_x0 = reg + 2 * n1;
+    A.st_x1 = reg + 3 * n1;
+    A.st_y0 = reg + 4 * n1;
+    A.st_y1 = reg + 5 * n1;
+    A.obj_list = obj;
+    A.n_obj = ctr;
+    ObjArgs O{};
+    O.w = w;
+    O.h = h;
+    O.pitch = pitch;
+    O.st_area = A.st_area;
+    O.st_x0 = A.st_x0;
+    O.st_x1 = A.st_x1;
+    O.st_y0 = A.st_y0;
+    O.st_y1 = A.st_y1;
+    O.labels = labels_out;
+    O.mask = mask_out;
+    O.seeds = seeds;
+    O.h_seed = h_seed;
+    O.min_area_pre = 0;
+    O.min_area = 0;
+    O.max_area = -1;
+    O.n_kept = nullptr;
+    Stager sg{c};
+    if ((e = sg.put(std::vector<CclArgs>{A}, o_cc)) || (e = sg.put(std::vector<ObjArgs>{O}, o_ob)) ||
+        (e = sg.flush(s)))
+        return e;
+    if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, at<void>(c, o_slices), slice, 4};
+    return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s);
 }
 
 int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h,
                     const rt_seg_params *p, uint8_t *mask_out, int32_t *labels_out, int64_t out_pitch,
                     int32_t *n_objects_dev, uint8_t *hq_out, void *stream) {
     CHECK(c && rgb && p && mask_out && labels_out, "rt_segment_tile: null argument");
-    CHECK(p->size == sizeof(rt_seg_params), "rt_segment_tile: params.size mismatch");
-    CHECK(!bad_size(w, h), "rt_segment_tile: bad size %dx%d", w, h);
+    int e = check_params(p, "rt_segment_tile");
+    if (e) return e;
+    CHECK(!bad_size(w, h, kMaxObjPixels), "rt_segment_tile: bad size %dx%d", w, h);
     CHECK(rgb_pitch >= 3LL * w && out_pitch >= w, "rt_segment_tile: pitch smaller than width");
-    CHECK(p->conn == 8, "rt_segment_tile: foreground connectivity must be 8");
-    CHECK(p->min_area <= p->max_area, "rt_segment_tile: min_area > max_area");
-    CHECK(stain_ok(p->stain_rows), "rt_segment_tile: singular stain matrix");
     if (hq_out && out_pitch != w) {
         set_error("rt_segment_tile: hq_out needs out_pitch == w");
         return RT_EUNSUPPORTED;
     }
-    int e = set_dev(c);
+    if ((e = set_dev(c))) return e;
+    const TileIn t{rgb, rgb_pitch, w, h, mask_out, labels_out, out_pitch, n_objects_dev, hq_out};
+    return pipeline(c, &t, 1, p, as_stream(stream));
+}
+
+int rt_segment_batch(rt_ctx *c, int32_t n, const rt_tile_desc *tiles, const rt_seg_params *p, void *stream) {
+    CHECK(c && p && (n == 0 || tiles), "rt_segment_batch: null argument");
+    CHECK(n >= 0, "rt_segment_batch: negative tile count");
+    int e = check_params(p, "rt_segment_batch");
     if (e) return e;
-    hipStream_t s = as_stream(stream);
-    const size_t N = (size_t)w * h;
-    const int nlev = c->knobs.recon_levels;
-    const int64_t ntiles = recon_tiles(w, h);
-    size_t need = 3 * al(N) + al(256 * 4) + al(64) +
-                  std::max(ccl_ids_bytes(w, h, std::max(nlev, 1)) + al(sizeof(int32_t) * (2 * ntiles + 4)),
-                           comp_scratch_bytes(w, h)) + 16384;
-    e = ensure_arena(c, need);
-    if (e) return e;
-    uint8_t *hq = hq_out ? hq_out : (uint8_t *)c->arena.take(N);
-    const int64_t hq_pitch = hq_out ? out_pitch : w;
-    uint8_t *R = (uint8_t *)c->arena.take(N);
-    uint8_t *F = (uint8_t *)c->arena.take(N);
-    uint32_t *hist = (uint32_t *)c->arena.take(256 * 4);
-    int32_t *levels = (int32_t *)c->arena.take(64);
-    const size_t mark = c->arena.off;  // the later CCL scratch reuses the level ids
-    int32_t *lev_ids = (int32_t *)c->arena.take(sizeof(int32_t) * (N + 1) * std::max(nlev, 1));
-    if (!hq || !R || !F || !hist || !levels || !lev_ids) {
-        set_error("rt_segment_tile: scratch arena too small");
-        return RT_ENOMEM;
+    for (int i = 0; i < n; ++i) {
+        const rt_tile_desc &d = tiles[i];
+        CHECK(d.rgb && d.mask_out && d.labels_out, "rt_segment_batch: tile %d: null pointer", i);
+        CHECK(!bad_size(d.w, d.h, kMaxObjPixels), "rt_segment_batch: tile %d: bad size %dx%d", i, d.w, d.h);
+        CHECK(d.rgb_pitch_bytes >= 3LL * d.w && d.out_pitch >= d.w, "rt_segment_batch: tile %d: bad pitch", i);
+        if (d.hq_out && d.out_pitch != d.w) {
+            set_error("rt_segment_batch: tile %d: hq_out needs out_pitch == w", i);
+            return RT_EUNSUPPORTED;
+        }
     }
-    // only rt_segment_tile records stage events
-    const bool prof = c->prof_on;
-    struct ProfGuard {
-        rt_ctx *c;
-        bool on;
-        ~ProfGuard() { c->prof_on = on; }
-    } guard{c, prof};
-    e = prof_mark(c, 0, s);
-    if (e) return e;
-    // 1. colour deconvolution + histogram of Hq
-    StainParams sp;
-    std::memcpy(sp.rows, p->stain_rows, sizeof sp.rows);
-    sp.scale = p->hq_scale;
-    e = launch_deconv_lut(sp, c->lut, nullptr, s);
-    if (e) return e;
-    e = launch_fill_i32((int32_t *)hist, 0, 256, s);
-    if (e) return e;
-    e = launch_deconv(c->lut, p->hq_scale, rgb, rgb_pitch, w, h, nullptr, 0, hq, hq_pitch, nullptr, 0, hist,
-                      c->n_cu, s);
-    if (e) return e;
-    e = prof_mark(c, 1, s);
-    if (e) return e;
-    c->prof_launches[0] += 3;
-    // 2. ReconToNuclei: start from the frame marker raised by the frame
-    //    connectivity of a few upper level sets, then propagate
-    if (nlev > 0) {
-        e = launch_select_levels(hist, nlev, levels, s);
-        if (e) return e;
-        CclArgs A{};
-        A.pred = CclPred::Level;
-        A.out = CclOut::LevelBound;
-        A.conn = 8;
-        A.frame_virtual = true;
-        A.w = w;
-        A.h = h;
-        A.a = hq;
-        A.pitch_a = hq_pitch;
-        A.levels = levels;
-        A.n_levels = nlev;
-        A.ids = lev_ids;
-        A.bound = R;
-        A.pitch_r = w;
-        e = launch_ccl(A, s);
-        if (e) return e;
-        c->prof_launches[1] += 4 + nlev;
-    } else {
-        e = launch_frame_marker(hq, hq_pitch, R, w, w, h, s);
-        if (e) return e;
-        c->prof_launches[1] += 1;
+    if ((e = set_dev(c))) return e;
+    std::vector<TileIn> t(n);
+    for (int i = 0; i < n; ++i) {
+        const rt_tile_desc &d = tiles[i];
+        t[i] = TileIn{d.rgb, d.rgb_pitch_bytes, d.w, d.h, d.mask_out, d.labels_out, d.out_pitch, d.n_objects_dev,
+                      d.hq_out};
     }
-    e = prof_mark(c, 2, s);
-    if (e) return e;
-    {
-        ReconArgs ra{RT_U8, 8, w, h, (int64_t)w, hq, R, nullptr};
-        int rounds = 0;
-        e = recon_rounds(c, ra, s, &rounds);
-        if (e) return e;
-        e = prof_mark(c, 3, s);
-        if (e) return e;
-        c->prof_launches[2] += rounds;
-    }
-    // 3. F0 = [Hq - R >= t]; FillHoles through the 4-connected background
-    {
-        c->arena.off = mark;
-        int32_t *ids = (int32_t *)c->arena.take(sizeof(int32_t) * (N + 1));
-        CclArgs A{};
-        A.pred = CclPred::TophatBg;
-        A.out = CclOut::FillHoles;
-        A.conn = 4;
-        A.frame_virtual = true;
-        A.w = w;
-        A.h = h;
-        A.a = hq;
-        A.b = R;
-        A.pitch_a = hq_pitch;
-        A.pitch_b = w;
-        A.t = p->t_fg;
-        A.ids = ids;
-        A.fill = F;
-        A.pitch_f = w;
-        e = launch_ccl(A, s);
-        if (e) return e;
-        e = prof_mark(c, 4, s);
-        if (e) return e;
-        c->prof_launches[3] += 4;
-    }
-    // 4-8. BWLabel + AreaThreshold + Pre-Watershed/Watershed + relabel + AreaThreshold
-    c->arena.off = mark;
-    CompScratch cs;
-    e = carve_comp(c, w, h, cs);
-    if (e) return e;
-    return components_and_watershed(c, F, w, nullptr, p->h_seed, p->min_area, p->min_area, p->max_area, labels_out,
-                                    mask_out, out_pitch, w, h, cs, n_objects_dev, s);
+    for (int b = 0; b < n; b += MAX_BATCH)
+        if ((e = pipeline(c, t.data() + b, std::min(MAX_BATCH, n - b), p, as_stream(stream)))) return e;
+    return RT_OK;
 }
 
 int rt_set_knob(rt_ctx *c, const char *name, int value) {

@@ -119,6 +119,18 @@ struct Tile {
     int tx, ty, x0, y0, tw, th;
 };
 
+__device__ __forceinline__ int img_of(const CclArgs *args, int n, int u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (args[mid].unit0 <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ Tile tile_of(const CclArgs &A, int b) {
     const int ntx = (A.w + CT - 1) / CT;
     Tile t;
@@ -241,11 +253,24 @@ __device__ void mark_touch(const Tile &t, const uint64_t *rows, int *P) {
 // ---------------------------------------------------------------------------
 // local phase
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CT) void k_ccl_local(CclArgs A) {
+__device__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
+
+__global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, int total) {
     __shared__ uint64_t rows[CT];
     __shared__ int P[CT * CT];
-    const Tile t = tile_of(A, blockIdx.x);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        ccl_local_tile(A, u - A.unit0, rows, P);
+    }
+}
+
+__device__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
+    const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
+    if (b == 0 && lane == 0) {  // the virtual node of every level is its own root
+        const int nl = A.pred == CclPred::Level ? A.n_levels : 1;
+        for (int l = 0; l < nl; ++l) A.ids[(int64_t)l * ((int64_t)A.w * A.h + 1)] = 0;
+    }
     Col c;
     load_col(A, t, c);
     const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
@@ -353,8 +378,17 @@ __device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bo
     }
 }
 
-__global__ __launch_bounds__(CT) void k_ccl_merge(CclArgs A) {
-    const Tile t = tile_of(A, blockIdx.x);
+__device__ void ccl_merge_tile(const CclArgs &A, int b);
+
+__global__ __launch_bounds__(CT) void k_ccl_merge(const CclArgs *args, int n, int total) {
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        ccl_merge_tile(A, u - A.unit0);
+    }
+}
+
+__device__ void ccl_merge_tile(const CclArgs &A, int b) {
+    const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
     const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
     const int64_t nid = (int64_t)A.w * A.h + 1;
@@ -415,10 +449,20 @@ __device__ __forceinline__ int global_of(const uint64_t *rows, const int *P, int
     return -P[r] - 1;
 }
 
-__global__ __launch_bounds__(CT) void k_ccl_flatten(CclArgs A) {
+__device__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
+
+__global__ __launch_bounds__(CT) void k_ccl_flatten(const CclArgs *args, int n, int total) {
     __shared__ uint64_t rows[CT];
     __shared__ int P[CT * CT];
-    const Tile t = tile_of(A, blockIdx.x);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        ccl_flatten_tile(A, u - A.unit0, rows, P);
+        __syncthreads();
+    }
+}
+
+__device__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
+    const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
     Col c;
     load_col(A, t, c);
@@ -492,29 +536,21 @@ __global__ __launch_bounds__(CT) void k_ccl_flatten(CclArgs A) {
             atomicMin(A.st_y0 + g, t.y0 + y);
             atomicMax(A.st_y1 + g, t.y0 + y);
         }
-        if (A.obj_list && P[y * CT + s] < 0 && g == gid(A, t, s, y)) A.obj_list[atomicAdd(A.n_obj, 1)] = g;
+        if (A.obj_list && P[y * CT + s] < 0 && g == gid(A, t, s, y))
+            A.obj_list[atomicAdd(A.n_obj, 1)] = (A.img << 25) | g;
     }
 }
 
-int launch_ccl(const CclArgs &a, hipStream_t s) {
-    if (a.pred == CclPred::Level && (a.n_levels < 1 || a.n_levels > MAXLEV)) {
-        set_error("ccl: bad level count %d", a.n_levels);
-        return RT_EINVAL;
-    }
-    const int ntx = (a.w + CT - 1) / CT, nty = (a.h + CT - 1) / CT;
-    const int nlev = a.pred == CclPred::Level ? a.n_levels : 1;
-    const int64_t nid = (int64_t)a.w * a.h + 1;
-    for (int l = 0; l < nlev; ++l) {   // the virtual node id 0 of every level is its own root
-        int e = launch_fill_i32(a.ids + l * nid, 0, 1, s);
-        if (e) return e;
-    }
-    hipLaunchKernelGGL(k_ccl_local, dim3(ntx * nty), dim3(CT), 0, s, a);
+int ccl_tiles(int w, int h) { return ((w + CT - 1) / CT) * ((h + CT - 1) / CT); }
+
+int launch_ccl(const CclArgs *args_dev, int n, int total, int n_cu, hipStream_t s) {
+    if (total <= 0) return RT_OK;
+    const int grid = std::min(total, n_cu * 16);
+    hipLaunchKernelGGL(k_ccl_local, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
-    if (ntx > 1 || nty > 1) {
-        hipLaunchKernelGGL(k_ccl_merge, dim3(ntx * nty), dim3(CT), 0, s, a);
-        RT_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(ntx * nty), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL(k_ccl_merge, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
+    RT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -5,8 +5,7 @@
 // built on the device from the stain rows; each block stages it in LDS, and a
 // pixel costs three LDS reads, two FP64 adds and one multiply-add pair (no
 // contraction).  The kernel is a pure HBM stream: 3 bytes in, 1 byte out
-// (+4 with the optional float c_H).  Each thread owns 16 consecutive pixels =
-// three 16-byte loads and one 16-byte store.
+// (+4 with the optional float c_H).
 #include "rt_internal.h"
 
 namespace rtseg {
@@ -49,120 +48,93 @@ __device__ __forceinline__ double chan(const double *T, uint32_t r, uint32_t g, 
     return __dadd_rn(__dadd_rn(T[r], T[256 + g]), T[512 + b]);
 }
 
-// Fast path: dense images, 16 pixels per thread, grid-stride over groups.
-template <bool WANT_CH, bool WANT_HIST>
-__global__ __launch_bounds__(256) void k_deconv16(const double *__restrict__ lut, double scale,
-                                                   const uint8_t *__restrict__ rgb, int64_t ngroups,
-                                                   uint8_t *__restrict__ hq, float *__restrict__ ch,
-                                                   uint32_t *__restrict__ hist) {
+// Unit = a chunk of 4096 consecutive pixels (row-major) of one image; one
+// 256-thread block handles a chunk, 16 pixels per thread.  Dense images with
+// 16-byte aligned rows take three 16-byte loads and one 16-byte store per
+// thread; others (pitched or unaligned) go pixel by pixel.  The block's
+// histogram of a chunk is added to its image's histogram.
+__device__ __forceinline__ int img_of(const DeconvImg *imgs, int n, int64_t u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].unit0 <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_deconv(const double *__restrict__ lut, double scale,
+                                                 const DeconvImg *__restrict__ imgs, int n, int64_t total) {
     __shared__ double T[768];
     __shared__ uint32_t H[256];
     for (int i = threadIdx.x; i < 768; i += blockDim.x) T[i] = lut[i];
-    if (WANT_HIST) H[threadIdx.x] = 0;
-    __syncthreads();
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(rgb);
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ngroups;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        u32x4 v0 = __builtin_nontemporal_load(src + 3 * g);
-        u32x4 v1 = __builtin_nontemporal_load(src + 3 * g + 1);
-        u32x4 v2 = __builtin_nontemporal_load(src + 3 * g + 2);
-        uint32_t wds[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
-        uint32_t out[4] = {0, 0, 0, 0};
-        float cf[16];
-#pragma unroll
-        for (int p = 0; p < 16; ++p) {
-            int b0 = 3 * p, b1 = 3 * p + 1, b2 = 3 * p + 2;
-            uint32_t r = (wds[b0 >> 2] >> ((b0 & 3) * 8)) & 255u;
-            uint32_t gg = (wds[b1 >> 2] >> ((b1 & 3) * 8)) & 255u;
-            uint32_t b = (wds[b2 >> 2] >> ((b2 & 3) * 8)) & 255u;
-            double c = chan(T, r, gg, b);
-            uint32_t q = quantize(c, scale);
-            out[p >> 2] |= q << ((p & 3) * 8);
-            if (WANT_CH) cf[p] = (float)c;
-            if (WANT_HIST) atomicAdd(&H[q], 1u);
-        }
-        reinterpret_cast<uint4 *>(hq)[g] = make_uint4(out[0], out[1], out[2], out[3]);
-        if (WANT_CH) {
-            float4 *cd = reinterpret_cast<float4 *>(ch) + 4 * g;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) cd[k] = make_float4(cf[4 * k], cf[4 * k + 1], cf[4 * k + 2], cf[4 * k + 3]);
-        }
-    }
-    if (WANT_HIST) {
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        const int ii = img_of(imgs, n, u);
+        const DeconvImg im = imgs[ii];
+        const int64_t npx = (int64_t)im.w * im.h;
+        const int64_t p0 = (u - im.unit0) * DECONV_CHUNK + (int64_t)threadIdx.x * 16;
+        H[threadIdx.x] = 0;
         __syncthreads();
-        if (H[threadIdx.x]) atomicAdd(&hist[threadIdx.x], H[threadIdx.x]);
+        const bool dense = im.rgb_pitch == 3LL * im.w && im.hq_pitch == im.w && (!im.ch || im.ch_pitch == im.w) &&
+                           ((uintptr_t)im.rgb % 16 == 0) && ((uintptr_t)im.hq % 16 == 0) &&
+                           (!im.ch || (uintptr_t)im.ch % 16 == 0);
+        if (dense && p0 + 16 <= npx) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(im.rgb + 3 * p0);
+            u32x4 v0 = __builtin_nontemporal_load(src);
+            u32x4 v1 = __builtin_nontemporal_load(src + 1);
+            u32x4 v2 = __builtin_nontemporal_load(src + 2);
+            uint32_t wds[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
+            uint32_t out[4] = {0, 0, 0, 0};
+            float cf[16];
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int b0 = 3 * p, b1 = 3 * p + 1, b2 = 3 * p + 2;
+                const uint32_t r = (wds[b0 >> 2] >> ((b0 & 3) * 8)) & 255u;
+                const uint32_t gg = (wds[b1 >> 2] >> ((b1 & 3) * 8)) & 255u;
+                const uint32_t b = (wds[b2 >> 2] >> ((b2 & 3) * 8)) & 255u;
+                const double c = chan(T, r, gg, b);
+                const uint32_t q = quantize(c, scale);
+                out[p >> 2] |= q << ((p & 3) * 8);
+                cf[p] = (float)c;
+                if (im.hist) atomicAdd(&H[q], 1u);
+            }
+            *reinterpret_cast<uint4 *>(im.hq + p0) = make_uint4(out[0], out[1], out[2], out[3]);
+            if (im.ch) {
+                float4 *cd = reinterpret_cast<float4 *>(im.ch + p0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) cd[k] = make_float4(cf[4 * k], cf[4 * k + 1], cf[4 * k + 2], cf[4 * k + 3]);
+            }
+        } else {
+            for (int64_t p = p0; p < p0 + 16 && p < npx; ++p) {
+                const int64_t y = p / im.w, x = p - y * im.w;
+                const uint8_t *px = im.rgb + y * im.rgb_pitch + 3 * x;
+                const double c = chan(T, px[0], px[1], px[2]);
+                const uint8_t q = quantize(c, scale);
+                im.hq[y * im.hq_pitch + x] = q;
+                if (im.ch) im.ch[y * im.ch_pitch + x] = (float)c;
+                if (im.hist) atomicAdd(&H[q], 1u);
+            }
+        }
+        __syncthreads();
+        if (im.hist && H[threadIdx.x]) atomicAdd(&im.hist[threadIdx.x], H[threadIdx.x]);
+        __syncthreads();
     }
 }
 
-// Generic path: any pitch/alignment; pixels [first, w*h) in row-major order.
-__global__ __launch_bounds__(256) void k_deconv_generic(const double *__restrict__ lut, double scale,
-                                                         const uint8_t *__restrict__ rgb, int64_t rgb_pitch,
-                                                         int w, int64_t first, int64_t npx,
-                                                         uint8_t *__restrict__ hq, int64_t hq_pitch,
-                                                         float *__restrict__ ch, int64_t ch_pitch,
-                                                         uint32_t *__restrict__ hist) {
-    __shared__ double T[768];
-    __shared__ uint32_t H[256];
-    for (int i = threadIdx.x; i < 768; i += blockDim.x) T[i] = lut[i];
-    H[threadIdx.x] = 0;
-    __syncthreads();
-    for (int64_t i = first + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npx;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        const uint8_t *px = rgb + y * rgb_pitch + 3 * x;
-        double c = chan(T, px[0], px[1], px[2]);
-        uint8_t q = quantize(c, scale);
-        hq[y * hq_pitch + x] = q;
-        if (ch) ch[y * ch_pitch + x] = (float)c;
-        if (hist) atomicAdd(&H[q], 1u);
-    }
-    if (hist) {
-        __syncthreads();
-        if (H[threadIdx.x]) atomicAdd(&hist[threadIdx.x], H[threadIdx.x]);
-    }
-}
-
-int launch_deconv_lut(const StainParams &sp, double *lut, int *, hipStream_t s) {
+int launch_deconv_lut(const StainParams &sp, double *lut, hipStream_t s) {
     hipLaunchKernelGGL(k_deconv_lut, dim3(1), dim3(256), 0, s, sp, lut);
     return hip_fail(hipGetLastError(), "k_deconv_lut");
 }
 
-int launch_deconv(const double *lut, double scale, const uint8_t *rgb, int64_t rgb_pitch, int w, int h,
-                  float *ch, int64_t ch_pitch, uint8_t *hq, int64_t hq_pitch, uint8_t *, int64_t,
-                  uint32_t *hist, int n_cu, hipStream_t s) {
-    int64_t n = (int64_t)w * h;
-    bool dense = rgb_pitch == 3LL * w && hq_pitch == w && (!ch || ch_pitch == w);
-    bool aligned = ((uintptr_t)rgb % 16 == 0) && ((uintptr_t)hq % 16 == 0) && (!ch || (uintptr_t)ch % 16 == 0);
-    int64_t first = 0;
-    if (dense && aligned && n >= 16) {
-        int64_t groups = n / 16;
-        int64_t blocks = (groups + 255) / 256;
-        int grid = (int)(blocks < (int64_t)n_cu * 8 ? blocks : (int64_t)n_cu * 8);
-        if (ch) {
-            if (hist)
-                hipLaunchKernelGGL((k_deconv16<true, true>), dim3(grid), dim3(256), 0, s, lut, scale, rgb, groups, hq, ch, hist);
-            else
-                hipLaunchKernelGGL((k_deconv16<true, false>), dim3(grid), dim3(256), 0, s, lut, scale, rgb, groups, hq, ch, hist);
-        } else {
-            if (hist)
-                hipLaunchKernelGGL((k_deconv16<false, true>), dim3(grid), dim3(256), 0, s, lut, scale, rgb, groups, hq, ch, hist);
-            else
-                hipLaunchKernelGGL((k_deconv16<false, false>), dim3(grid), dim3(256), 0, s, lut, scale, rgb, groups, hq, ch, hist);
-        }
-        int e = hip_fail(hipGetLastError(), "k_deconv16");
-        if (e) return e;
-        first = groups * 16;
-    }
-    if (first < n) {
-        int64_t rem = n - first;
-        int64_t blocks = (rem + 255) / 256;
-        int grid = (int)(blocks < (int64_t)n_cu * 8 ? blocks : (int64_t)n_cu * 8);
-        hipLaunchKernelGGL(k_deconv_generic, dim3(grid), dim3(256), 0, s, lut, scale, rgb, rgb_pitch, w, first, n,
-                           hq, hq_pitch, ch, ch_pitch, hist);
-        return hip_fail(hipGetLastError(), "k_deconv_generic");
-    }
-    return RT_OK;
+int launch_deconv(const double *lut, double scale, const DeconvImg *imgs_dev, int n, int64_t total, int n_cu,
+                  hipStream_t s) {
+    if (total <= 0) return RT_OK;
+    const int grid = (int)std::min<int64_t>(total, (int64_t)n_cu * 8);
+    hipLaunchKernelGGL(k_deconv, dim3(grid), dim3(256), 0, s, lut, scale, imgs_dev, n, total);
+    return hip_fail(hipGetLastError(), "k_deconv");
 }
 
 }  // namespace rtseg

@@ -17,22 +17,6 @@ int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s) {
     return hip_fail(hipGetLastError(), "k_fill_i32");
 }
 
-__global__ void k_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out) {
-    int64_t n = (int64_t)w * h;
-    int c = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t y = i / w, x = i - y * w;
-        c += m[y * pitch + x] == 0;
-    }
-    if (__syncthreads_or(c > 0) && threadIdx.x == 0) atomicAdd(out, 1);
-}
-int launch_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out, hipStream_t s) {
-    int64_t n = (int64_t)w * h;
-    int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_count_zero, dim3(grid), dim3(256), 0, s, m, w, h, pitch, out);
-    return hip_fail(hipGetLastError(), "k_count_zero");
-}
-
 // area filter on labels (root ids); area_scratch has w*h+1 entries
 __global__ void k_area_zero(const int32_t *lab, int w, int h, int64_t pitch, int32_t *area) {
     int64_t n = (int64_t)w * h;

@@ -632,53 +632,61 @@ __device__ __forceinline__ Crop<int32_t> lds_crop(unsigned char *smem, const Cro
     return m;
 }
 
+constexpr int CODE_MASK = (1 << 25) - 1;   // component code = image << 25 | root
+
 // small class: reads the component list, erases components below the first
-// area threshold, defers crops above CAP_S
-__global__ __launch_bounds__(WAVE, 2) void k_objects_s(ObjArgs a) {
+// area threshold, defers crops above 32 x 32
+__global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
     __shared__ int Ts[2 * RS_ * (RS_ + 1)];
-    const int nobj = *a.n_obj;
+    const int nobj = *L.n_obj;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
-        const int g = a.obj_list[o];
+        const int code = L.obj[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
         if (a.st_area[g] < a.min_area_pre) {
             erase_object(a, g, q);
             continue;
         }
         if (q.cw > RS_ || q.ch > RS_) {
-            if (threadIdx.x == 0) a.list_m[atomicAdd(a.n_m, 1)] = g;
+            if (threadIdx.x == 0) L.list_m[atomicAdd(L.n_m, 1)] = code;
             continue;
         }
         process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist, Ts);
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_objects_m(ObjArgs a) {
+__global__ __launch_bounds__(WAVE) void k_objects_m(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
     __shared__ int Ts[2 * RM_ * (RM_ + 1)];
-    const int nobj = *a.n_m;
+    const int nobj = *L.n_m;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
-        const int g = a.list_m[o];
+        const int code = L.list_m[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
         if (q.cw > RM_ || q.ch > RM_) {
-            if (threadIdx.x == 0) a.big_list[atomicAdd(a.n_big, 1)] = g;
+            if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
             continue;
         }
         process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist, Ts);
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_objects_big(ObjArgs a, size_t per_block) {
+__global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, ObjLists L) {
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
-    const int nbig = *a.n_big;
-    char *base = (char *)a.big_scratch + per_block * blockIdx.x;
+    const int nbig = *L.n_big;
+    char *base = (char *)L.big_scratch + L.big_slice_bytes * blockIdx.x;
     for (int o = blockIdx.x; o < nbig; o += gridDim.x) {
-        const int g = a.big_list[o];
+        const int code = L.big[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
         Crop<int64_t> m;
         m.B = (int64_t *)base;
@@ -698,19 +706,18 @@ __global__ __launch_bounds__(WAVE) void k_objects_big(ObjArgs a, size_t per_bloc
 // bytes of global scratch one block needs for the largest crop of a w x h tile
 size_t big_object_bytes(int w, int h) { return (size_t)h * (size_t)(w | 1) * (8 + 4 + 4 + 1) + 256; }
 
-int launch_objects(const ObjArgs &a, int n_cu, hipStream_t s) {
+int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStream_t s, hipEvent_t before_big) {
     const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
-    hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, a);
+    hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 2), dim3(WAVE), lds_m, s, a);
+    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 2), dim3(WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    size_t per = (big_object_bytes(a.w, a.h) + 255) & ~size_t(255);
-    int grid = (int)std::min<size_t>(a.big_scratch_bytes / per, 4);
-    if (grid < 1) {
-        set_error("objects: big-object scratch too small");
+    if (L.big_slices < 1) {
+        set_error("objects: no global scratch slice");
         return RT_ENOMEM;
     }
-    hipLaunchKernelGGL(k_objects_big, dim3(grid), dim3(WAVE), 0, s, a, per);
+    if (before_big) RT_HIP(hipEventRecord(before_big, s));
+    hipLaunchKernelGGL(k_objects_big, dim3(L.big_slices), dim3(WAVE), 0, s, args_dev, L);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

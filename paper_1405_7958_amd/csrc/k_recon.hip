@@ -30,12 +30,9 @@ constexpr int RIN = 62;   // interior edge of a tile (the 64-lane block adds a 1
 constexpr int NEG = INT_MIN;
 
 struct RoundArgs {
-    const void *mask;
-    void *r;
-    const uint8_t *domain;
-    int w, h;
-    int64_t pitch;
-    int ntx, nty;
+    const ReconImg *imgs;  // one record per image (device)
+    int n;
+    int total;           // tiles of the whole batch
     const int32_t *list_in;
     int32_t *list_out;
     int32_t *cnt;        // 3 rotating counters
@@ -46,9 +43,21 @@ struct RoundArgs {
     int max_sweeps;
 };
 
+__device__ __forceinline__ int recon_img_of(const ReconImg *imgs, int n, int u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].unit0 <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 
 template <typename T>
-__device__ __forceinline__ int gval(const RoundArgs &a, const T *p, int x, int y) {
+__device__ __forceinline__ int gval(const ReconImg &a, const T *p, int x, int y) {
     if (x < 0 || y < 0 || x >= a.w || y >= a.h) return NEG;
     int64_t o = (int64_t)y * a.pitch + x;
     if (a.domain && !a.domain[o]) return NEG;
@@ -98,24 +107,35 @@ __device__ __forceinline__ int shl0(int v) {  // lane i <- lane i+1 (lane 63: do
 }
 
 template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
+__device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, int32_t *cnt_out, int (*Ts)[65]);
+
+template <typename T, int CONN>
+__global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
+    __shared__ int Ts[64][65];
     const int lane = threadIdx.x;
-    int32_t *cnt_in = a.cnt + (a.k % 3);
-    int32_t *cnt_out = a.cnt + ((a.k + 1) % 3);
-    int32_t *cnt_clr = a.cnt + ((a.k + 2) % 3);
+    int32_t *cnt_in = ra.cnt + (ra.k % 3);
+    int32_t *cnt_out = ra.cnt + ((ra.k + 1) % 3);
+    int32_t *cnt_clr = ra.cnt + ((ra.k + 2) % 3);
     if (blockIdx.x == 0 && lane == 0) *cnt_clr = 0;
-    const int ntiles = a.ntx * a.nty;
-    const int n_in = a.first ? ntiles : *cnt_in;
-    if ((int)blockIdx.x >= n_in) return;
-    const int tile = a.first ? (int)blockIdx.x : a.list_in[blockIdx.x];
+    const int n_in = ra.first ? ra.total : *cnt_in;
+    for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
+        const int gtile = ra.first ? slot : ra.list_in[slot];
+        const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
+        recon_tile<T, CONN>(ra, a, gtile, cnt_out, Ts);
+        __syncthreads();
+    }
+}
+
+template <typename T, int CONN>
+__device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, int32_t *cnt_out, int (*Ts)[65]) {
+    const int lane = threadIdx.x;
+    const int tile = gtile - a.unit0;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     // the register block covers the interior [x0, x0+62) x [y0, y0+62) and a
     // one-pixel ring: block coordinate (i, j) is image pixel (x0-1+i, y0-1+j)
     const int x0 = tx * RIN, y0 = ty * RIN;
     const T *mask = static_cast<const T *>(a.mask);
     T *rr = static_cast<T *>(a.r);
-
-    __shared__ int Ts[64][65];
 
     int r[64];
     MaskRegs<T> mc, mr;
@@ -147,7 +167,7 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
 
     bool any_change = false;
     bool converged = false;
-    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+    for (int sweep = 0; sweep < ra.max_sweeps; ++sweep) {
         bool ch = false;
         // down and up, lane = column; ring lanes never change and feed their
         // values to the DPP shifts like any other lane
@@ -252,7 +272,7 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
         int nn = 0;
         auto add = [&](int dx, int dy) {
             int nx = tx + dx, ny = ty + dy;
-            if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = ny * a.ntx + nx;
+            if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = a.unit0 + ny * a.ntx + nx;
         };
         if (mT) add(0, -1);
         if (mB) add(0, 1);
@@ -264,9 +284,9 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs a) {
             if ((mB >> 1) & 1ull) add(-1, 1);    // (1, 62)
             if ((mB >> 62) & 1ull) add(1, 1);    // (62, 62)
         }
-        if (!converged) nb[nn++] = tile;  // sweep budget exhausted: continue next round
+        if (!converged) nb[nn++] = gtile;  // sweep budget exhausted: continue next round
         for (int k = 0; k < nn; ++k) {
-            if (atomicExch(a.stamp + nb[k], a.epoch) != a.epoch) a.list_out[atomicAdd(cnt_out, 1)] = nb[k];
+            if (atomicExch(ra.stamp + nb[k], ra.epoch) != ra.epoch) ra.list_out[atomicAdd(cnt_out, 1)] = nb[k];
         }
     }
 }
@@ -283,8 +303,8 @@ __global__ void k_recon_init(const T *marker, const T *mask, T *out, int w, int 
     }
 }
 
-int recon_init(int dtype, const void *marker, const void *mask, void *out, const uint8_t *, int w, int h,
-               int64_t pitch, hipStream_t s) {
+int recon_init(int dtype, const void *marker, const void *mask, void *out, int w, int h, int64_t pitch,
+               hipStream_t s) {
     int64_t n = (int64_t)w * h;
     int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
     if (dtype == RT_U8)
@@ -348,53 +368,52 @@ static void launch_round(const RoundArgs &ra, int grid, hipStream_t s) {
 
 int64_t recon_tiles(int w, int h) { return (int64_t)((w + RIN - 1) / RIN) * ((h + RIN - 1) / RIN); }
 
-int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s, int *rounds_out) {
-    const int ntx = (a.w + RIN - 1) / RIN, nty = (a.h + RIN - 1) / RIN;
-    const int ntiles = ntx * nty;
-    int e = ensure_stamps(c, (size_t)ntiles);
+int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total, hipStream_t s,
+                 int *rounds_out) {
+    int e = ensure_stamps(c, (size_t)total);
     if (e) return e;
     const size_t mark = c->arena.off;
-    int32_t *lists = (int32_t *)c->arena.take(sizeof(int32_t) * (2 * (size_t)ntiles + 4));
+    int32_t *lists = (int32_t *)c->arena.take(sizeof(int32_t) * (2 * (size_t)total + 4));
     if (!lists) {
         c->arena.off = mark;
         set_error("recon: scratch arena too small");
         return RT_ENOMEM;
     }
-    int32_t *cnt = lists + 2 * ntiles;
+    int32_t *cnt = lists + 2 * (size_t)total;
     RoundArgs ra;
-    ra.mask = a.mask;
-    ra.r = a.r;
-    ra.domain = a.domain;
-    ra.w = a.w;
-    ra.h = a.h;
-    ra.pitch = a.pitch;
-    ra.ntx = ntx;
-    ra.nty = nty;
+    ra.imgs = imgs_dev;
+    ra.n = n;
+    ra.total = total;
     ra.cnt = cnt;
     ra.stamp = c->stamps;
     ra.max_sweeps = c->knobs.recon_max_sweeps;
+    const int grid = std::min(total, c->n_cu * 8);
     int k = 0;
     const int batch = c->knobs.recon_round_batch;
-    const int max_rounds = 4 * (ntx + nty) * (int)std::max(1, 4096 / std::max(1, ra.max_sweeps)) + 64;
+    const int max_rounds = 1 << 20;
     e = RT_OK;
     for (;;) {
         for (int b = 0; b < batch; ++b, ++k) {
             ra.k = k;
             ra.first = k == 0;
-            ra.list_in = lists + (k & 1) * ntiles;
-            ra.list_out = lists + ((k + 1) & 1) * ntiles;
+            ra.list_in = lists + (k & 1) * (size_t)total;
+            ra.list_out = lists + ((k + 1) & 1) * (size_t)total;
             if (++c->stamp_epoch == 0) {
-                RT_HIP(hipMemsetAsync(c->stamps, 0, sizeof(uint32_t) * c->stamps_cap, s));
+                int e2 = launch_fill_i32((int32_t *)c->stamps, 0, c->stamps_cap, s);
+                if (e2) return e2;
                 c->stamp_epoch = 1;
             }
             ra.epoch = c->stamp_epoch;
-            if (k == 0) RT_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 3, s));
-            if (a.dtype == RT_U8) {
-                if (a.conn == 8) launch_round<uint8_t, 8>(ra, ntiles, s);
-                else launch_round<uint8_t, 4>(ra, ntiles, s);
+            if (k == 0) {
+                int e2 = launch_fill_i32(cnt, 0, 3, s);
+                if (e2) return e2;
+            }
+            if (dtype == RT_U8) {
+                if (conn == 8) launch_round<uint8_t, 8>(ra, grid, s);
+                else launch_round<uint8_t, 4>(ra, grid, s);
             } else {
-                if (a.conn == 8) launch_round<int32_t, 8>(ra, ntiles, s);
-                else launch_round<int32_t, 4>(ra, ntiles, s);
+                if (conn == 8) launch_round<int32_t, 8>(ra, grid, s);
+                else launch_round<int32_t, 4>(ra, grid, s);
             }
             RT_HIP(hipGetLastError());
         }

@@ -1,4 +1,11 @@
 // Internal declarations shared by the host API and the HIP kernels of librtseg.
+//
+// Every stage kernel is batch-native: it receives a device array with one
+// argument record per image and walks a combined space of work units (pixel
+// chunks, 64 x 64 CCL tiles, 62 x 62 reconstruction tiles, components) with a
+// persistent grid-stride loop.  A record's `unit0` is the first unit of its
+// image; unit u belongs to the image i with unit0[i] <= u < unit0[i+1].  One
+// tile is a batch of one.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -23,8 +30,10 @@ int hip_fail(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::rtseg::hip_fail(_e, #call);          \
     } while (0)
 
+constexpr int MAX_BATCH = 64;   // images per launch (component codes carry a 6-bit image index)
+
 // ---------------------------------------------------------------------------
-// context: device, scratch arena, pinned readback slot
+// context: device, scratch arena, pinned staging
 // ---------------------------------------------------------------------------
 struct Arena {
     char *base = nullptr;
@@ -51,6 +60,10 @@ struct rt_ctx_impl {
     int n_cu = 256;
     Arena arena;
     int32_t *pinned = nullptr;   // small pinned host buffer for counter readback
+    char *staging = nullptr;     // pinned host staging for per-image argument records
+    size_t staging_cap = 0;
+    hipEvent_t staging_done = nullptr;   // recorded after the last upload from `staging`
+    bool staging_pending = false;
     double *lut = nullptr;       // 3 x 256 FP64 deconvolution table (device)
     uint32_t stamp_epoch = 1;    // round stamps for the reconstruction worklists
     uint32_t *stamps = nullptr;  // per-tile stamp array (device)
@@ -66,24 +79,35 @@ struct rt_ctx_impl {
 
 int ensure_arena(rt_ctx_impl *c, size_t bytes);
 int ensure_stamps(rt_ctx_impl *c, size_t ntiles);
+int ensure_staging(rt_ctx_impl *c, size_t bytes);
 
 // ---------------------------------------------------------------------------
-// kernel launchers (all asynchronous on `s`)
+// colour deconvolution
 // ---------------------------------------------------------------------------
 struct StainParams {
     double rows[9];
     double scale;
 };
+struct DeconvImg {
+    const uint8_t *rgb;
+    int64_t rgb_pitch;
+    uint8_t *hq;
+    int64_t hq_pitch;
+    float *ch;                     // nullable
+    int64_t ch_pitch;
+    uint32_t *hist;                // nullable: 256 bins
+    int w, h;
+    int64_t unit0;                 // first 4096-pixel chunk of this image
+};
+constexpr int DECONV_CHUNK = 4096;
+int launch_deconv_lut(const StainParams &sp, double *lut, hipStream_t s);
+int launch_deconv(const double *lut, double scale, const DeconvImg *imgs_dev, int n, int64_t total_units,
+                  int n_cu, hipStream_t s);
 
-// deconvolution
-int launch_deconv_lut(const StainParams &sp, double *lut, int *status_dev, hipStream_t s);
-int launch_deconv(const double *lut, double scale, const uint8_t *rgb, int64_t rgb_pitch, int w, int h,
-                  float *ch, int64_t ch_pitch, uint8_t *hq, int64_t hq_pitch,
-                  uint8_t *frame_init /*nullable: R0 = Hq on frame, 0 inside*/, int64_t fi_pitch,
-                  uint32_t *hist /*nullable: 256 bins*/, int n_cu, hipStream_t s);
-
+// ---------------------------------------------------------------------------
 // connected components (union-find).  `ids` is a scratch int32 array of
-// w*h + 1 entries: id 0 is a virtual node, pixel p has id p + 1.
+// w*h + 1 entries per level: id 0 is a virtual node, pixel p has id p + 1.
+// ---------------------------------------------------------------------------
 enum class CclPred { NonZero, Zero, TophatBg, Level };
 enum class CclOut { Labels, FillHoles, LevelBound };
 struct CclArgs {
@@ -106,24 +130,32 @@ struct CclArgs {
     uint8_t *bg_zero_mask; int64_t pitch_m;  // Labels: write 0 to this mask at background pixels (nullable)
     // per-component statistics (Labels, nullable): indexed by root id
     int32_t *st_area, *st_x0, *st_x1, *st_y0, *st_y1;
-    int32_t *obj_list, *n_obj;     // roots registered here (nullable)
+    int32_t *obj_list, *n_obj;     // components registered here (nullable); entries are image << 25 | root
+    int img;                       // index of this record in its batch
+    int unit0;                     // first 64 x 64 tile of this image
 };
-int launch_ccl(const CclArgs &a, hipStream_t s);
+int ccl_tiles(int w, int h);   // number of 64 x 64 CCL tiles of a w x h image
+int launch_ccl(const CclArgs *args_dev, int n, int total_units, int n_cu, hipStream_t s);
 
+// ---------------------------------------------------------------------------
 // reconstruction rounds
-struct ReconArgs {
-    int dtype;                     // RT_U8 / RT_I32
-    int conn;
+// ---------------------------------------------------------------------------
+struct ReconImg {
     int w, h;
     int64_t pitch;
     const void *mask;
     void *r;                       // in: initial values (already min(marker,mask)); out: result
-    const uint8_t *domain;
+    const uint8_t *domain;         // nullable
+    int ntx, nty;                  // reconstruction tiles per row / column
+    int unit0;                     // first tile of this image in the batch
 };
-int recon_init(int dtype, const void *marker, const void *mask, void *out, const uint8_t *domain, int w, int h,
-               int64_t pitch, hipStream_t s);
-int recon_rounds(rt_ctx_impl *c, const ReconArgs &a, hipStream_t s, int *rounds_out = nullptr);
-int64_t recon_tiles(int w, int h);   // number of reconstruction tiles of a w x h image
+int64_t recon_tiles(int w, int h);   // number of 62 x 62 reconstruction tiles of a w x h image
+int recon_init(int dtype, const void *marker, const void *mask, void *out, int w, int h, int64_t pitch,
+               hipStream_t s);
+// Runs rounds until every image of the batch has converged.  All images share
+// dtype and connectivity.  Synchronises `s` between round batches.
+int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total_tiles,
+                 hipStream_t s, int *rounds_out = nullptr);
 int launch_select_levels(const uint32_t *hist, int n_levels, int32_t *levels, hipStream_t s);
 int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h,
                         hipStream_t s);
@@ -132,12 +164,12 @@ int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t
 int launch_area_filter(const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int w, int h, int64_t pitch,
                        int min_area, int max_area, int32_t *area_scratch, hipStream_t s);
 
+// ---------------------------------------------------------------------------
 // per-object watershed split (runs on the components registered by the CCL)
-struct ObjArgs {
+// ---------------------------------------------------------------------------
+struct ObjArgs {                   // one record per image
     int w, h;
     int64_t pitch;
-    const int32_t *obj_list;
-    const int32_t *n_obj;
     const int32_t *st_area, *st_x0, *st_x1, *st_y0, *st_y1;
     int32_t *labels;               // in: root id of each pixel's component; out: final labels
     uint8_t *mask;                 // out
@@ -145,16 +177,21 @@ struct ObjArgs {
     int h_seed;
     int min_area_pre;              // components below this area are erased
     int min_area, max_area;        // final area filter (max_area < 0: none)
-    int32_t *n_kept;               // nullable: number of kept objects
-    int32_t *list_m, *n_m;         // components deferred to the medium LDS class
-    int32_t *big_list, *n_big;     // components deferred to the global-memory class
-    void *big_scratch;             // global scratch slices for the global-memory class
-    size_t big_scratch_bytes;
+    int32_t *n_kept;               // nullable: number of kept objects of this image
 };
-int launch_objects(const ObjArgs &a, int n_cu, hipStream_t s);
-size_t big_object_bytes(int w, int h);
+struct ObjLists {                  // shared by the batch; entries are image << 25 | root
+    const int32_t *obj, *n_obj;
+    int32_t *list_m, *n_m;         // deferred to the medium LDS class
+    int32_t *big, *n_big;          // deferred to the global-memory class
+    void *big_scratch;             // global scratch slices for the global-memory class
+    size_t big_slice_bytes;
+    int big_slices;
+};
+// `before_big` (nullable) is recorded on `s` before the global-memory class starts.
+int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hipStream_t s,
+                   hipEvent_t before_big = nullptr);
+size_t big_object_bytes(int w, int h);   // one slice for the largest crop of a w x h image
 
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
-int launch_count_zero(const uint8_t *m, int w, int h, int64_t pitch, int32_t *out, hipStream_t s);
 
 }  // namespace rtseg

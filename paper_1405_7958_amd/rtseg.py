@@ -38,6 +38,12 @@ class rt_seg_params(C.Structure):
                 ("h_seed", C.c_int32), ("conn", C.c_int32)]
 
 
+class rt_tile_desc(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("rgb_pitch_bytes", C.c_int64), ("w", C.c_int32), ("h", C.c_int32),
+                ("mask_out", C.c_void_p), ("labels_out", C.c_void_p), ("out_pitch", C.c_int64),
+                ("n_objects_dev", C.c_void_p), ("hq_out", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -60,6 +66,7 @@ def lib():
         L.rt_watershed.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, i64, vp]
         L.rt_seg_params_default.argtypes = [C.POINTER(rt_seg_params)]
         L.rt_segment_tile.argtypes = [vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), vp, vp, i64, vp, vp, vp]
+        L.rt_segment_batch.argtypes = [vp, i32, C.POINTER(rt_tile_desc), C.POINTER(rt_seg_params), vp]
         L.rt_set_knob.argtypes = [vp, C.c_char_p, C.c_int]
         L.rt_get_knob.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
         L.rt_profile_enable.argtypes = [vp, C.c_int]
@@ -250,6 +257,29 @@ def rt_segment_tile(rgb, params=None, want_hq=False, ctx=None, out=None):
     return (mask, lab, n, hq) if want_hq else (mask, lab, n)
 
 
+def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None):
+    """Segments a list of (H_i, W_i, 3) uint8 device tiles in one call.
+
+    Returns a list of (mask, labels, n_objects[, hq]) per tile, as
+    rt_segment_tile would for each tile alone."""
+    ctx = ctx or (default_context(rgbs[0].device.index) if rgbs else default_context())
+    p = params if params is not None else default_params()
+    outs = []
+    descs = (rt_tile_desc * max(1, len(rgbs)))()
+    for i, rgb in enumerate(rgbs):
+        _img(rgb, torch.uint8, f"rgbs[{i}]", 3)
+        h, w = rgb.shape[:2]
+        mask = torch.empty((h, w), dtype=torch.uint8, device=rgb.device)
+        lab = torch.empty((h, w), dtype=torch.int32, device=rgb.device)
+        n = torch.zeros(1, dtype=torch.int32, device=rgb.device)
+        hq = torch.empty((h, w), dtype=torch.uint8, device=rgb.device) if want_hq else None
+        descs[i] = rt_tile_desc(rgb.data_ptr(), rgb.stride(0), w, h, mask.data_ptr(), lab.data_ptr(), w,
+                                n.data_ptr(), hq.data_ptr() if hq is not None else None)
+        outs.append((mask, lab, n, hq) if want_hq else (mask, lab, n))
+    _check(lib().rt_segment_batch(ctx.h, len(rgbs), descs, C.byref(p), _stream()))
+    return outs
+
+
 RT_PROF_STAGES = 7
 KNOBS = ("recon_levels", "recon_round_batch", "recon_max_sweeps")
 
@@ -286,5 +316,5 @@ def rt_profile_read(ctx=None):
 
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
            "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
-           "rt_segment_tile", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read",
+           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read",
            "rt_profile_stage_name")

@@ -22,7 +22,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ["rt_deconv", "rt_morph_recon", "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed",
-              "rt_segment_tile"]:
+              "rt_segment_tile", "rt_segment_batch"]:
         assert n in names
 
 
@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_mirrors_the_boundary():
     from paper_1405_7958_amd import rtseg
     for n in ["rt_deconv", "rt_morph_recon", "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed",
-              "rt_segment_tile"]:
+              "rt_segment_tile", "rt_segment_batch"]:
         assert callable(getattr(rtseg, n))
 
 
@@ -46,3 +46,10 @@ def test_params_struct_layout_matches_header():
     from paper_1405_7958_amd import rtseg
     # uint32 size; 9 doubles; 1 double; 5 int32 (with alignment padding after size)
     assert ctypes.sizeof(rtseg.rt_seg_params) == 8 + 9 * 8 + 8 + 5 * 4 + 4
+
+
+def test_tile_desc_struct_layout_matches_header():
+    from paper_1405_7958_amd import rtseg
+    # ptr, int64, 2 x int32, ptr, ptr, int64, ptr, ptr
+    assert ctypes.sizeof(rtseg.rt_tile_desc) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8
+    assert rtseg.rt_tile_desc.w.offset == 16 and rtseg.rt_tile_desc.mask_out.offset == 24
