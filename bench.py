@@ -5,13 +5,24 @@ nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20,
 seed 0), input resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                  [--no-batch] [--copy-calibration MB]
 
-The roofline object describes the stage that takes the most time, with its
-algorithmic bytes per launch (what the launch must read and write at
-minimum) divided by its average launch time measured with HIP events that
-the library records on its own stream during the timed steps.  The CPU
-baseline is the project's oracle (plain single-threaded C) timed on the same
-tile on this host.
+Roofline: the dominant kernel is the reconstruction round kernel (most of the
+GPU time of a tile).  The library records a pair of HIP events around every
+round launch on its own stream during the timed steps, and counts the 62 x 62
+tiles the rounds process; achieved = tile visits x 11532 algorithmic bytes
+(read Hq and R, write R: 3 bytes per interior pixel) / summed kernel time.
+
+The "batch64" object times rt_segment_batch on the 64-tile batch of uneven
+slide-edge sizes (each side drawn from {512, 1024, 2048, 4096}), with knobs
+picked by the autotuner on that batch.
+
+The CPU baseline is the project's oracle (plain single-threaded C) timed on
+the same 4096 x 4096 tile on this host.
+
+--copy-calibration MB runs one plain device copy of MB MiB before anything
+else, so that a counter run (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) sees a
+kernel of known traffic beside the pipeline kernels.
 """
 from __future__ import annotations
 
@@ -25,10 +36,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TILE_VISIT_BYTES = 62 * 62 * 3
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def batch64(rtseg, synth, torch, args):
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1405_7958_amd import tune
+    d = torch.device("cuda", 0)
+    specs = [synth.spec_uneven(i) for i in range(64)]
+    log("generating the 64-tile uneven batch ...")
+    with ThreadPoolExecutor(8) as ex:
+        rgbs = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
+    ctx = rtseg.Context(0)
+    res = tune.autotune(rgbs, ctx=ctx, reps=3, cache=None)
+    log(f"autotuned knobs {res['knobs']} ({res['ms']:.2f} ms/batch, {res['seconds']} s)")
+    params = rtseg.default_params()
+    for _ in range(2):
+        rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    px = sum(s.w * s.h for s in specs)
+    ms = (t1 - t0) * 1e3 / steps
+    objs = sum(int(o[2].item()) for o in outs)
+    log(f"batch64: {ms:.2f} ms/batch, {64 / (ms * 1e-3):.1f} tiles/s, {px / (ms * 1e-3) / 1e6:.0f} Mpx/s")
+    out = {"tiles": 64, "megapixels": round(px / 1e6, 2), "steps": steps, "ms_per_batch": round(ms, 3),
+           "tiles_per_s": round(64 / (ms * 1e-3), 2), "mpx_per_s": round(px / (ms * 1e-3) / 1e6, 1),
+           "objects": objs, "knobs": res["knobs"],
+           "pipeline_floor_frac": round(8 * px / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
+    ctx.close()
+    return out
 
 
 def main():
@@ -37,7 +83,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_4k.json"))
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         if int(os.environ.get("RANK", "0")) == 0:
@@ -45,14 +93,22 @@ def main():
                   "same single-GPU pipeline on their own tiles; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1405_7958_amd import rtseg, synth
+
+    d = torch.device("cuda", 0)
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=d)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration} MiB done")
+        del src, dst
 
     spec = synth.spec_4k(0)
     log(f"generating {spec.w}x{spec.h} tile ...")
     rgb_np, gt, info = synth.make_tile(spec)
-    d = torch.device("cuda", 0)
     rgb = torch.from_numpy(rgb_np).to(d)
     ctx = rtseg.Context(0)
     h, w = spec.h, spec.w
@@ -66,8 +122,9 @@ def main():
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    rtseg.rt_profile_read(ctx)          # discard
     rtseg.rt_profile_enable(True, ctx)
+    rtseg.rt_profile_read(ctx)          # discard
+    rtseg.rt_profile_recon_rounds(ctx)  # discard
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -76,6 +133,7 @@ def main():
     t1 = time.perf_counter()
     rtseg.rt_profile_enable(False, ctx)
     calls, stages = rtseg.rt_profile_read(ctx)
+    r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
     n_obj = int(n.item())
     ms_step = (t1 - t0) * 1e3 / args.steps
     tiles_s = args.steps / (t1 - t0)
@@ -83,42 +141,34 @@ def main():
 
     N = w * h
     fg = int((lab > 0).sum().item())
-    # algorithmic bytes per launch of each stage (what one launch must move at minimum)
-    alg = {
-        "deconv": 4 * N,                 # RGB in (3 B/px) + Hq out (1 B/px)
-        "level_bound": 2 * N,            # Hq in + lower-bound image out
-        "recon": 3 * N,                  # Hq + R in, R out (one full pass)
-        "fill_holes": 3 * N,             # Hq + R in, F out
-        "ccl": 5 * N,                    # F in, int32 labels out
-        "objects": 9 * fg,               # labels in, labels + mask out, on foreground pixels
-        "objects_big": 0,
-    }
     per_stage = {}
     for k, (ms_tot, launches) in stages.items():
         per_call = ms_tot / max(1, calls)
         per_stage[k] = {"ms_per_tile": round(per_call, 4), "launches_per_tile": round(launches / max(1, calls), 2)}
         log(f"  {k:12s} {per_call:8.4f} ms/tile  launches/tile {launches / max(1, calls):6.2f}")
-    dom = max((k for k in stages if alg.get(k, 0) > 0), key=lambda k: stages[k][0])
-    ms_tot, launches = stages[dom]
-    # one launch processes the whole tile for every stage except recon, whose
-    # launches are propagation rounds over active tiles only: count a whole
-    # tile pass for the stage
-    if dom == "recon":
-        t_launch = ms_tot / max(1, calls)
-    else:
-        t_launch = ms_tot / max(1, launches) * (launches / max(1, calls)) if launches else ms_tot / max(1, calls)
-    achieved = alg[dom] / (t_launch * 1e-3) / 1e9
+    # dominant kernel: the reconstruction round kernel
+    ms_launch = r_ms / max(1, r_launches)
+    bytes_launch = TILE_VISIT_BYTES * r_visits / max(1, r_launches)
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9 if r_launches else 0.0
+    log(f"recon round kernel: {r_launches} launches, {ms_launch * 1e3:.1f} us/launch, "
+        f"{r_visits / max(1, r_launches):.0f} tile visits/launch, {achieved:.1f} GB/s")
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("stage") == dom:
-                traffic = tj.get("bytes_per_launch")
+            traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "stage": dom,
-            "alg_bytes_per_launch": alg[dom], "ms_per_launch": round(t_launch, 4)}
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "kernel": "k_recon_round<unsigned char, 8>",
+            "alg_bytes_per_launch": round(bytes_launch), "us_per_launch": round(ms_launch * 1e3, 2),
+            "launches_per_tile": round(r_launches / max(1, calls), 2),
+            "tile_visits_per_launch": round(r_visits / max(1, r_launches), 1)}
+
+    batch = None
+    if not args.no_batch:
+        batch = batch64(rtseg, synth, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -152,6 +202,7 @@ def main():
                    "pipeline_floor_frac": round(8 * N * tiles_s / (HBM_PEAK_GBS * 1e9), 5),
                    "stages": per_stage},
         "roofline": roof,
+        "batch64": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

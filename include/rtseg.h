@@ -202,6 +202,17 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *                             the worklist counter; default 8
  *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;
  *                             default 64
+ *   "graph"             0|1   rt_segment_tile / rt_segment_batch replay the
+ *                             launch sequence from captured HIP graphs (cached
+ *                             per tile-size list, up to 4); default 0.  The
+ *                             first graph holds "graph_rounds" reconstruction
+ *                             rounds; if tiles are still queued after them the
+ *                             remaining rounds run as ordinary launches before
+ *                             the second graph.  Ignored while stage timing is on.
+ *   "graph_rounds"      1..4096; default 24
+ * Read-only (rt_get_knob): "graph_captures", "graph_replays" (counts since
+ * the context was created), "last_rounds" (reconstruction rounds of the last
+ * segmentation call).
  * Errors: RT_EINVAL for an unknown name or a value out of range.
  */
 int rt_set_knob(rt_ctx *ctx, const char *name, int value);
@@ -227,6 +238,14 @@ int rt_get_knob(rt_ctx *ctx, const char *name, int *value);
 int rt_profile_enable(rt_ctx *ctx, int enable);
 int rt_profile_read(rt_ctx *ctx, double *ms, int64_t *launches, int max_stages);
 const char *rt_profile_stage_name(int stage);
+/*
+ * Per-launch timing of the reconstruction round kernel, recorded while stage
+ * timing is enabled: a pair of HIP events around every round launch on the
+ * call's stream.  Returns the summed kernel milliseconds, the number of round
+ * launches and the number of 62 x 62 tile visits (tiles processed, over all
+ * rounds) since the last read, synchronises the events and clears the record.
+ */
+int rt_profile_recon_rounds(rt_ctx *ctx, double *kernel_ms, int64_t *launches, int64_t *tile_visits);
 
 #ifdef __cplusplus
 }

@@ -74,7 +74,6 @@ int ensure_stamps(rt_ctx_impl *c, size_t ntiles) {
     }
     RT_HIP(hipMemset(c->stamps, 0, cap * sizeof(uint32_t)));
     c->stamps_cap = cap;
-    c->stamp_epoch = 1;
     return RT_OK;
 }
 
@@ -261,8 +260,96 @@ struct TileIn {
     uint8_t *hq_out;
 };
 
+// Device-side plan of one launch group: arena offsets of the argument arrays
+// and the shared lists, plus the unit counts of each batch kernel.
+struct Plan {
+    int n = 0, nlev = 0;
+    size_t o_dec = 0, o_cl = 0, o_rec = 0, o_cf = 0, o_cc = 0, o_ob = 0, o_aux = 0;
+    size_t o_obj = 0, o_m = 0, o_big = 0, o_ctr = 0, o_slices = 0, slice = 0;
+    int slices = 4;
+    int64_t dec_total = 0;
+    int ccl_total = 0, rec_total = 0;
+    ReconRun run;
+};
+
+constexpr int kSharedCounters = 16;
+
+// Stages 1-2a: deconvolution + histogram, level choice and the frame
+// connectivity bound (or the bare frame marker).
+int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s, bool prof) {
+    int e;
+    if (prof && (e = prof_mark(c, 0, s))) return e;
+    if ((e = launch_deconv_lut(sp, c->lut, s))) return e;
+    if ((e = launch_batch_begin(at<BatchAux>(c, P.o_aux), P.n, at<int32_t>(c, P.o_ctr), kSharedCounters, s)))
+        return e;
+    if ((e = launch_deconv(c->lut, sp.scale, at<DeconvImg>(c, P.o_dec), P.n, P.dec_total, c->n_cu, s))) return e;
+    c->prof_launches[0] += 3;
+    if (prof && (e = prof_mark(c, 1, s))) return e;
+    if (P.nlev > 0) {
+        if ((e = launch_batch_levels(at<BatchAux>(c, P.o_aux), P.n, P.nlev, s))) return e;
+        if ((e = launch_ccl(at<CclArgs>(c, P.o_cl), P.n, P.ccl_total, c->n_cu, s))) return e;
+        c->prof_launches[1] += 4;
+    } else {
+        if ((e = launch_batch_frame_marker(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
+        c->prof_launches[1] += 1;
+    }
+    if (prof && (e = prof_mark(c, 2, s))) return e;
+    return RT_OK;
+}
+
+// Stages 3-8: FillHoles, BWLabel with statistics, the per-object stage and
+// the object counts.
+int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
+    int e;
+    if (prof && (e = prof_mark(c, 3, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, P.o_cf), P.n, P.ccl_total, c->n_cu, s))) return e;
+    c->prof_launches[3] += 3;
+    if (prof && (e = prof_mark(c, 4, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, P.o_cc), P.n, P.ccl_total, c->n_cu, s))) return e;
+    c->prof_launches[4] += 3;
+    if (prof && (e = prof_mark(c, 5, s))) return e;
+    int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big
+    ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_big), ctr + 2,
+                at<void>(c, P.o_slices), P.slice, P.slices};
+    if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr))) return e;
+    if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
+    c->prof_launches[5] += 2;
+    c->prof_launches[6] += 2;
+    if (prof && (e = prof_mark(c, 7, s))) return e;
+    return RT_OK;
+}
+
+void destroy_graph(GraphPair &g) {
+    if (g.a) (void)hipGraphExecDestroy(g.a);
+    if (g.b) (void)hipGraphExecDestroy(g.b);
+    g.a = g.b = nullptr;
+    g.key.clear();
+}
+
+// Captures fn(stream) on the context's private stream into an executable graph.
+template <typename F>
+int capture(rt_ctx *c, F fn, hipGraphExec_t *out) {
+    if (!c->cap_stream) RT_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    RT_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int e = fn(c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamEndCapture(c->cap_stream, &g);
+    if (e) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+    he = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return hip_fail(he, "hipGraphInstantiate");
+}
+
 int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipStream_t s) {
-    const int nlev = c->knobs.recon_levels;
+    Plan P;
+    P.n = n;
+    P.nlev = c->knobs.recon_levels;
+    const bool use_graph = c->knobs.graph && !c->prof_on;
+    const int budget = c->knobs.graph_rounds;
     // ---- scratch layout
     struct Per {
         size_t hq, R, F, hist, levels, regA, kept;
@@ -271,8 +358,6 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     };
     std::vector<Per> per(n);
     Layout L;
-    int64_t dec_total = 0;
-    int ccl_total = 0, rec_total = 0;
     size_t obj_cap = 0;
     int big_w = 1, big_h = 1;
     for (int i = 0; i < n; ++i) {
@@ -285,43 +370,45 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         q.hist = L.add(256 * sizeof(uint32_t));
         q.levels = L.add(8 * sizeof(int32_t));
         // level ids, then fill-holes ids, then component ids + 5 statistics
-        q.regA = L.add(sizeof(int32_t) * (N + 1) * (size_t)std::max(nlev, 6));
+        q.regA = L.add(sizeof(int32_t) * (N + 1) * (size_t)std::max(P.nlev, 6));
         q.kept = L.add(sizeof(int32_t));
-        q.dec0 = dec_total;
-        q.ccl0 = ccl_total;
-        q.rec0 = rec_total;
-        dec_total += ((int64_t)N + DECONV_CHUNK - 1) / DECONV_CHUNK;
-        ccl_total += ccl_tiles(t.w, t.h);
-        rec_total += (int)recon_tiles(t.w, t.h);
+        q.dec0 = P.dec_total;
+        q.ccl0 = P.ccl_total;
+        q.rec0 = P.rec_total;
+        P.dec_total += ((int64_t)N + DECONV_CHUNK - 1) / DECONV_CHUNK;
+        P.ccl_total += ccl_tiles(t.w, t.h);
+        P.rec_total += (int)recon_tiles(t.w, t.h);
         obj_cap += max_obj_of(t.w, t.h);
         big_w = std::max(big_w, t.w);
         big_h = std::max(big_h, t.h);
     }
-    const size_t o_obj = L.add(sizeof(int32_t) * obj_cap);
-    const size_t o_m = L.add(sizeof(int32_t) * obj_cap);
-    const size_t o_big = L.add(sizeof(int32_t) * obj_cap);
-    const size_t o_ctr = L.add(16 * sizeof(int32_t));
-    const size_t slice = al(big_object_bytes(big_w, big_h));
-    const int slices = 4;
-    const size_t o_slices = L.add(slice * slices);
+    P.o_obj = L.add(sizeof(int32_t) * obj_cap);
+    P.o_m = L.add(sizeof(int32_t) * obj_cap);
+    P.o_big = L.add(sizeof(int32_t) * obj_cap);
+    P.o_ctr = L.add(kSharedCounters * sizeof(int32_t));
+    P.slice = al(big_object_bytes(big_w, big_h));
+    P.o_slices = L.add(P.slice * P.slices);
     // argument records, back to back
-    const size_t o_dec = L.add(sizeof(DeconvImg) * n);
-    const size_t o_cl = L.add(sizeof(CclArgs) * n);
-    const size_t o_rec = L.add(sizeof(ReconImg) * n);
-    const size_t o_cf = L.add(sizeof(CclArgs) * n);
-    const size_t o_cc = L.add(sizeof(CclArgs) * n);
-    const size_t o_ob = L.add(sizeof(ObjArgs) * n);
+    P.o_dec = L.add(sizeof(DeconvImg) * n);
+    P.o_cl = L.add(sizeof(CclArgs) * n);
+    P.o_rec = L.add(sizeof(ReconImg) * n);
+    P.o_cf = L.add(sizeof(CclArgs) * n);
+    P.o_cc = L.add(sizeof(CclArgs) * n);
+    P.o_ob = L.add(sizeof(ObjArgs) * n);
+    P.o_aux = L.add(sizeof(BatchAux) * n);
     const size_t rec_end = L.off;
-    const size_t recon_lists = al(sizeof(int32_t) * (2 * (size_t)rec_total + 4));
+    const size_t recon_lists = al(sizeof(int32_t) * (2 * (size_t)P.rec_total + 4));
     int e = ensure_arena(c, al(L.off) + recon_lists + 4096);
     if (e) return e;
-    if ((e = ensure_staging(c, rec_end - o_dec + 4096))) return e;
-    c->arena.off = L.off;  // the reconstruction worklists are carved after the layout
+    if ((e = ensure_staging(c, rec_end - P.o_dec + 4096))) return e;
+    c->arena.off = L.off;
+    if ((e = recon_prepare(c, P.rec_total, P.run))) return e;
     // ---- argument records
     std::vector<DeconvImg> dec(n);
     std::vector<CclArgs> cl(n), cf(n), cc(n);
     std::vector<ReconImg> rec(n);
     std::vector<ObjArgs> ob(n);
+    std::vector<BatchAux> aux(n);
     for (int i = 0; i < n; ++i) {
         const TileIn &t = tiles[i];
         const Per &q = per[i];
@@ -333,6 +420,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         // with hq_out the caller guarantees out_pitch == w
         const int64_t pw = t.w;
         dec[i] = DeconvImg{t.rgb, t.rgb_pitch, hq, pw, nullptr, 0, at<uint32_t>(c, q.hist), t.w, t.h, q.dec0};
+        aux[i] = BatchAux{at<uint32_t>(c, q.hist), at<int32_t>(c, q.levels), at<int32_t>(c, q.kept), t.n_dev, hq, R,
+                          t.w, t.h};
 
         CclArgs A{};
         A.pred = CclPred::Level;
@@ -344,7 +433,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         A.a = hq;
         A.pitch_a = pw;
         A.levels = at<int32_t>(c, q.levels);
-        A.n_levels = nlev;
+        A.n_levels = P.nlev;
         A.ids = regA;
         A.bound = R;
         A.pitch_r = pw;
@@ -391,8 +480,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         C.st_x1 = regA + 3 * n1;
         C.st_y0 = regA + 4 * n1;
         C.st_y1 = regA + 5 * n1;
-        C.obj_list = at<int32_t>(c, o_obj);
-        C.n_obj = at<int32_t>(c, o_ctr);
+        C.obj_list = at<int32_t>(c, P.o_obj);
+        C.n_obj = at<int32_t>(c, P.o_ctr);
         C.img = i;
         C.unit0 = q.ccl0;
         cc[i] = C;
@@ -417,63 +506,72 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         ob[i] = O;
     }
     Stager sg{c};
-    if ((e = sg.put(dec, o_dec)) || (e = sg.put(cl, o_cl)) || (e = sg.put(rec, o_rec)) || (e = sg.put(cf, o_cf)) ||
-        (e = sg.put(cc, o_cc)) || (e = sg.put(ob, o_ob)) || (e = sg.flush(s)))
+    if ((e = sg.put(dec, P.o_dec)) || (e = sg.put(cl, P.o_cl)) || (e = sg.put(rec, P.o_rec)) ||
+        (e = sg.put(cf, P.o_cf)) || (e = sg.put(cc, P.o_cc)) || (e = sg.put(ob, P.o_ob)) ||
+        (e = sg.put(aux, P.o_aux)) || (e = sg.flush(s)))
         return e;
-    int32_t *ctr = at<int32_t>(c, o_ctr);  // n_obj, n_m, n_big
-    if ((e = prof_mark(c, 0, s))) return e;
-    // ---- 1. colour deconvolution and the histogram of Hq
     StainParams sp;
     std::memcpy(sp.rows, p->stain_rows, sizeof sp.rows);
     sp.scale = p->hq_scale;
-    if ((e = launch_deconv_lut(sp, c->lut, s))) return e;
-    for (int i = 0; i < n; ++i) {
-        if ((e = launch_fill_i32(at<int32_t>(c, per[i].hist), 0, 256, s))) return e;
-        if ((e = launch_fill_i32(at<int32_t>(c, per[i].kept), 0, 1, s))) return e;
-    }
-    if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
-    if ((e = launch_deconv(c->lut, p->hq_scale, at<DeconvImg>(c, o_dec), n, dec_total, c->n_cu, s))) return e;
-    c->prof_launches[0] += 3 + 2 * n;
-    if ((e = prof_mark(c, 1, s))) return e;
-    // ---- 2. ReconToNuclei: the frame marker raised by the frame
-    //         connectivity of a few upper level sets, then propagation rounds
-    if (nlev > 0) {
-        for (int i = 0; i < n; ++i)
-            if ((e = launch_select_levels(at<uint32_t>(c, per[i].hist), nlev, at<int32_t>(c, per[i].levels), s)))
-                return e;
-        if ((e = launch_ccl(at<CclArgs>(c, o_cl), n, ccl_total, c->n_cu, s))) return e;
-        c->prof_launches[1] += 3 + n;
-    } else {
-        for (int i = 0; i < n; ++i) {
-            const TileIn &t = tiles[i];
-            if ((e = launch_frame_marker(cl[i].a, t.w, at<uint8_t>(c, per[i].R), t.w, t.w, t.h, s))) return e;
-        }
-        c->prof_launches[1] += n;
-    }
-    if ((e = prof_mark(c, 2, s))) return e;
+    const ReconImg *rimgs = at<ReconImg>(c, P.o_rec);
     int rounds = 0;
-    if ((e = recon_rounds(c, at<ReconImg>(c, o_rec), n, RT_U8, 8, rec_total, s, &rounds))) return e;
-    c->prof_launches[2] += rounds;
-    if ((e = prof_mark(c, 3, s))) return e;
-    // ---- 3. F0 = [Hq - R >= t]; FillHoles through the 4-connected background
-    if ((e = launch_ccl(at<CclArgs>(c, o_cf), n, ccl_total, c->n_cu, s))) return e;
-    c->prof_launches[3] += 3;
-    if ((e = prof_mark(c, 4, s))) return e;
-    // ---- 4. BWLabel with area and bounding box of every component
-    if ((e = launch_ccl(at<CclArgs>(c, o_cc), n, ccl_total, c->n_cu, s))) return e;
-    c->prof_launches[4] += 3;
-    if ((e = prof_mark(c, 5, s))) return e;
-    // ---- 5-8. AreaThreshold, Pre-Watershed, Watershed, relabel, AreaThreshold
-    ObjLists OL{at<int32_t>(c, o_obj), ctr, at<int32_t>(c, o_m), ctr + 1, at<int32_t>(c, o_big), ctr + 2,
-                at<void>(c, o_slices), slice, slices};
-    if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, prof_event(c, 6)))) return e;
-    c->prof_launches[5] += 2;
-    c->prof_launches[6] += 1;
-    if ((e = prof_mark(c, 7, s))) return e;
-    for (int i = 0; i < n; ++i)
-        if (tiles[i].n_dev)
-            RT_HIP(hipMemcpyAsync(tiles[i].n_dev, at<int32_t>(c, per[i].kept), sizeof(int32_t),
-                                  hipMemcpyDeviceToDevice, s));
+    if (!use_graph) {
+        if ((e = enqueue_front(c, P, sp, s, true))) return e;
+        if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &rounds))) return e;
+        c->prof_launches[2] += rounds;
+        c->last_rounds = rounds;
+        return enqueue_back(c, P, s, true);
+    }
+    // ---- graph path: everything that fixes a launch parameter goes into the key
+    std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu,
+                                (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
+                                (int64_t)(intptr_t)c->lut};
+    int64_t bits;
+    for (int k = 0; k < 9; ++k) {
+        std::memcpy(&bits, &sp.rows[k], 8);
+        key.push_back(bits);
+    }
+    std::memcpy(&bits, &sp.scale, 8);
+    key.push_back(bits);
+    for (int i = 0; i < n; ++i) key.push_back(((int64_t)tiles[i].w << 32) | ((int64_t)tiles[i].h << 1) | (tiles[i].hq_out != nullptr));
+    GraphPair *g = nullptr;
+    for (GraphPair &x : c->graphs)
+        if (x.key == key) g = &x;
+    if (!g) {
+        const size_t kMaxGraphs = 4;
+        if (c->graphs.size() < kMaxGraphs) {
+            c->graphs.emplace_back();
+            g = &c->graphs.back();
+        } else {
+            g = &c->graphs[0];
+            for (GraphPair &x : c->graphs)
+                if (x.last_use < g->last_use) g = &x;
+            destroy_graph(*g);
+        }
+        // the captured kernels read the arena; nothing of an earlier call may still run
+        RT_HIP(hipStreamSynchronize(s));
+        e = capture(
+            c,
+            [&](hipStream_t cs) {
+                int e2 = enqueue_front(c, P, sp, cs, false);
+                if (!e2) e2 = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, budget, cs);
+                return e2;
+            },
+            &g->a);
+        if (!e) e = capture(c, [&](hipStream_t cs) { return enqueue_back(c, P, cs, false); }, &g->b);
+        if (e) {
+            destroy_graph(*g);
+            return e;
+        }
+        g->key = key;
+        c->graph_captures++;
+    }
+    g->last_use = ++c->graph_clock;
+    RT_HIP(hipGraphLaunch(g->a, s));
+    if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, budget, s, &rounds))) return e;
+    c->last_rounds = rounds;
+    RT_HIP(hipGraphLaunch(g->b, s));
+    c->graph_replays++;
     return RT_OK;
 }
 
@@ -530,7 +628,11 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staging) (void)hipHostFree(c->staging);
     if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    for (GraphPair &g : c->graphs) destroy_graph(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : c->round_events) (void)hipEventDestroy(ev);
+    if (c->prof_visits) (void)hipFree(c->prof_visits);
     delete c;
     return RT_OK;
 }
@@ -795,6 +897,12 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     } else if (n == "recon_max_sweeps") {
         CHECK(value >= 1 && value <= 1024, "rt_set_knob: recon_max_sweeps must be 1..1024");
         c->knobs.recon_max_sweeps = value;
+    } else if (n == "graph") {
+        CHECK(value == 0 || value == 1, "rt_set_knob: graph must be 0 or 1");
+        c->knobs.graph = value;
+    } else if (n == "graph_rounds") {
+        CHECK(value >= 1 && value <= 4096, "rt_set_knob: graph_rounds must be 1..4096");
+        c->knobs.graph_rounds = value;
     } else {
         set_error("rt_set_knob: unknown knob '%s'", name);
         return RT_EINVAL;
@@ -811,6 +919,16 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.recon_round_batch;
     else if (n == "recon_max_sweeps")
         *value = c->knobs.recon_max_sweeps;
+    else if (n == "graph")
+        *value = c->knobs.graph;
+    else if (n == "graph_rounds")
+        *value = c->knobs.graph_rounds;
+    else if (n == "graph_captures")
+        *value = (int)c->graph_captures;
+    else if (n == "graph_replays")
+        *value = (int)c->graph_replays;
+    else if (n == "last_rounds")
+        *value = c->last_rounds;
     else {
         set_error("rt_get_knob: unknown knob '%s'", name);
         return RT_EINVAL;
@@ -820,7 +938,36 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
 
 int rt_profile_enable(rt_ctx *c, int enable) {
     CHECK(c, "rt_profile_enable: ctx is NULL");
+    int e = set_dev(c);
+    if (e) return e;
+    if (enable && !c->prof_visits) {
+        RT_HIP(hipMalloc((void **)&c->prof_visits, sizeof(unsigned long long)));
+        RT_HIP(hipMemset(c->prof_visits, 0, sizeof(unsigned long long)));
+    }
     c->prof_on = enable != 0;
+    return RT_OK;
+}
+
+int rt_profile_recon_rounds(rt_ctx *c, double *kernel_ms, int64_t *launches, int64_t *tile_visits) {
+    CHECK(c && kernel_ms && launches && tile_visits, "rt_profile_recon_rounds: null argument");
+    int e = set_dev(c);
+    if (e) return e;
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < c->round_used; i += 2) {
+        RT_HIP(hipEventSynchronize(c->round_events[i + 1]));
+        float t = 0.f;
+        RT_HIP(hipEventElapsedTime(&t, c->round_events[i], c->round_events[i + 1]));
+        ms += t;
+    }
+    *kernel_ms = ms;
+    *launches = (int64_t)(c->round_used / 2);
+    unsigned long long v = 0;
+    if (c->prof_visits) {
+        RT_HIP(hipMemcpy(&v, c->prof_visits, sizeof v, hipMemcpyDeviceToHost));
+        RT_HIP(hipMemset(c->prof_visits, 0, sizeof v));
+    }
+    *tile_visits = (int64_t)v;
+    c->round_used = 0;
     return RT_OK;
 }
 

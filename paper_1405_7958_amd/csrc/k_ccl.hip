@@ -253,7 +253,7 @@ __device__ void mark_touch(const Tile &t, const uint64_t *rows, int *P) {
 // ---------------------------------------------------------------------------
 // local phase
 // ---------------------------------------------------------------------------
-__device__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
+__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
 
 __global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, int total) {
     __shared__ uint64_t rows[CT];
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, in
     }
 }
 
-__device__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
+__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
     const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
     if (b == 0 && lane == 0) {  // the virtual node of every level is its own root
@@ -378,7 +378,7 @@ __device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bo
     }
 }
 
-__device__ void ccl_merge_tile(const CclArgs &A, int b);
+__device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b);
 
 __global__ __launch_bounds__(CT) void k_ccl_merge(const CclArgs *args, int n, int total) {
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(CT) void k_ccl_merge(const CclArgs *args, int n, in
     }
 }
 
-__device__ void ccl_merge_tile(const CclArgs &A, int b) {
+__device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b) {
     const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
     const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
@@ -449,7 +449,7 @@ __device__ __forceinline__ int global_of(const uint64_t *rows, const int *P, int
     return -P[r] - 1;
 }
 
-__device__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
+__device__ __forceinline__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
 
 __global__ __launch_bounds__(CT) void k_ccl_flatten(const CclArgs *args, int n, int total) {
     __shared__ uint64_t rows[CT];
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(CT) void k_ccl_flatten(const CclArgs *args, int n, 
     }
 }
 
-__device__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
+__device__ __forceinline__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
     const Tile t = tile_of(A, b);
     const int lane = threadIdx.x;
     Col c;

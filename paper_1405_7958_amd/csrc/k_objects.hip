@@ -710,7 +710,7 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
     const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 2), dim3(WAVE), lds_m, s, args_dev, L);
+    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
     if (L.big_slices < 1) {
         set_error("objects: no global scratch slice");

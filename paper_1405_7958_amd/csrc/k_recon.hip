@@ -41,6 +41,7 @@ struct RoundArgs {
     uint32_t *stamp;
     uint32_t epoch;      // stamp value of this round's output list
     int max_sweeps;
+    unsigned long long *visits;   // nullable: tiles processed (stage timing only)
 };
 
 __device__ __forceinline__ int recon_img_of(const ReconImg *imgs, int n, int u) {
@@ -118,6 +119,8 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
     int32_t *cnt_clr = ra.cnt + ((ra.k + 2) % 3);
     if (blockIdx.x == 0 && lane == 0) *cnt_clr = 0;
     const int n_in = ra.first ? ra.total : *cnt_in;
+    if (ra.visits && lane == 0 && (int)blockIdx.x < n_in)
+        atomicAdd(ra.visits, (unsigned long long)((n_in - 1 - (int)blockIdx.x) / (int)gridDim.x + 1));
     for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
         const int gtile = ra.first ? slot : ra.list_in[slot];
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
@@ -320,8 +323,7 @@ int recon_init(int dtype, const void *marker, const void *mask, void *out, int w
 // the density at which the upper level set {v >= l} stops percolating (about
 // 0.41 for 8-connected sites), so the n levels are the smallest values whose
 // upper-set density drops to n targets spread over [0.33, 0.75].
-__global__ void k_select_levels(const uint32_t *hist, int n_levels, int32_t *levels) {
-    if (threadIdx.x != 0) return;
+__device__ void select_levels(const uint32_t *hist, int n_levels, int32_t *levels) {
     double total = 0;
     for (int v = 0; v < 256; ++v) total += hist[v];
     double above = total;  // pixels with value >= v
@@ -338,27 +340,60 @@ __global__ void k_select_levels(const uint32_t *hist, int n_levels, int32_t *lev
     while (k < n_levels) levels[k++] = 255;
 }
 
-// R0 = J: the frame marker (Hq on the 1-pixel tile frame, 0 inside)
-__global__ void k_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h) {
-    const int64_t n = (int64_t)w * h;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t y = i / w, x = i - y * w;
-        const bool fr = x == 0 || y == 0 || x == w - 1 || y == h - 1;
-        r[y * pitch_r + x] = fr ? hq[y * pitch_hq + x] : 0;
+// Per-image set-up and tear-down of a batch (one block per image):
+// begin zeroes the Hq histogram and the kept-object counter (block n zeroes
+// the shared counters); levels picks the threshold levels; end copies each
+// image's kept-object count to the caller's counter.
+__global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr) {
+    const int i = blockIdx.x;
+    if (i == n) {
+        for (int k = threadIdx.x; k < n_ctr; k += blockDim.x) shared_ctr[k] = 0;
+        return;
+    }
+    const BatchAux a = aux[i];
+    for (int k = threadIdx.x; k < 256; k += blockDim.x) a.hist[k] = 0;
+    if (threadIdx.x == 0) *a.kept = 0;
+}
+
+__global__ void k_batch_levels(const BatchAux *aux, int n_levels) {
+    if (threadIdx.x == 0) {
+        const BatchAux a = aux[blockIdx.x];
+        select_levels(a.hist, n_levels, a.levels);
     }
 }
 
-int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h,
-                        hipStream_t s) {
-    const int64_t n = (int64_t)w * h;
-    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_frame_marker, dim3(grid), dim3(256), 0, s, hq, pitch_hq, r, pitch_r, w, h);
-    return hip_fail(hipGetLastError(), "k_frame_marker");
+__global__ void k_batch_end(const BatchAux *aux, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && aux[i].n_dev) *aux[i].n_dev = *aux[i].kept;
 }
 
-int launch_select_levels(const uint32_t *hist, int n_levels, int32_t *levels, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_levels, dim3(1), dim3(64), 0, s, hist, n_levels, levels);
-    return hip_fail(hipGetLastError(), "k_select_levels");
+// R0 = J: the frame marker (Hq on the 1-pixel tile frame, 0 inside); image =
+// blockIdx.y
+__global__ void k_batch_frame_marker(const BatchAux *aux) {
+    const BatchAux a = aux[blockIdx.y];
+    const int64_t n = (int64_t)a.w * a.h;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / a.w, x = i - y * a.w;
+        const bool fr = x == 0 || y == 0 || x == a.w - 1 || y == a.h - 1;
+        a.R[i] = fr ? a.hq[i] : 0;
+    }
+}
+
+int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(n + 1), dim3(256), 0, s, aux, n, shared_ctr, n_ctr);
+    return hip_fail(hipGetLastError(), "k_batch_begin");
+}
+int launch_batch_levels(const BatchAux *aux, int n, int n_levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_levels, dim3(n), dim3(64), 0, s, aux, n_levels);
+    return hip_fail(hipGetLastError(), "k_batch_levels");
+}
+int launch_batch_frame_marker(const BatchAux *aux, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_frame_marker, dim3(256, n), dim3(256), 0, s, aux);
+    return hip_fail(hipGetLastError(), "k_batch_frame_marker");
+}
+int launch_batch_end(const BatchAux *aux, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_end, dim3((n + 63) / 64), dim3(64), 0, s, aux, n);
+    return hip_fail(hipGetLastError(), "k_batch_end");
 }
 
 template <typename T, int CONN>
@@ -368,67 +403,115 @@ static void launch_round(const RoundArgs &ra, int grid, hipStream_t s) {
 
 int64_t recon_tiles(int w, int h) { return (int64_t)((w + RIN - 1) / RIN) * ((h + RIN - 1) / RIN); }
 
-int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total, hipStream_t s,
-                 int *rounds_out) {
+int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run) {
     int e = ensure_stamps(c, (size_t)total);
     if (e) return e;
-    const size_t mark = c->arena.off;
     int32_t *lists = (int32_t *)c->arena.take(sizeof(int32_t) * (2 * (size_t)total + 4));
     if (!lists) {
-        c->arena.off = mark;
         set_error("recon: scratch arena too small");
         return RT_ENOMEM;
     }
-    int32_t *cnt = lists + 2 * (size_t)total;
+    run.lists = lists;
+    run.cnt = lists + 2 * (size_t)total;
+    run.total = total;
+    return RT_OK;
+}
+
+// Rounds k0 .. k1-1.  Round k reads list k & 1 (all tiles when k == 0) and
+// counter k % 3, writes list (k+1) & 1 and counter (k+1) % 3, and clears
+// counter (k+2) % 3.  A tile is queued once per round: its stamp holds the
+// number of the round that queued it (k + 1); the stamps are cleared at k = 0.
+int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
+                 int k1, hipStream_t s) {
     RoundArgs ra;
     ra.imgs = imgs_dev;
     ra.n = n;
-    ra.total = total;
-    ra.cnt = cnt;
+    ra.total = run.total;
+    ra.cnt = run.cnt;
     ra.stamp = c->stamps;
     ra.max_sweeps = c->knobs.recon_max_sweeps;
-    const int grid = std::min(total, c->n_cu * 8);
-    int k = 0;
+    const int grid = std::min(run.total, c->n_cu * 8);
+    if (run.total <= 0) return RT_OK;
+    if (k0 == 0) {
+        int e = launch_fill_i32((int32_t *)c->stamps, 0, (size_t)run.total, s);
+        if (!e) e = launch_fill_i32(run.cnt, 0, 3, s);
+        if (e) return e;
+    }
+    ra.visits = c->prof_on ? c->prof_visits : nullptr;
+    for (int k = k0; k < k1; ++k) {
+        ra.k = k;
+        ra.first = k == 0;
+        ra.list_in = run.lists + (k & 1) * (size_t)run.total;
+        ra.list_out = run.lists + ((k + 1) & 1) * (size_t)run.total;
+        ra.epoch = (uint32_t)k + 1;
+        hipEvent_t ev_end = nullptr;
+        if (c->prof_on) {
+            // per-launch timing of the round kernel: a pair of events around it
+            while (c->round_events.size() < c->round_used + 2) {
+                hipEvent_t ev;
+                RT_HIP(hipEventCreate(&ev));
+                c->round_events.push_back(ev);
+            }
+            RT_HIP(hipEventRecord(c->round_events[c->round_used], s));
+            ev_end = c->round_events[c->round_used + 1];
+            c->round_used += 2;
+        }
+        if (dtype == RT_U8) {
+            if (conn == 8) launch_round<uint8_t, 8>(ra, grid, s);
+            else launch_round<uint8_t, 4>(ra, grid, s);
+        } else {
+            if (conn == 8) launch_round<int32_t, 8>(ra, grid, s);
+            else launch_round<int32_t, 4>(ra, grid, s);
+        }
+        RT_HIP(hipGetLastError());
+        if (ev_end) RT_HIP(hipEventRecord(ev_end, s));
+    }
+    return RT_OK;
+}
+
+int recon_pending(rt_ctx_impl *c, const ReconRun &run, int k, hipStream_t s, int *pending) {
+    if (run.total <= 0) {
+        *pending = 0;
+        return RT_OK;
+    }
+    // the list produced by round k-1 is counted by counter k % 3
+    RT_HIP(hipMemcpyAsync(c->pinned, run.cnt + (k % 3), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    *pending = c->pinned[0];
+    return RT_OK;
+}
+
+int recon_finish(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
+                 hipStream_t s, int *rounds_out) {
     const int batch = c->knobs.recon_round_batch;
     const int max_rounds = 1 << 20;
-    e = RT_OK;
+    int k = k0;
     for (;;) {
-        for (int b = 0; b < batch; ++b, ++k) {
-            ra.k = k;
-            ra.first = k == 0;
-            ra.list_in = lists + (k & 1) * (size_t)total;
-            ra.list_out = lists + ((k + 1) & 1) * (size_t)total;
-            if (++c->stamp_epoch == 0) {
-                int e2 = launch_fill_i32((int32_t *)c->stamps, 0, c->stamps_cap, s);
-                if (e2) return e2;
-                c->stamp_epoch = 1;
-            }
-            ra.epoch = c->stamp_epoch;
-            if (k == 0) {
-                int e2 = launch_fill_i32(cnt, 0, 3, s);
-                if (e2) return e2;
-            }
-            if (dtype == RT_U8) {
-                if (conn == 8) launch_round<uint8_t, 8>(ra, grid, s);
-                else launch_round<uint8_t, 4>(ra, grid, s);
-            } else {
-                if (conn == 8) launch_round<int32_t, 8>(ra, grid, s);
-                else launch_round<int32_t, 4>(ra, grid, s);
-            }
-            RT_HIP(hipGetLastError());
+        if (k > 0) {
+            int pending = 0;
+            int e = recon_pending(c, run, k, s, &pending);
+            if (e) return e;
+            if (!pending) break;
         }
-        // the list produced by the last round: counter (k % 3)
-        RT_HIP(hipMemcpyAsync(c->pinned, cnt + (k % 3), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        RT_HIP(hipStreamSynchronize(s));
-        if (c->pinned[0] == 0) break;
         if (k > max_rounds) {
             set_error("recon: no convergence after %d rounds", k);
-            e = RT_EDEVICE;
-            break;
+            return RT_EDEVICE;
         }
+        int e = recon_launch(c, run, imgs_dev, n, dtype, conn, k, k + batch, s);
+        if (e) return e;
+        k += batch;
     }
-    c->arena.off = mark;
     if (rounds_out) *rounds_out = k;
+    return RT_OK;
+}
+
+int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total, hipStream_t s,
+                 int *rounds_out) {
+    const size_t mark = c->arena.off;
+    ReconRun run;
+    int e = recon_prepare(c, total, run);
+    if (!e) e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
+    c->arena.off = mark;
     return e;
 }
 

@@ -53,6 +53,18 @@ struct Knobs {
     int recon_levels = 3;        // threshold levels of the connectivity lower bound
     int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
+    int graph = 0;               // replay segmentation batches from captured HIP graphs
+    int graph_rounds = 24;       // reconstruction rounds inside the first graph
+};
+
+// A captured segmentation batch: graph A = deconvolution, connectivity bound
+// and the first `graph_rounds` reconstruction rounds; graph B = fill holes,
+// labelling and the per-object stage.  `key` lists everything the launch
+// parameters depend on.
+struct GraphPair {
+    std::vector<int64_t> key;
+    hipGraphExec_t a = nullptr, b = nullptr;
+    uint64_t last_use = 0;
 };
 
 struct rt_ctx_impl {
@@ -65,16 +77,23 @@ struct rt_ctx_impl {
     hipEvent_t staging_done = nullptr;   // recorded after the last upload from `staging`
     bool staging_pending = false;
     double *lut = nullptr;       // 3 x 256 FP64 deconvolution table (device)
-    uint32_t stamp_epoch = 1;    // round stamps for the reconstruction worklists
     uint32_t *stamps = nullptr;  // per-tile stamp array (device)
     size_t stamps_cap = 0;
     Knobs knobs;
+    hipStream_t cap_stream = nullptr;      // private stream for graph capture
+    std::vector<GraphPair> graphs;         // small cache of captured batches
+    uint64_t graph_clock = 0;
+    int64_t graph_replays = 0, graph_captures = 0;
+    int last_rounds = 0;
     // stage timing
     bool prof_on = false;
     std::vector<hipEvent_t> prof_events;   // (RT_PROF_STAGES + 1) per profiled call
     size_t prof_used = 0;                  // events in use
     int64_t prof_launches[RT_PROF_STAGES] = {};
     int prof_calls = 0;
+    std::vector<hipEvent_t> round_events;  // begin/end pairs around reconstruction round launches
+    size_t round_used = 0;
+    unsigned long long *prof_visits = nullptr;   // device: tiles processed by the round kernel
 };
 
 int ensure_arena(rt_ctx_impl *c, size_t bytes);
@@ -152,13 +171,42 @@ struct ReconImg {
 int64_t recon_tiles(int w, int h);   // number of 62 x 62 reconstruction tiles of a w x h image
 int recon_init(int dtype, const void *marker, const void *mask, void *out, int w, int h, int64_t pitch,
                hipStream_t s);
-// Runs rounds until every image of the batch has converged.  All images share
-// dtype and connectivity.  Synchronises `s` between round batches.
-int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total_tiles,
+// Worklists and counters of one reconstruction over `total` tiles (carved
+// from the arena).
+struct ReconRun {
+    int32_t *lists = nullptr;      // two lists of `total` tile ids
+    int32_t *cnt = nullptr;        // 3 rotating counters
+    int total = 0;
+};
+int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run);
+// Enqueues rounds k0 .. k1-1 (no synchronisation; capturable).  All images
+// share dtype and connectivity.
+int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
+                 int k1, hipStream_t s);
+// Reads the number of tiles queued for round k (synchronises `s`).
+int recon_pending(rt_ctx_impl *c, const ReconRun &run, int k, hipStream_t s, int *pending);
+// Runs rounds from k0 on until no tile is queued (synchronises `s` every
+// `recon_round_batch` rounds).
+int recon_finish(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
                  hipStream_t s, int *rounds_out = nullptr);
-int launch_select_levels(const uint32_t *hist, int n_levels, int32_t *levels, hipStream_t s);
-int launch_frame_marker(const uint8_t *hq, int64_t pitch_hq, uint8_t *r, int64_t pitch_r, int w, int h,
-                        hipStream_t s);
+// recon_prepare + recon_finish from round 0; releases the worklists.
+int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int conn, int total, hipStream_t s,
+                 int *rounds_out = nullptr);
+
+// Per-image bookkeeping of a segmentation batch.
+struct BatchAux {
+    uint32_t *hist;                // 256 bins of Hq
+    int32_t *levels;               // threshold levels of the connectivity bound
+    int32_t *kept;                 // kept objects (device)
+    int32_t *n_dev;                // nullable caller counter
+    const uint8_t *hq;             // dense, pitch w
+    uint8_t *R;                    // dense, pitch w
+    int w, h;
+};
+int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr, hipStream_t s);
+int launch_batch_levels(const BatchAux *aux, int n, int n_levels, hipStream_t s);
+int launch_batch_frame_marker(const BatchAux *aux, int n, hipStream_t s);
+int launch_batch_end(const BatchAux *aux, int n, hipStream_t s);
 
 // area filter for labels produced by CCL (root ids)
 int launch_area_filter(const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int w, int h, int64_t pitch,

@@ -71,6 +71,7 @@ def lib():
         L.rt_get_knob.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
         L.rt_profile_enable.argtypes = [vp, C.c_int]
         L.rt_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+        L.rt_profile_recon_rounds.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.rt_profile_stage_name.argtypes = [C.c_int]
         L.rt_profile_stage_name.restype = C.c_char_p
         _lib = L
@@ -281,7 +282,8 @@ def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None):
 
 
 RT_PROF_STAGES = 7
-KNOBS = ("recon_levels", "recon_round_batch", "recon_max_sweeps")
+KNOBS = ("recon_levels", "recon_round_batch", "recon_max_sweeps", "graph", "graph_rounds")
+READ_ONLY = ("graph_captures", "graph_replays", "last_rounds")
 
 
 def rt_set_knob(name, value, ctx=None):
@@ -314,7 +316,18 @@ def rt_profile_read(ctx=None):
     return n, {names[i]: (ms[i], int(ln[i])) for i in range(RT_PROF_STAGES)}
 
 
+def rt_profile_recon_rounds(ctx=None):
+    """Returns (kernel_ms, launches, tile_visits) of the reconstruction round
+    kernel since the last read (recorded while stage timing is on)."""
+    ctx = ctx or default_context()
+    ms = C.c_double()
+    ln = C.c_int64()
+    tv = C.c_int64()
+    _check(lib().rt_profile_recon_rounds(ctx.h, C.byref(ms), C.byref(ln), C.byref(tv)))
+    return ms.value, ln.value, tv.value
+
+
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
            "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
-           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read",
+           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds",
            "rt_profile_stage_name")

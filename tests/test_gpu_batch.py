@@ -122,3 +122,80 @@ def test_batch_empty_and_bad_arguments(rt):
     big = rt.rt_tile_desc(rgb.data_ptr(), 3 * 6000, 6000, 6000, m.data_ptr(), lab.data_ptr(), 6000, None, None)
     rc = rt.lib().rt_segment_batch(ctx.h, 1, (rt.rt_tile_desc * 1)(big), C.byref(p), None)
     assert rc == rt.RT_EINVAL
+
+
+def _knobs(rt, ctx, **kv):
+    old = {k: rt.rt_get_knob(k, ctx=ctx) for k in kv}
+    for k, v in kv.items():
+        rt.rt_set_knob(k, v, ctx=ctx)
+    return old
+
+
+def test_graph_replays_match_eager(rt, oracle):
+    """Graph replays of a batch equal the eager launches, replay after replay,
+    with eager work and synchronisation between replays; a round budget too
+    small for convergence falls back to ordinary rounds."""
+    import torch
+    d = dev()
+    specs = [synth.spec_uneven(i) for i in (0, 2, 7, 9)]
+    specs = [synth.TileSpec(w=min(s.w, 1024), h=min(s.h, 1024), seed=s.seed, n_nuclei=s.n_nuclei // 4, amin=4,
+                            amax=14, cluster_frac=0.2, cluster_min=2, cluster_max=4, jitter=20) for s in specs]
+    rgbs = _gen(specs)
+    t = [to_dev(r, d) for r in rgbs]
+    ctx = rt.Context(0)
+    say("graph: eager reference")
+    ref = [tuple(to_np(x) for x in o) for o in rt.rt_segment_batch(t, want_hq=True, ctx=ctx)]
+    for i, r in enumerate(ref):
+        emask, elab, en = oracle.segment_from_hq(r[3])
+        assert_equal(r[1], elab, f"eager tile {i} labels")
+        assert int(r[2][0]) == en
+    for budget in (1, 64):
+        _knobs(rt, ctx, graph=1, graph_rounds=budget)
+        caps0 = rt.rt_get_knob("graph_captures", ctx=ctx)
+        for rep in range(3):
+            say("graph replay", budget, rep)
+            got = rt.rt_segment_batch(t, ctx=ctx)
+            # eager work on the same stream between replays
+            rt.rt_segment_tile(t[0], ctx=rt.default_context(0))
+            torch.cuda.synchronize()
+            for i, (g, r) in enumerate(zip(got, ref)):
+                assert_equal(to_np(g[0]), r[0], f"budget {budget} replay {rep} tile {i} mask")
+                assert_equal(to_np(g[1]), r[1], f"budget {budget} replay {rep} tile {i} labels")
+                assert int(to_np(g[2])[0]) == int(r[2][0])
+        assert rt.rt_get_knob("graph_captures", ctx=ctx) == caps0 + 1
+    assert rt.rt_get_knob("graph_replays", ctx=ctx) >= 6
+    ctx.close()
+
+
+def test_graph_single_tile_and_profile_off(rt, oracle):
+    d = dev()
+    rgb = synth.make_tile(synth.spec_small(2))[0]
+    ctx = rt.Context(0)
+    _knobs(rt, ctx, graph=1, graph_rounds=8)
+    for rep in range(2):
+        say("graph single tile", rep)
+        mask, lab, n, hq = rt.rt_segment_tile(to_dev(rgb, d), want_hq=True, ctx=ctx)
+        emask, elab, en = oracle.segment_from_hq(to_np(hq))
+        assert_equal(to_np(lab), elab, "graph single labels")
+        assert_equal(to_np(mask), emask, "graph single mask")
+        assert int(to_np(n)[0]) == en
+    ctx.close()
+
+
+def test_autotune_keeps_results(rt, tmp_path):
+    from paper_1405_7958_amd import tune
+    d = dev()
+    rgbs = [to_dev(synth.make_tile(synth.spec_uneven(i))[0][:700, :900].copy(), d) for i in (1, 4)]
+    ctx = rt.Context(0)
+    ref = [tuple(to_np(x) for x in o) for o in rt.rt_segment_batch(rgbs, ctx=ctx)]
+    say("autotune")
+    res = tune.autotune(rgbs, ctx=ctx, reps=2, cache=str(tmp_path / "tune.json"))
+    assert set(res["knobs"]) >= {"recon_levels", "recon_round_batch", "recon_max_sweeps", "graph"}
+    assert len(res["trials"]) >= 8
+    got = rt.rt_segment_batch(rgbs, ctx=ctx)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        assert_equal(to_np(g[1]), r[1], f"tuned tile {i} labels")
+    # a second call is served from the cache
+    res2 = tune.autotune(rgbs, ctx=ctx, reps=2, cache=str(tmp_path / "tune.json"))
+    assert res2["knobs"] == res["knobs"]
+    ctx.close()
