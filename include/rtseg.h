@@ -189,6 +189,10 @@ typedef struct {
     int64_t out_pitch;       /* elements, >= w */
     int32_t *n_objects_dev;  /* nullable device int32 */
     uint8_t *hq_out;         /* nullable device uint8; needs out_pitch == w */
+    uint8_t *fg_out;         /* nullable device uint8, pitch out_pitch: the foreground A after the
+                                first area threshold (the watershed's input), 0/1 */
+    uint8_t *seeds_out;      /* nullable (given iff fg_out is): the watershed seeds (regional
+                                maxima of the h-maxima transform of Dq) inside A, 0/1 */
 } rt_tile_desc;
 int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt_seg_params *params, void *stream);
 
@@ -212,7 +216,7 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *   "graph_rounds"      1..4096; default 24
  * Read-only (rt_get_knob): "graph_captures", "graph_replays" (counts since
  * the context was created), "last_rounds" (reconstruction rounds of the last
- * segmentation call).
+ * segmentation call), "device" (the context's HIP device).
  * Errors: RT_EINVAL for an unknown name or a value out of range.
  */
 int rt_set_knob(rt_ctx *ctx, const char *name, int value);

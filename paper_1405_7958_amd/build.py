@@ -16,7 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtseg.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "k_deconv.hip", "k_ccl.hip", "k_recon.hip", "k_objects.hip", "k_misc.hip"]
+SOURCES = ["api.cpp", "unet.cpp", "k_deconv.hip", "k_ccl.hip", "k_recon.hip", "k_objects.hip", "k_misc.hip",
+           "k_nn.hip"]
 
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

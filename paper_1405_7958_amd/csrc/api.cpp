@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/rtseg_unet.h"
 #include "rt_internal.h"
 
 struct rt_ctx : rtseg::rt_ctx_impl {};
@@ -258,6 +259,7 @@ struct TileIn {
     int64_t out_pitch;
     int32_t *n_dev;
     uint8_t *hq_out;
+    uint8_t *fg_out, *seeds_out;
 };
 
 // Device-side plan of one launch group: arena offsets of the argument arrays
@@ -269,6 +271,7 @@ struct Plan {
     int slices = 4;
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
+    bool any_maps = false;   // some tile asks for its foreground / seed maps
     ReconRun run;
 };
 
@@ -282,6 +285,7 @@ int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s
     if ((e = launch_deconv_lut(sp, c->lut, s))) return e;
     if ((e = launch_batch_begin(at<BatchAux>(c, P.o_aux), P.n, at<int32_t>(c, P.o_ctr), kSharedCounters, s)))
         return e;
+    if (P.any_maps && (e = launch_batch_zero_maps(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     if ((e = launch_deconv(c->lut, sp.scale, at<DeconvImg>(c, P.o_dec), P.n, P.dec_total, c->n_cu, s))) return e;
     c->prof_launches[0] += 3;
     if (prof && (e = prof_mark(c, 1, s))) return e;
@@ -364,6 +368,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         const TileIn &t = tiles[i];
         const size_t N = (size_t)t.w * t.h;
         Per &q = per[i];
+        P.any_maps |= t.fg_out != nullptr;
         q.hq = t.hq_out ? 0 : L.add(N);
         q.R = L.add(N);
         q.F = L.add(N);
@@ -421,7 +426,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         const int64_t pw = t.w;
         dec[i] = DeconvImg{t.rgb, t.rgb_pitch, hq, pw, nullptr, 0, at<uint32_t>(c, q.hist), t.w, t.h, q.dec0};
         aux[i] = BatchAux{at<uint32_t>(c, q.hist), at<int32_t>(c, q.levels), at<int32_t>(c, q.kept), t.n_dev, hq, R,
-                          t.w, t.h};
+                          t.w, t.h, t.fg_out, t.seeds_out, t.out_pitch};
 
         CclArgs A{};
         A.pred = CclPred::Level;
@@ -503,6 +508,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         O.min_area = p->min_area;
         O.max_area = p->max_area;
         O.n_kept = at<int32_t>(c, q.kept);
+        O.fg_out = t.fg_out;
+        O.seeds_out = t.seeds_out;
         ob[i] = O;
     }
     Stager sg{c};
@@ -523,7 +530,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         return enqueue_back(c, P, s, true);
     }
     // ---- graph path: everything that fixes a launch parameter goes into the key
-    std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu,
+    std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -854,7 +861,7 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
         return RT_EUNSUPPORTED;
     }
     if ((e = set_dev(c))) return e;
-    const TileIn t{rgb, rgb_pitch, w, h, mask_out, labels_out, out_pitch, n_objects_dev, hq_out};
+    const TileIn t{rgb, rgb_pitch, w, h, mask_out, labels_out, out_pitch, n_objects_dev, hq_out, nullptr, nullptr};
     return pipeline(c, &t, 1, p, as_stream(stream));
 }
 
@@ -872,16 +879,127 @@ int rt_segment_batch(rt_ctx *c, int32_t n, const rt_tile_desc *tiles, const rt_s
             set_error("rt_segment_batch: tile %d: hq_out needs out_pitch == w", i);
             return RT_EUNSUPPORTED;
         }
+        CHECK(!d.fg_out == !d.seeds_out, "rt_segment_batch: tile %d: give both fg_out and seeds_out or neither", i);
     }
     if ((e = set_dev(c))) return e;
     std::vector<TileIn> t(n);
     for (int i = 0; i < n; ++i) {
         const rt_tile_desc &d = tiles[i];
         t[i] = TileIn{d.rgb, d.rgb_pitch_bytes, d.w, d.h, d.mask_out, d.labels_out, d.out_pitch, d.n_objects_dev,
-                      d.hq_out};
+                      d.hq_out, d.fg_out, d.seeds_out};
     }
     for (int b = 0; b < n; b += MAX_BATCH)
         if ((e = pipeline(c, t.data() + b, std::min(MAX_BATCH, n - b), p, as_stream(stream)))) return e;
+    return RT_OK;
+}
+
+int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h,
+                              const rt_seg_params *p, float tau, uint8_t *mask_out, int32_t *labels_out,
+                              int64_t out_pitch, int32_t *n_objects_dev, int32_t *used_fallback, float *confidence,
+                              void *stream) {
+    CHECK(c && net && rgb && p && mask_out && labels_out, "rt_segment_tile_surrogate: null argument");
+    int e = check_params(p, "rt_segment_tile_surrogate");
+    if (e) return e;
+    CHECK(!bad_size(w, h, kMaxObjPixels), "rt_segment_tile_surrogate: bad size %dx%d", w, h);
+    CHECK(rgb_pitch >= 3LL * w && out_pitch >= w, "rt_segment_tile_surrogate: pitch smaller than width");
+    if ((e = set_dev(c))) return e;
+    hipStream_t s = as_stream(stream);
+    const size_t N = (size_t)w * h, n1 = N + 1;
+    Layout L;
+    const size_t o_pf = L.add(sizeof(float) * N);
+    const size_t o_ps = L.add(sizeof(float) * N);
+    const size_t o_f0 = L.add(N);
+    const size_t o_sd = L.add(N);
+    const size_t o_f = L.add(N);
+    const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
+    const size_t mo = max_obj_of(w, h);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 3);
+    const size_t o_ctr = L.add(kSharedCounters * sizeof(int32_t));
+    const size_t slice = al(big_object_bytes(w, h));
+    const size_t o_slices = L.add(slice * 4);
+    const size_t o_cf = L.add(sizeof(CclArgs));
+    const size_t o_cc = L.add(sizeof(CclArgs));
+    const size_t o_ob = L.add(sizeof(ObjArgs));
+    if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, L.off - o_cf + 4096))) return e;
+    int32_t *ctr = at<int32_t>(c, o_ctr);
+    // 1. network probabilities and the thresholded maps
+    if ((e = rt_unet_forward(net, rgb, rgb_pitch, w, h, at<float>(c, o_pf), at<float>(c, o_ps), w, stream))) return e;
+    if ((e = launch_fill_i32(ctr, 0, kSharedCounters, s))) return e;
+    if ((e = launch_surrogate_maps(at<float>(c, o_pf), at<float>(c, o_ps), w, h, at<uint8_t>(c, o_f0),
+                                   at<uint8_t>(c, o_sd), ctr + 4, s)))
+        return e;
+    RT_HIP(hipMemcpyAsync(c->pinned, ctr + 4, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    const double conf = 1.0 - (double)c->pinned[1] / (double)std::max(1, c->pinned[0]);
+    if (confidence) *confidence = (float)conf;
+    if (conf < tau) {   // low confidence: the plain pipeline decides this tile
+        if (used_fallback) *used_fallback = 1;
+        return rt_segment_tile(c, rgb, rgb_pitch, w, h, p, mask_out, labels_out, out_pitch, n_objects_dev, nullptr,
+                               stream);
+    }
+    if (used_fallback) *used_fallback = 0;
+    // 2. FillHoles of the foreground map, BWLabel, then the per-object stage
+    //    with the network's seeds, both area thresholds
+    int32_t *reg = at<int32_t>(c, o_reg);
+    int32_t *obj = at<int32_t>(c, o_obj);
+    CclArgs B{};
+    B.pred = CclPred::Zero;
+    B.out = CclOut::FillHoles;
+    B.conn = 4;
+    B.frame_virtual = true;
+    B.w = w;
+    B.h = h;
+    B.a = at<uint8_t>(c, o_f0);
+    B.pitch_a = w;
+    B.ids = reg;
+    B.fill = at<uint8_t>(c, o_f);
+    B.pitch_f = w;
+    CclArgs A{};
+    A.pred = CclPred::NonZero;
+    A.out = CclOut::Labels;
+    A.conn = 8;
+    A.w = w;
+    A.h = h;
+    A.a = at<uint8_t>(c, o_f);
+    A.pitch_a = w;
+    A.ids = reg;
+    A.labels = labels_out;
+    A.pitch_l = out_pitch;
+    A.bg_zero_mask = mask_out;
+    A.pitch_m = out_pitch;
+    A.st_area = reg + n1;
+    A.st_x0 = reg + 2 * n1;
+    A.st_x1 = reg + 3 * n1;
+    A.st_y0 = reg + 4 * n1;
+    A.st_y1 = reg + 5 * n1;
+    A.obj_list = obj;
+    A.n_obj = ctr;
+    ObjArgs O{};
+    O.w = w;
+    O.h = h;
+    O.pitch = out_pitch;
+    O.st_area = A.st_area;
+    O.st_x0 = A.st_x0;
+    O.st_x1 = A.st_x1;
+    O.st_y0 = A.st_y0;
+    O.st_y1 = A.st_y1;
+    O.labels = labels_out;
+    O.mask = mask_out;
+    O.seeds = at<uint8_t>(c, o_sd);
+    O.h_seed = p->h_seed;
+    O.min_area_pre = p->min_area;
+    O.min_area = p->min_area;
+    O.max_area = p->max_area;
+    O.n_kept = ctr + 3;
+    Stager sg{c};
+    if ((e = sg.put(std::vector<CclArgs>{B}, o_cf)) || (e = sg.put(std::vector<CclArgs>{A}, o_cc)) ||
+        (e = sg.put(std::vector<ObjArgs>{O}, o_ob)) || (e = sg.flush(s)))
+        return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, at<void>(c, o_slices), slice, 4};
+    if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s))) return e;
+    if (n_objects_dev) RT_HIP(hipMemcpyAsync(n_objects_dev, ctr + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     return RT_OK;
 }
 
@@ -929,6 +1047,8 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = (int)c->graph_replays;
     else if (n == "last_rounds")
         *value = c->last_rounds;
+    else if (n == "device")
+        *value = c->device;
     else {
         set_error("rt_get_knob: unknown knob '%s'", name);
         return RT_EINVAL;

@@ -89,6 +89,9 @@ __global__ __launch_bounds__(256) void k_deconv(const double *__restrict__ lut, 
             uint32_t wds[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
             uint32_t out[4] = {0, 0, 0, 0};
             float cf[16];
+            // histogram by runs of equal values (background dominates, so one
+            // LDS atomic covers most of a thread's 16 pixels)
+            uint32_t run_q = 256u, run_n = 0u;
 #pragma unroll
             for (int p = 0; p < 16; ++p) {
                 const int b0 = 3 * p, b1 = 3 * p + 1, b2 = 3 * p + 2;
@@ -99,8 +102,15 @@ __global__ __launch_bounds__(256) void k_deconv(const double *__restrict__ lut, 
                 const uint32_t q = quantize(c, scale);
                 out[p >> 2] |= q << ((p & 3) * 8);
                 cf[p] = (float)c;
-                if (im.hist) atomicAdd(&H[q], 1u);
+                if (q == run_q) {
+                    ++run_n;
+                } else {
+                    if (im.hist && run_n) atomicAdd(&H[run_q], run_n);
+                    run_q = q;
+                    run_n = 1u;
+                }
             }
+            if (im.hist && run_n) atomicAdd(&H[run_q], run_n);
             *reinterpret_cast<uint4 *>(im.hq + p0) = make_uint4(out[0], out[1], out[2], out[3]);
             if (im.ch) {
                 float4 *cd = reinterpret_cast<float4 *>(im.ch + p0);

@@ -17,6 +17,50 @@ int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s) {
     return hip_fail(hipGetLastError(), "k_fill_i32");
 }
 
+__global__ void k_zero_u8(uint8_t *p, int64_t pitch, int w, int h) {
+    const int64_t n = (int64_t)w * h;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / w, x = i - y * w;
+        p[y * pitch + x] = 0;
+    }
+}
+int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s) {
+    const int64_t n = (int64_t)w * h;
+    if (n <= 0) return RT_OK;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_u8, dim3(grid), dim3(256), 0, s, p, pitch, w, h);
+    return hip_fail(hipGetLastError(), "k_zero_u8");
+}
+
+__global__ void k_surrogate_maps(const float *pf, const float *ps, int64_t n, uint8_t *fg, uint8_t *seeds,
+                                 int32_t *counts) {
+    int c0 = 0, c1 = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float f = pf[i];
+        fg[i] = f >= 0.5f ? 1 : 0;
+        seeds[i] = ps[i] >= 0.5f ? 1 : 0;
+        c0 += f >= 0.25f;
+        c1 += (f >= 0.25f && f < 0.75f);
+    }
+    // wave sums, one atomic per wave
+    for (int off = 32; off >= 1; off >>= 1) {
+        c0 += __shfl_xor(c0, off, 64);
+        c1 += __shfl_xor(c1, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c0) atomicAdd(counts, c0);
+        if (c1) atomicAdd(counts + 1, c1);
+    }
+}
+int launch_surrogate_maps(const float *p_fg, const float *p_seed, int w, int h, uint8_t *fg, uint8_t *seeds,
+                          int32_t *counts, hipStream_t s) {
+    const int64_t n = (int64_t)w * h;
+    if (n <= 0) return RT_OK;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_surrogate_maps, dim3(grid), dim3(256), 0, s, p_fg, p_seed, n, fg, seeds, counts);
+    return hip_fail(hipGetLastError(), "k_surrogate_maps");
+}
+
 // area filter on labels (root ids); area_scratch has w*h+1 entries
 __global__ void k_area_zero(const int32_t *lab, int w, int h, int64_t pitch, int32_t *area) {
     int64_t n = (int64_t)w * h;

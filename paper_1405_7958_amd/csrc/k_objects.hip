@@ -443,6 +443,15 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
         __syncthreads();
     }
+    if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
+        for (int i = lane; i < m.n; i += WAVE) {
+            if (!(m.fl[i] & F_IN)) continue;
+            const int c = i % m.st, r = i / m.st;
+            const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+            a.fg_out[o] = 1;
+            a.seeds_out[o] = (m.fl[i] & F_RM) ? 1 : 0;
+        }
+    }
     crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
     int nroots = 0;
     for (int i = lane; i < m.n; i += WAVE) nroots += (m.B[i] == (L)i);

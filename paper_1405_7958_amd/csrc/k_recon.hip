@@ -379,6 +379,23 @@ __global__ void k_batch_frame_marker(const BatchAux *aux) {
     }
 }
 
+// zeroes the optional foreground / seed maps of every image (image = blockIdx.y)
+__global__ void k_batch_zero_maps(const BatchAux *aux) {
+    const BatchAux a = aux[blockIdx.y];
+    if (!a.fg_out) return;
+    const int64_t n = (int64_t)a.w * a.h;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = i / a.w, x = i - y * a.w;
+        a.fg_out[y * a.out_pitch + x] = 0;
+        a.seeds_out[y * a.out_pitch + x] = 0;
+    }
+}
+
+int launch_batch_zero_maps(const BatchAux *aux, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_zero_maps, dim3(64, n), dim3(256), 0, s, aux);
+    return hip_fail(hipGetLastError(), "k_batch_zero_maps");
+}
+
 int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_begin, dim3(n + 1), dim3(256), 0, s, aux, n, shared_ctr, n_ctr);
     return hip_fail(hipGetLastError(), "k_batch_begin");

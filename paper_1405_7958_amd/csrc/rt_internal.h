@@ -202,11 +202,14 @@ struct BatchAux {
     const uint8_t *hq;             // dense, pitch w
     uint8_t *R;                    // dense, pitch w
     int w, h;
+    uint8_t *fg_out, *seeds_out;   // nullable caller maps (pitch out_pitch), zeroed at the start
+    int64_t out_pitch;
 };
 int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr, hipStream_t s);
 int launch_batch_levels(const BatchAux *aux, int n, int n_levels, hipStream_t s);
 int launch_batch_frame_marker(const BatchAux *aux, int n, hipStream_t s);
 int launch_batch_end(const BatchAux *aux, int n, hipStream_t s);
+int launch_batch_zero_maps(const BatchAux *aux, int n, hipStream_t s);
 
 // area filter for labels produced by CCL (root ids)
 int launch_area_filter(const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int w, int h, int64_t pitch,
@@ -226,6 +229,8 @@ struct ObjArgs {                   // one record per image
     int min_area_pre;              // components below this area are erased
     int min_area, max_area;        // final area filter (max_area < 0: none)
     int32_t *n_kept;               // nullable: number of kept objects of this image
+    uint8_t *fg_out, *seeds_out;   // nullable (both or neither): foreground after the first
+                                   // area threshold and its seeds; zeroed by the caller
 };
 struct ObjLists {                  // shared by the batch; entries are image << 25 | root
     const int32_t *obj, *n_obj;
@@ -241,5 +246,11 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hip
 size_t big_object_bytes(int w, int h);   // one slice for the largest crop of a w x h image
 
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
+// zeroes a pitched w x h uint8 image
+int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s);
+// Surrogate maps: fg = [p_fg >= 0.5], seeds = [p_seed >= 0.5]; counts[0] +=
+// pixels with p_fg >= 0.25, counts[1] += pixels with 0.25 <= p_fg < 0.75.
+int launch_surrogate_maps(const float *p_fg, const float *p_seed, int w, int h, uint8_t *fg, uint8_t *seeds,
+                          int32_t *counts, hipStream_t s);
 
 }  // namespace rtseg

@@ -41,7 +41,8 @@ class rt_seg_params(C.Structure):
 class rt_tile_desc(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("rgb_pitch_bytes", C.c_int64), ("w", C.c_int32), ("h", C.c_int32),
                 ("mask_out", C.c_void_p), ("labels_out", C.c_void_p), ("out_pitch", C.c_int64),
-                ("n_objects_dev", C.c_void_p), ("hq_out", C.c_void_p)]
+                ("n_objects_dev", C.c_void_p), ("hq_out", C.c_void_p), ("fg_out", C.c_void_p),
+                ("seeds_out", C.c_void_p)]
 
 
 _lib = None
@@ -71,6 +72,31 @@ def lib():
         L.rt_get_knob.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
         L.rt_profile_enable.argtypes = [vp, C.c_int]
         L.rt_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+        u64 = C.c_uint64
+        f32 = C.c_float
+        L.rt_unet_param_count.restype = C.c_int64
+        L.rt_unet_param_count.argtypes = []
+        L.rt_unet_create.argtypes = [vp, u64, C.POINTER(vp)]
+        L.rt_unet_destroy.argtypes = [vp]
+        L.rt_unet_get_params.argtypes = [vp, vp, i64]
+        L.rt_unet_set_params.argtypes = [vp, vp, i64]
+        L.rt_unet_get_grads.argtypes = [vp, vp, i64]
+        L.rt_unet_grad_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, vp, vp]
+        L.rt_unet_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, f32, vp, vp]
+        L.rt_unet_forward.argtypes = [vp, vp, i64, i32, i32, vp, vp, i64, vp]
+        L.rt_unet_save.argtypes = [vp, C.c_char_p]
+        L.rt_unet_load.argtypes = [vp, C.c_char_p]
+        L.rt_segment_tile_surrogate.argtypes = [vp, vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), f32, vp, vp,
+                                                i64, vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), vp]
+        L.rt_nn_conv3_fwd.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.rt_nn_conv3_dgrad.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp]
+        L.rt_nn_conv3_wgrad.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, i32, vp, vp, vp]
+        L.rt_nn_up2_fwd.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, i32, vp, vp, vp]
+        L.rt_nn_up2_bwd.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.rt_nn_pool2.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.rt_nn_head_loss.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp]
+        L.rt_nn_pack.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
+        L.rt_nn_prep_input.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.rt_profile_recon_rounds.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.rt_profile_stage_name.argtypes = [C.c_int]
         L.rt_profile_stage_name.restype = C.c_char_p
@@ -258,11 +284,13 @@ def rt_segment_tile(rgb, params=None, want_hq=False, ctx=None, out=None):
     return (mask, lab, n, hq) if want_hq else (mask, lab, n)
 
 
-def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None):
+def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None, want_maps=False):
     """Segments a list of (H_i, W_i, 3) uint8 device tiles in one call.
 
-    Returns a list of (mask, labels, n_objects[, hq]) per tile, as
-    rt_segment_tile would for each tile alone."""
+    Returns a list of (mask, labels, n_objects[, hq][, fg, seeds]) per tile,
+    as rt_segment_tile would for each tile alone; with want_maps the
+    foreground after the first area threshold and its watershed seeds are
+    returned too (uint8 0/1 maps)."""
     ctx = ctx or (default_context(rgbs[0].device.index) if rgbs else default_context())
     p = params if params is not None else default_params()
     outs = []
@@ -274,9 +302,13 @@ def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None):
         lab = torch.empty((h, w), dtype=torch.int32, device=rgb.device)
         n = torch.zeros(1, dtype=torch.int32, device=rgb.device)
         hq = torch.empty((h, w), dtype=torch.uint8, device=rgb.device) if want_hq else None
+        fg = torch.empty((h, w), dtype=torch.uint8, device=rgb.device) if want_maps else None
+        sd = torch.empty((h, w), dtype=torch.uint8, device=rgb.device) if want_maps else None
         descs[i] = rt_tile_desc(rgb.data_ptr(), rgb.stride(0), w, h, mask.data_ptr(), lab.data_ptr(), w,
-                                n.data_ptr(), hq.data_ptr() if hq is not None else None)
-        outs.append((mask, lab, n, hq) if want_hq else (mask, lab, n))
+                                n.data_ptr(), hq.data_ptr() if hq is not None else None,
+                                fg.data_ptr() if fg is not None else None, sd.data_ptr() if sd is not None else None)
+        o = (mask, lab, n, hq) if want_hq else (mask, lab, n)
+        outs.append(o + (fg, sd) if want_maps else o)
     _check(lib().rt_segment_batch(ctx.h, len(rgbs), descs, C.byref(p), _stream()))
     return outs
 
@@ -327,7 +359,225 @@ def rt_profile_recon_rounds(ctx=None):
     return ms.value, ln.value, tv.value
 
 
+# ----------------------------------------------------------------------------
+# the U-Net surrogate (include/rtseg_unet.h)
+# ----------------------------------------------------------------------------
+
+def unet_param_count():
+    return int(lib().rt_unet_param_count())
+
+
+class UNet:
+    """Owns an rt_unet on the context's device."""
+
+    def __init__(self, seed: int = 0, ctx=None):
+        self.ctx = ctx or default_context()
+        h = C.c_void_p()
+        _check(lib().rt_unet_create(self.ctx.h, C.c_uint64(seed), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().rt_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(unet_param_count(), np.float32)
+        _check(lib().rt_unet_get_params(self.h, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, vec):
+        import numpy as np
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        _check(lib().rt_unet_set_params(self.h, v.ctypes.data, v.size))
+
+    def get_grads(self):
+        import numpy as np
+        out = np.empty(unet_param_count(), np.float32)
+        _check(lib().rt_unet_get_grads(self.h, out.ctypes.data, out.size))
+        return out
+
+    def _batch(self, rgb, fg, seed):
+        _img(rgb[0], torch.uint8, "rgb[0]", 3)
+        if not (rgb.is_contiguous() and fg.is_contiguous() and seed.is_contiguous()):
+            raise ValueError("batch tensors must be contiguous")
+        b, h, w = rgb.shape[:3]
+        if fg.shape != (b, h, w) or seed.shape != (b, h, w) or fg.dtype != torch.uint8 or seed.dtype != torch.uint8:
+            raise ValueError("targets must be (b, h, w) uint8")
+        return b, h, w
+
+    def grad_step(self, rgb, fg, seed, w_seed=1.0, loss=None):
+        """Adds the gradient of the batch loss; returns the loss tensor (device)."""
+        b, h, w = self._batch(rgb, fg, seed)
+        loss = loss if loss is not None else torch.zeros(1, dtype=torch.float32, device=rgb.device)
+        _check(lib().rt_unet_grad_step(self.h, _ptr(rgb), _ptr(fg), _ptr(seed), b, h, w, float(w_seed), _ptr(loss),
+                                       _stream()))
+        return loss
+
+    def train_step(self, rgb, fg, seed, lr=1e-3, w_seed=1.0, loss=None):
+        b, h, w = self._batch(rgb, fg, seed)
+        loss = loss if loss is not None else torch.zeros(1, dtype=torch.float32, device=rgb.device)
+        _check(lib().rt_unet_train_step(self.h, _ptr(rgb), _ptr(fg), _ptr(seed), b, h, w, float(lr), float(w_seed),
+                                        _ptr(loss), _stream()))
+        return loss
+
+    def forward(self, rgb):
+        """(H, W, 3) uint8 tile -> (p_fg, p_seed) float32 maps."""
+        _img(rgb, torch.uint8, "rgb", 3)
+        h, w = rgb.shape[:2]
+        pf = torch.empty((h, w), dtype=torch.float32, device=rgb.device)
+        ps = torch.empty((h, w), dtype=torch.float32, device=rgb.device)
+        _check(lib().rt_unet_forward(self.h, _ptr(rgb), rgb.stride(0), w, h, _ptr(pf), _ptr(ps), w, _stream()))
+        return pf, ps
+
+    def save(self, path):
+        _check(lib().rt_unet_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        _check(lib().rt_unet_load(self.h, os.fsencode(path)))
+
+
+def rt_segment_tile_surrogate(rgb, net, tau=0.5, params=None, ctx=None):
+    """Returns (mask, labels, n_objects, used_fallback, confidence)."""
+    ctx = ctx or net.ctx
+    _img(rgb, torch.uint8, "rgb", 3)
+    h, w = rgb.shape[:2]
+    p = params if params is not None else default_params()
+    mask = torch.empty((h, w), dtype=torch.uint8, device=rgb.device)
+    lab = torch.empty((h, w), dtype=torch.int32, device=rgb.device)
+    n = torch.zeros(1, dtype=torch.int32, device=rgb.device)
+    fb = C.c_int32(0)
+    conf = C.c_float(0.0)
+    _check(lib().rt_segment_tile_surrogate(ctx.h, net.h, _ptr(rgb), rgb.stride(0), w, h, C.byref(p), float(tau),
+                                           _ptr(mask), _ptr(lab), w, _ptr(n), C.byref(fb), C.byref(conf),
+                                           _stream()))
+    return mask, lab, n, bool(fb.value), float(conf.value)
+
+
+def _u16(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in (torch.int16, torch.uint16, torch.bfloat16):
+        raise TypeError(f"{name}: expected a 16-bit device tensor holding bfloat16")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    return t
+
+
+def nn_conv3_fwd(x0, wf, bias, co, relu=False, x1=None, ctx=None):
+    """x0 (n, h, w, c0) [and x1 (n, h, w, c1)] bf16 -> y float32 (n, h, w, co)."""
+    ctx = ctx or default_context()
+    n, h, w, c0 = x0.shape
+    c1 = x1.shape[3] if x1 is not None else 0
+    y = torch.empty((n, h, w, co), dtype=torch.float32, device=x0.device)
+    _check(lib().rt_nn_conv3_fwd(ctx.h, _ptr(_u16(x0, "x0")), c0, _ptr(x1), c1, n, h, w, _ptr(_u16(wf, "wf")),
+                                 _ptr(bias), co, 1 if relu else 0, _ptr(y), None, _stream()))
+    return y
+
+
+def nn_conv3_dgrad(g, wt, ci, c0=None, ctx=None):
+    ctx = ctx or default_context()
+    n, h, w, co = g.shape
+    c0 = ci if c0 is None else c0
+    dx0 = torch.empty((n, h, w, c0), dtype=torch.float32, device=g.device)
+    dx1 = torch.empty((n, h, w, ci - c0), dtype=torch.float32, device=g.device) if c0 < ci else None
+    _check(lib().rt_nn_conv3_dgrad(ctx.h, _ptr(_u16(g, "g")), co, n, h, w, _ptr(_u16(wt, "wt")), ci, c0, _ptr(dx0),
+                                   _ptr(dx1), _stream()))
+    return (dx0, dx1) if dx1 is not None else dx0
+
+
+def nn_conv3_wgrad(x0, g, x1=None, ctx=None):
+    ctx = ctx or default_context()
+    n, h, w, c0 = x0.shape
+    c1 = x1.shape[3] if x1 is not None else 0
+    co = g.shape[3]
+    dw = torch.zeros((co, 9, c0 + c1), dtype=torch.float32, device=x0.device)
+    db = torch.zeros(co, dtype=torch.float32, device=x0.device)
+    _check(lib().rt_nn_conv3_wgrad(ctx.h, _ptr(_u16(x0, "x0")), c0, _ptr(x1), c1, _ptr(_u16(g, "g")), co, n, h, w,
+                                   _ptr(dw), _ptr(db), _stream()))
+    return dw, db
+
+
+def nn_up2_fwd(x, uf, bias, co, ctx=None):
+    ctx = ctx or default_context()
+    n, h, w, ci = x.shape
+    y = torch.empty((n, 2 * h, 2 * w, co), dtype=torch.float32, device=x.device)
+    _check(lib().rt_nn_up2_fwd(ctx.h, _ptr(_u16(x, "x")), ci, n, h, w, _ptr(_u16(uf, "uf")), _ptr(bias), co, _ptr(y),
+                               None, _stream()))
+    return y
+
+
+def nn_up2_bwd(x, g, ut, ctx=None):
+    ctx = ctx or default_context()
+    n, h, w, ci = x.shape
+    co = g.shape[3]
+    dx = torch.empty((n, h, w, ci), dtype=torch.float32, device=x.device)
+    dw = torch.zeros((ci, 4, co), dtype=torch.float32, device=x.device)
+    db = torch.zeros(co, dtype=torch.float32, device=x.device)
+    _check(lib().rt_nn_up2_bwd(ctx.h, _ptr(_u16(x, "x")), ci, _ptr(_u16(g, "g")), co, n, h, w, _ptr(_u16(ut, "ut")),
+                               _ptr(dx), _ptr(dw), _ptr(db), _stream()))
+    return dx, dw, db
+
+
+def nn_pool2_fwd(x, ctx=None):
+    ctx = ctx or default_context()
+    n, h, w, c = x.shape
+    y = torch.empty((n, h // 2, w // 2, c), dtype=x.dtype, device=x.device)
+    idx = torch.empty((n, h // 2, w // 2, c), dtype=torch.uint8, device=x.device)
+    _check(lib().rt_nn_pool2(ctx.h, _ptr(_u16(x, "x")), c, n, h, w, _ptr(y), _ptr(idx), None, None, _stream()))
+    return y, idx
+
+
+def nn_pool2_bwd(dy, idx, dx, ctx=None):
+    """dx (n, h, w, c) float32 += unpool(dy)."""
+    ctx = ctx or default_context()
+    n, h, w, c = dx.shape
+    _check(lib().rt_nn_pool2(ctx.h, None, c, n, h, w, None, _ptr(idx), _ptr(dy), _ptr(dx), _stream()))
+    return dx
+
+
+def nn_head_loss(x, wh, bh, t_fg, t_seed, w_seed=1.0, ctx=None):
+    """Returns (loss, dx, dw, db) of the 1x1 head + loss on x (n, h, w, 16) bf16."""
+    ctx = ctx or default_context()
+    n, h, w, _ = x.shape
+    loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    dx = torch.empty((n, h, w, 16), dtype=torch.float32, device=x.device)
+    dw = torch.zeros((2, 16), dtype=torch.float32, device=x.device)
+    db = torch.zeros(2, dtype=torch.float32, device=x.device)
+    _check(lib().rt_nn_head_loss(ctx.h, _ptr(_u16(x, "x")), n, h, w, _ptr(wh), _ptr(bh), _ptr(t_fg), _ptr(t_seed),
+                                 float(w_seed), _ptr(loss), _ptr(dx), _ptr(dw), _ptr(db), _stream()))
+    return loss, dx, dw, db
+
+
+def nn_pack(kind, w, ci, co, ctx=None):
+    """bfloat16 operand copies (fwd, tr) of a float32 weight: kind 0 conv3
+    [co][9][ci], kind 1 up2 [ci][4][co]."""
+    ctx = ctx or default_context()
+    fwd = torch.empty(w.numel(), dtype=torch.int16, device=w.device)
+    tr = torch.empty(w.numel(), dtype=torch.int16, device=w.device)
+    _check(lib().rt_nn_pack(ctx.h, int(kind), _ptr(w), ci, co, _ptr(fwd), _ptr(tr), _stream()))
+    return fwd, tr
+
+
+def nn_prep_input(rgb, ctx=None):
+    ctx = ctx or default_context()
+    _img(rgb, torch.uint8, "rgb", 3)
+    h, w = rgb.shape[:2]
+    x = torch.empty((1, h, w, 8), dtype=torch.int16, device=rgb.device)
+    _check(lib().rt_nn_prep_input(ctx.h, _ptr(rgb), rgb.stride(0), w, h, _ptr(x), _stream()))
+    return x
+
+
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
            "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
            "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds",
-           "rt_profile_stage_name")
+           "rt_profile_stage_name", "rt_unet_param_count", "rt_unet_create", "rt_unet_destroy", "rt_unet_get_params",
+           "rt_unet_set_params", "rt_unet_get_grads", "rt_unet_grad_step", "rt_unet_train_step", "rt_unet_forward",
+           "rt_unet_save", "rt_unet_load", "rt_segment_tile_surrogate", "rt_nn_conv3_fwd", "rt_nn_conv3_dgrad",
+           "rt_nn_conv3_wgrad", "rt_nn_up2_fwd", "rt_nn_up2_bwd", "rt_nn_pool2", "rt_nn_head_loss", "rt_nn_pack",
+           "rt_nn_prep_input")

@@ -50,6 +50,11 @@ def test_params_struct_layout_matches_header():
 
 def test_tile_desc_struct_layout_matches_header():
     from paper_1405_7958_amd import rtseg
-    # ptr, int64, 2 x int32, ptr, ptr, int64, ptr, ptr
-    assert ctypes.sizeof(rtseg.rt_tile_desc) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8
+    # ptr, int64, 2 x int32, ptr, ptr, int64, ptr, ptr, ptr, ptr
+    assert ctypes.sizeof(rtseg.rt_tile_desc) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert rtseg.rt_tile_desc.w.offset == 16 and rtseg.rt_tile_desc.mask_out.offset == 24
+
+
+def test_binding_exports_list_matches_headers():
+    from paper_1405_7958_amd import rtseg
+    assert set(_declared()) == set(rtseg.EXPORTS)
