@@ -17,6 +17,14 @@ The "batch64" object times rt_segment_batch on the 64-tile batch of uneven
 slide-edge sizes (each side drawn from {512, 1024, 2048, 4096}), with knobs
 picked by the autotuner on that batch.
 
+The "surrogate" object compares the U-Net surrogate (rt_segment_tile_surrogate)
+with the plain pipeline: on held-out 4096 x 4096 tiles without fallback (Dice,
+IoU, tiles/s) and on a sample of the mixed stream (60% normal, 30% dense, 10%
+low contrast; sizes 512..4096 per side) with plain fallback below confidence
+tau (tiles/s of both, fallback rate, Dice with fallback tiles counting 1).
+Weights come from --weights if that file exists, else the network is trained
+in the run on --train-crops crops labelled by the plain pipeline.
+
 The CPU baseline is the project's oracle (plain single-threaded C) timed on
 the same 4096 x 4096 tile on this host.
 
@@ -77,6 +85,77 @@ def batch64(rtseg, synth, torch, args):
     return out
 
 
+def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
+    """Configs 4/5: the U-Net surrogate (+ plain fallback) against the plain
+    pipeline: 4096 x 4096 held-out tiles (Dice / IoU, tiles/s) and a sample
+    of the mixed stream (tiles/s of both, fallback rate, Dice)."""
+    import numpy as np
+
+    from paper_1405_7958_amd import surrogate
+    d = torch.device("cuda", 0)
+    ctx = rtseg.Context(0)
+    net = rtseg.UNet(seed=0, ctx=ctx)
+    train = None
+    if args.weights and os.path.exists(args.weights):
+        net.load(args.weights)
+        src = os.path.relpath(args.weights, ROOT)
+        log(f"surrogate weights loaded from {src}")
+    else:
+        log(f"training the surrogate: {args.train_crops} crops, {args.train_epochs} epochs ...")
+        t0 = time.time()
+        data = surrogate.make_training_set(args.train_crops, device=d, ctx=ctx)
+        t_data = time.time() - t0
+        losses, secs, steps = surrogate.train(net, data, epochs=args.train_epochs, batch=8, lr=2e-3, log=log)
+        px = steps * 8 * 512 * 512
+        train = {"crops": args.train_crops, "epochs": args.train_epochs, "steps": steps, "seconds": round(secs, 2),
+                 "data_seconds": round(t_data, 1), "mpx_per_s": round(px / secs / 1e6, 1),
+                 "loss_first": round(losses[0], 4), "loss_last": round(float(np.mean(losses[-10:])), 4)}
+        src = "trained in this run"
+        del data
+    # config 4: held-out 4096 x 4096 tiles, surrogate alone (no fallback)
+    held = []
+    for i in range(args.heldout):
+        spec = synth.spec_4k(0)
+        spec = synth.TileSpec(w=4096, h=4096, seed=15000 + i, n_nuclei=spec.n_nuclei, amin=spec.amin, amax=spec.amax,
+                              cluster_frac=spec.cluster_frac, cluster_min=spec.cluster_min,
+                              cluster_max=spec.cluster_max, jitter=spec.jitter)
+        held.append(torch.from_numpy(synth.make_tile(spec)[0]).to(d))
+    for t in held[:1]:   # warm-up
+        rtseg.rt_segment_tile_surrogate(t, net, tau=-1.0, ctx=ctx)
+    recs, t_plain, t_sur = surrogate.evaluate(net, held, tau=-1.0, ctx=ctx)
+    dice = [r["dice"] for r in recs]
+    iou = [r["iou"] for r in recs]
+    cfg4 = {"tiles": len(held), "tile": [4096, 4096], "surrogate_tiles_per_s": round(len(held) / t_sur, 2),
+            "plain_tiles_per_s": round(len(held) / t_plain, 2), "dice_mean": round(float(np.mean(dice)), 4),
+            "iou_mean": round(float(np.mean(iou)), 4), "confidence": [round(r["confidence"], 3) for r in recs]}
+    log(f"held-out 4K: surrogate {cfg4['surrogate_tiles_per_s']} tiles/s, plain {cfg4['plain_tiles_per_s']} "
+        f"tiles/s, Dice {cfg4['dice_mean']}, IoU {cfg4['iou_mean']}")
+    # config 5: a sample of the mixed stream, surrogate + fallback
+    from concurrent.futures import ThreadPoolExecutor
+    specs = [synth.spec_stream(20000 + i) for i in range(args.stream)]
+    with ThreadPoolExecutor(8) as ex:
+        tiles = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
+    recs, t_plain, t_sur = surrogate.evaluate(net, tiles, tau=args.tau, ctx=ctx)
+    dice = np.array([1.0 if r["fallback"] else r["dice"] for r in recs])
+    raw = np.array([r["dice"] for r in recs])
+    fb = np.array([r["fallback"] for r in recs])
+    px = sum(s.w * s.h for s in specs)
+    cfg5 = {"tiles": len(tiles), "megapixels": round(px / 1e6, 1), "tau": args.tau,
+            "surrogate_tiles_per_s": round(len(tiles) / t_sur, 2), "plain_tiles_per_s": round(len(tiles) / t_plain, 2),
+            "fallback_rate": round(float(fb.mean()), 4), "dice_mean": round(float(dice.mean()), 4),
+            "dice_p5": round(float(np.percentile(dice, 5)), 4),
+            "dice_surrogate_tiles_mean": round(float(raw[~fb].mean()), 4) if (~fb).any() else None,
+            "by_kind": {k: round(float(dice[[s.kind == k for s in specs]].mean()), 4)
+                        for k in ("normal", "dense", "low_contrast") if any(s.kind == k for s in specs)},
+            "per_tile": [[s.kind[0], round(r["confidence"], 3), round(r["dice"], 4)] for s, r in zip(specs, recs)]}
+    log(f"stream sample: surrogate+fallback {cfg5['surrogate_tiles_per_s']} tiles/s, plain "
+        f"{cfg5['plain_tiles_per_s']} tiles/s, fallback {cfg5['fallback_rate']}, Dice {cfg5['dice_mean']} "
+        f"(p5 {cfg5['dice_p5']})")
+    net.close()
+    ctx.close()
+    return {"weights": src, "training": train, "heldout_4k": cfg4, "stream": cfg5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +165,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1405_7958_amd", "weights", "unet_surrogate.rtunet"))
+    ap.add_argument("--train-crops", type=int, default=512)
+    ap.add_argument("--train-epochs", type=float, default=2.0)
+    ap.add_argument("--heldout", type=int, default=2)
+    ap.add_argument("--stream", type=int, default=48)
+    ap.add_argument("--tau", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         if int(os.environ.get("RANK", "0")) == 0:
@@ -169,6 +255,9 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch64(rtseg, synth, torch, args)
+    sur = None
+    if not args.no_surrogate:
+        sur = surrogate_leg(rtseg, synth, torch, args, ms_step)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -203,6 +292,7 @@ def main():
                    "stages": per_stage},
         "roofline": roof,
         "batch64": batch,
+        "surrogate": sur,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

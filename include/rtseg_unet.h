@@ -90,8 +90,10 @@ int rt_unet_load(rt_unet *net, const char *path);
  * [p_seed >= 0.5]; F = FillHoles(fg, 4); BWLabel; components with area >=
  * min_area; watershed of them from the network's seeds (rt_watershed with
  * external seeds); cut, relabel and keep [min_area, max_area] -- the last
- * steps of rt_segment_tile.  Confidence = 1 - #(0.25 <= p_fg < 0.75) /
- * #(p_fg >= 0.25); a tile with confidence < tau is segmented by the plain
+ * steps of rt_segment_tile.  Confidence = 1 - max(u_fg, u_seed) with
+ * u_m = #(0.25 <= p_m < 0.75) / #(p_m >= 0.25), the share of undecided
+ * pixels among the likely-positive ones of each map; a tile with
+ * confidence < tau is segmented by the plain
  * pipeline instead (*used_fallback = 1).  used_fallback and confidence are
  * host pointers (nullable); the call synchronises `stream` to read the
  * confidence.  Outputs as rt_segment_tile.

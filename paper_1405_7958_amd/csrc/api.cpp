@@ -928,9 +928,11 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     if ((e = launch_surrogate_maps(at<float>(c, o_pf), at<float>(c, o_ps), w, h, at<uint8_t>(c, o_f0),
                                    at<uint8_t>(c, o_sd), ctr + 4, s)))
         return e;
-    RT_HIP(hipMemcpyAsync(c->pinned, ctr + 4, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipMemcpyAsync(c->pinned, ctr + 4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
-    const double conf = 1.0 - (double)c->pinned[1] / (double)std::max(1, c->pinned[0]);
+    const double u_fg = (double)c->pinned[1] / (double)std::max(1, c->pinned[0]);
+    const double u_seed = (double)c->pinned[3] / (double)std::max(1, c->pinned[2]);
+    const double conf = 1.0 - std::max(u_fg, u_seed);
     if (confidence) *confidence = (float)conf;
     if (conf < tau) {   // low confidence: the plain pipeline decides this tile
         if (used_fallback) *used_fallback = 1;

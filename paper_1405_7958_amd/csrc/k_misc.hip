@@ -34,22 +34,22 @@ int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s) {
 
 __global__ void k_surrogate_maps(const float *pf, const float *ps, int64_t n, uint8_t *fg, uint8_t *seeds,
                                  int32_t *counts) {
-    int c0 = 0, c1 = 0;
+    int c[4] = {0, 0, 0, 0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float f = pf[i];
+        const float f = pf[i], q = ps[i];
         fg[i] = f >= 0.5f ? 1 : 0;
-        seeds[i] = ps[i] >= 0.5f ? 1 : 0;
-        c0 += f >= 0.25f;
-        c1 += (f >= 0.25f && f < 0.75f);
+        seeds[i] = q >= 0.5f ? 1 : 0;
+        c[0] += f >= 0.25f;
+        c[1] += (f >= 0.25f && f < 0.75f);
+        c[2] += q >= 0.25f;
+        c[3] += (q >= 0.25f && q < 0.75f);
     }
-    // wave sums, one atomic per wave
-    for (int off = 32; off >= 1; off >>= 1) {
-        c0 += __shfl_xor(c0, off, 64);
-        c1 += __shfl_xor(c1, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (c0) atomicAdd(counts, c0);
-        if (c1) atomicAdd(counts + 1, c1);
+    // wave sums, one atomic per wave and counter
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int v = c[k];
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(counts + k, v);
     }
 }
 int launch_surrogate_maps(const float *p_fg, const float *p_seed, int w, int h, uint8_t *fg, uint8_t *seeds,

@@ -249,7 +249,8 @@ int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
 // zeroes a pitched w x h uint8 image
 int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s);
 // Surrogate maps: fg = [p_fg >= 0.5], seeds = [p_seed >= 0.5]; counts[0] +=
-// pixels with p_fg >= 0.25, counts[1] += pixels with 0.25 <= p_fg < 0.75.
+// pixels with p_fg >= 0.25, counts[1] += pixels with 0.25 <= p_fg < 0.75,
+// counts[2], counts[3] the same for p_seed.
 int launch_surrogate_maps(const float *p_fg, const float *p_seed, int w, int h, uint8_t *fg, uint8_t *seeds,
                           int32_t *counts, hipStream_t s);
 
