@@ -130,6 +130,10 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
             "iou_mean": round(float(np.mean(iou)), 4), "confidence": [round(r["confidence"], 3) for r in recs]}
     log(f"held-out 4K: surrogate {cfg4['surrogate_tiles_per_s']} tiles/s, plain {cfg4['plain_tiles_per_s']} "
         f"tiles/s, Dice {cfg4['dice_mean']}, IoU {cfg4['iou_mean']}")
+    if args.stream <= 0:
+        net.close()
+        ctx.close()
+        return {"weights": src, "training": train, "heldout_4k": cfg4, "stream": None}
     # config 5: a sample of the mixed stream, surrogate + fallback
     from concurrent.futures import ThreadPoolExecutor
     specs = [synth.spec_stream(20000 + i) for i in range(args.stream)]

@@ -267,8 +267,8 @@ struct TileIn {
 struct Plan {
     int n = 0, nlev = 0;
     size_t o_dec = 0, o_cl = 0, o_rec = 0, o_cf = 0, o_cc = 0, o_ob = 0, o_aux = 0;
-    size_t o_obj = 0, o_m = 0, o_big = 0, o_ctr = 0, o_slices = 0, slice = 0;
-    int slices = 4;
+    size_t o_obj = 0, o_m = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
+    int slices = 4, mid_slices = 8;
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
     bool any_maps = false;   // some tile asks for its foreground / seed maps
@@ -312,8 +312,9 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
     if ((e = launch_ccl(at<CclArgs>(c, P.o_cc), P.n, P.ccl_total, c->n_cu, s))) return e;
     c->prof_launches[4] += 3;
     if (prof && (e = prof_mark(c, 5, s))) return e;
-    int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big
+    int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big, (kept), n_huge
     ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_big), ctr + 2,
+                at<int32_t>(c, P.o_huge), ctr + 8, at<void>(c, P.o_mid), P.mid_slice, P.mid_slices,
                 at<void>(c, P.o_slices), P.slice, P.slices};
     if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr))) return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
@@ -363,16 +364,18 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     std::vector<Per> per(n);
     Layout L;
     size_t obj_cap = 0;
+    int64_t total_px = 0;
     int big_w = 1, big_h = 1;
     for (int i = 0; i < n; ++i) {
         const TileIn &t = tiles[i];
         const size_t N = (size_t)t.w * t.h;
         Per &q = per[i];
+        total_px += (int64_t)N;
         P.any_maps |= t.fg_out != nullptr;
         q.hq = t.hq_out ? 0 : L.add(N);
         q.R = L.add(N);
         q.F = L.add(N);
-        q.hist = L.add(256 * sizeof(uint32_t));
+        q.hist = L.add(256 * HIST_COPIES * sizeof(uint32_t));
         q.levels = L.add(8 * sizeof(int32_t));
         // level ids, then fill-holes ids, then component ids + 5 statistics
         q.regA = L.add(sizeof(int32_t) * (N + 1) * (size_t)std::max(P.nlev, 6));
@@ -390,9 +393,13 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     P.o_obj = L.add(sizeof(int32_t) * obj_cap);
     P.o_m = L.add(sizeof(int32_t) * obj_cap);
     P.o_big = L.add(sizeof(int32_t) * obj_cap);
+    P.o_huge = L.add(sizeof(int32_t) * obj_cap);
     P.o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     P.slice = al(big_object_bytes(big_w, big_h));
     P.o_slices = L.add(P.slice * P.slices);
+    P.mid_slice = al(mid_object_bytes(big_w, big_h));
+    P.mid_slices = mid_slices_for(total_px);
+    P.o_mid = L.add(P.mid_slice * P.mid_slices);
     // argument records, back to back
     P.o_dec = L.add(sizeof(DeconvImg) * n);
     P.o_cl = L.add(sizeof(CclArgs) * n);
@@ -791,10 +798,13 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     const size_t mo = max_obj_of(w, h);
     Layout L;
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 3);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 4);
     const size_t o_ctr = L.add(16 * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
+    const size_t mid_slice = al(mid_object_bytes(w, h));
+    const int mid_n = mid_slices_for((int64_t)w * h);
+    const size_t o_mid = L.add(mid_slice * mid_n);
     const size_t o_cc = L.add(sizeof(CclArgs));
     const size_t o_ob = L.add(sizeof(ObjArgs));
     if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, L.off - o_cc + 4096))) return e;
@@ -844,7 +854,8 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
         return e;
     if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, at<void>(c, o_slices), slice, 4};
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
+                at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s);
 }
 
@@ -913,10 +924,13 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     const size_t o_f = L.add(N);
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
     const size_t mo = max_obj_of(w, h);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 3);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 4);
     const size_t o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
+    const size_t mid_slice = al(mid_object_bytes(w, h));
+    const int mid_n = mid_slices_for((int64_t)w * h);
+    const size_t o_mid = L.add(mid_slice * mid_n);
     const size_t o_cf = L.add(sizeof(CclArgs));
     const size_t o_cc = L.add(sizeof(CclArgs));
     const size_t o_ob = L.add(sizeof(ObjArgs));
@@ -999,7 +1013,8 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
         return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, at<void>(c, o_slices), slice, 4};
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
+                at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s))) return e;
     if (n_objects_dev) RT_HIP(hipMemcpyAsync(n_objects_dev, ctr + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     return RT_OK;

@@ -71,13 +71,23 @@ __global__ __launch_bounds__(256) void k_deconv(const double *__restrict__ lut, 
     __shared__ uint32_t H[256];
     for (int i = threadIdx.x; i < 768; i += blockDim.x) T[i] = lut[i];
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    // the block's histogram runs over all its chunks of one image and is added
+    // to one of HIST_COPIES copies of that image's histogram when the image
+    // changes (spreads the global atomics over more addresses)
+    const uint32_t copy = (blockIdx.x % HIST_COPIES) * 256u;
+    int cur = -1;
     for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
         const int ii = img_of(imgs, n, u);
+        if (ii != cur) {
+            __syncthreads();
+            if (cur >= 0 && imgs[cur].hist && H[threadIdx.x]) atomicAdd(&imgs[cur].hist[copy + threadIdx.x], H[threadIdx.x]);
+            H[threadIdx.x] = 0;
+            __syncthreads();
+            cur = ii;
+        }
         const DeconvImg im = imgs[ii];
         const int64_t npx = (int64_t)im.w * im.h;
         const int64_t p0 = (u - im.unit0) * DECONV_CHUNK + (int64_t)threadIdx.x * 16;
-        H[threadIdx.x] = 0;
-        __syncthreads();
         const bool dense = im.rgb_pitch == 3LL * im.w && im.hq_pitch == im.w && (!im.ch || im.ch_pitch == im.w) &&
                            ((uintptr_t)im.rgb % 16 == 0) && ((uintptr_t)im.hq % 16 == 0) &&
                            (!im.ch || (uintptr_t)im.ch % 16 == 0);
@@ -128,10 +138,9 @@ __global__ __launch_bounds__(256) void k_deconv(const double *__restrict__ lut, 
                 if (im.hist) atomicAdd(&H[q], 1u);
             }
         }
-        __syncthreads();
-        if (im.hist && H[threadIdx.x]) atomicAdd(&im.hist[threadIdx.x], H[threadIdx.x]);
-        __syncthreads();
     }
+    __syncthreads();
+    if (cur >= 0 && imgs[cur].hist && H[threadIdx.x]) atomicAdd(&imgs[cur].hist[copy + threadIdx.x], H[threadIdx.x]);
 }
 
 int launch_deconv_lut(const StainParams &sp, double *lut, hipStream_t s) {

@@ -44,19 +44,26 @@ __global__ void k_surrogate_maps(const float *pf, const float *ps, int64_t n, ui
         c[2] += q >= 0.25f;
         c[3] += (q >= 0.25f && q < 0.75f);
     }
-    // wave sums, one atomic per wave and counter
+    // wave sums, then block sums in LDS: one atomic per block and counter
+    __shared__ int red[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int v = c[k];
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if ((threadIdx.x & 63) == 0 && v) atomicAdd(counts + k, v);
+        if (lane == 0) red[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int v = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (v) atomicAdd(counts + threadIdx.x, v);
     }
 }
 int launch_surrogate_maps(const float *p_fg, const float *p_seed, int w, int h, uint8_t *fg, uint8_t *seeds,
                           int32_t *counts, hipStream_t s) {
     const int64_t n = (int64_t)w * h;
     if (n <= 0) return RT_OK;
-    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_surrogate_maps, dim3(grid), dim3(256), 0, s, p_fg, p_seed, n, fg, seeds, counts);
     return hip_fail(hipGetLastError(), "k_surrogate_maps");
 }

@@ -687,16 +687,31 @@ __global__ __launch_bounds__(WAVE) void k_objects_m(const ObjArgs *args, ObjList
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, ObjLists L) {
+// global-memory class: one wave per component on a scratch slice.  Two
+// passes: crops up to mid_max_px on many moderate slices, deferring larger
+// ones to a second pass on a few slices sized for the whole tile.
+struct BigPass {
+    const int32_t *list, *n;
+    int32_t *defer, *n_defer;   // nullable
+    char *scratch;
+    size_t slice_bytes;
+    int64_t max_px;             // crops above this are deferred (when defer is set)
+};
+
+__global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, BigPass P) {
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
-    const int nbig = *L.n_big;
-    char *base = (char *)L.big_scratch + L.big_slice_bytes * blockIdx.x;
+    const int nbig = *P.n;
+    char *base = P.scratch + P.slice_bytes * blockIdx.x;
     for (int o = blockIdx.x; o < nbig; o += gridDim.x) {
-        const int code = L.big[o];
+        const int code = P.list[o];
         const ObjArgs a = args[code >> 25];
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
+        if (P.defer && (int64_t)q.n > P.max_px) {
+            if (threadIdx.x == 0) P.defer[atomicAdd(P.n_defer, 1)] = code;
+            continue;
+        }
         Crop<int64_t> m;
         m.B = (int64_t *)base;
         m.dq = (int32_t *)(m.B + q.n);
@@ -712,8 +727,11 @@ __global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, ObjLi
     }
 }
 
-// bytes of global scratch one block needs for the largest crop of a w x h tile
-size_t big_object_bytes(int w, int h) { return (size_t)h * (size_t)(w | 1) * (8 + 4 + 4 + 1) + 256; }
+// bytes of global scratch one block needs for a crop of n = stride x rows pixels
+static size_t crop_bytes(int64_t n) { return (size_t)n * (8 + 4 + 4 + 1) + 256; }
+// ... and for the largest crop of a w x h tile
+size_t big_object_bytes(int w, int h) { return crop_bytes((int64_t)h * (w | 1)); }
+size_t mid_object_bytes(int w, int h) { return std::min(big_object_bytes(w, h), crop_bytes(MID_MAX_PX)); }
 
 int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStream_t s, hipEvent_t before_big) {
     const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
@@ -721,12 +739,16 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
     RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    if (L.big_slices < 1) {
+    if (L.big_slices < 1 || L.mid_slices < 1) {
         set_error("objects: no global scratch slice");
         return RT_ENOMEM;
     }
     if (before_big) RT_HIP(hipEventRecord(before_big, s));
-    hipLaunchKernelGGL(k_objects_big, dim3(L.big_slices), dim3(WAVE), 0, s, args_dev, L);
+    BigPass mid{L.big, L.n_big, L.huge, L.n_huge, (char *)L.mid_scratch, L.mid_slice_bytes, MID_MAX_PX};
+    hipLaunchKernelGGL(k_objects_big, dim3(L.mid_slices), dim3(WAVE), 0, s, args_dev, mid);
+    RT_HIP(hipGetLastError());
+    BigPass huge{L.huge, L.n_huge, nullptr, nullptr, (char *)L.big_scratch, L.big_slice_bytes, 0};
+    hipLaunchKernelGGL(k_objects_big, dim3(L.big_slices), dim3(WAVE), 0, s, args_dev, huge);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

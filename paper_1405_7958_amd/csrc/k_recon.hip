@@ -351,15 +351,20 @@ __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, i
         return;
     }
     const BatchAux a = aux[i];
-    for (int k = threadIdx.x; k < 256; k += blockDim.x) a.hist[k] = 0;
+    for (int k = threadIdx.x; k < 256 * HIST_COPIES; k += blockDim.x) a.hist[k] = 0;
     if (threadIdx.x == 0) *a.kept = 0;
 }
 
 __global__ void k_batch_levels(const BatchAux *aux, int n_levels) {
-    if (threadIdx.x == 0) {
-        const BatchAux a = aux[blockIdx.x];
-        select_levels(a.hist, n_levels, a.levels);
+    __shared__ uint32_t H[256];
+    const BatchAux a = aux[blockIdx.x];
+    for (int v = threadIdx.x; v < 256; v += blockDim.x) {
+        uint32_t s = 0;
+        for (int c = 0; c < HIST_COPIES; ++c) s += a.hist[c * 256 + v];
+        H[v] = s;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) select_levels(H, n_levels, a.levels);
 }
 
 __global__ void k_batch_end(const BatchAux *aux, int n) {

@@ -9,6 +9,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -114,11 +115,12 @@ struct DeconvImg {
     int64_t hq_pitch;
     float *ch;                     // nullable
     int64_t ch_pitch;
-    uint32_t *hist;                // nullable: 256 bins
+    uint32_t *hist;                // nullable: HIST_COPIES x 256 bins (their sum is the histogram)
     int w, h;
     int64_t unit0;                 // first 4096-pixel chunk of this image
 };
 constexpr int DECONV_CHUNK = 4096;
+constexpr int HIST_COPIES = 16;
 int launch_deconv_lut(const StainParams &sp, double *lut, hipStream_t s);
 int launch_deconv(const double *lut, double scale, const DeconvImg *imgs_dev, int n, int64_t total_units,
                   int n_cu, hipStream_t s);
@@ -195,7 +197,7 @@ int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int
 
 // Per-image bookkeeping of a segmentation batch.
 struct BatchAux {
-    uint32_t *hist;                // 256 bins of Hq
+    uint32_t *hist;                // HIST_COPIES x 256 bins of Hq
     int32_t *levels;               // threshold levels of the connectivity bound
     int32_t *kept;                 // kept objects (device)
     int32_t *n_dev;                // nullable caller counter
@@ -235,15 +237,25 @@ struct ObjArgs {                   // one record per image
 struct ObjLists {                  // shared by the batch; entries are image << 25 | root
     const int32_t *obj, *n_obj;
     int32_t *list_m, *n_m;         // deferred to the medium LDS class
-    int32_t *big, *n_big;          // deferred to the global-memory class
-    void *big_scratch;             // global scratch slices for the global-memory class
+    int32_t *big, *n_big;          // deferred to the global-memory classes
+    int32_t *huge, *n_huge;        // crops above MID_MAX_PX pixels
+    void *mid_scratch;             // many slices for crops up to MID_MAX_PX pixels
+    size_t mid_slice_bytes;
+    int mid_slices;
+    void *big_scratch;             // a few slices for the largest crop of the batch
     size_t big_slice_bytes;
     int big_slices;
 };
+constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
 // `before_big` (nullable) is recorded on `s` before the global-memory class starts.
 int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hipStream_t s,
                    hipEvent_t before_big = nullptr);
 size_t big_object_bytes(int w, int h);   // one slice for the largest crop of a w x h image
+size_t mid_object_bytes(int w, int h);   // one slice for a crop of at most MID_MAX_PX pixels
+// number of mid slices for a launch group of `pixels` pixels
+inline int mid_slices_for(int64_t pixels) {
+    return (int)std::max<int64_t>(8, std::min<int64_t>(128, pixels / 65536));
+}
 
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
 // zeroes a pitched w x h uint8 image
