@@ -267,7 +267,7 @@ struct TileIn {
 struct Plan {
     int n = 0, nlev = 0;
     size_t o_dec = 0, o_cl = 0, o_rec = 0, o_cf = 0, o_cc = 0, o_ob = 0, o_aux = 0;
-    size_t o_obj = 0, o_m = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
+    size_t o_obj = 0, o_m = 0, o_l = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
     int slices = 4, mid_slices = 8;
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
@@ -313,9 +313,9 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
     c->prof_launches[4] += 3;
     if (prof && (e = prof_mark(c, 5, s))) return e;
     int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big, (kept), n_huge
-    ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_big), ctr + 2,
-                at<int32_t>(c, P.o_huge), ctr + 8, at<void>(c, P.o_mid), P.mid_slice, P.mid_slices,
-                at<void>(c, P.o_slices), P.slice, P.slices};
+    ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_l), ctr + 9,
+                at<int32_t>(c, P.o_big), ctr + 2, at<int32_t>(c, P.o_huge), ctr + 8, at<void>(c, P.o_mid),
+                P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
     if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr))) return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     c->prof_launches[5] += 2;
@@ -394,6 +394,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     P.o_m = L.add(sizeof(int32_t) * obj_cap);
     P.o_big = L.add(sizeof(int32_t) * obj_cap);
     P.o_huge = L.add(sizeof(int32_t) * obj_cap);
+    P.o_l = L.add(sizeof(int32_t) * obj_cap);
     P.o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     P.slice = al(big_object_bytes(big_w, big_h));
     P.o_slices = L.add(P.slice * P.slices);
@@ -798,7 +799,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     const size_t mo = max_obj_of(w, h);
     Layout L;
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 4);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 5);
     const size_t o_ctr = L.add(16 * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -854,7 +855,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
         return e;
     if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
                 at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s);
 }
@@ -924,7 +925,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     const size_t o_f = L.add(N);
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
     const size_t mo = max_obj_of(w, h);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 4);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 5);
     const size_t o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -1013,7 +1014,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
         return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
+    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
                 at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s))) return e;
     if (n_objects_dev) RT_HIP(hipMemcpyAsync(n_objects_dev, ctr + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));

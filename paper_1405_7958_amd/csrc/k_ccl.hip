@@ -75,6 +75,19 @@ __device__ __forceinline__ int gfind(int32_t *ids, int x) {
     return x;
 }
 
+// Read-only find for the flatten pass: the forest no longer changes once the
+// merge kernel has finished, so plain loads suffice and no path is rewritten
+// (rewriting with atomics made every tile of a frame-spanning component
+// contend on the same few nodes).
+__device__ __forceinline__ int gfind_ro(const int32_t *ids, int x) {
+    int p = ids[x];
+    while (p != x) {
+        x = p;
+        p = ids[x];
+    }
+    return x;
+}
+
 __device__ __forceinline__ void gunite(int32_t *ids, int a, int b) {
     for (;;) {
         a = gfind(ids, a);
@@ -438,7 +451,7 @@ __device__ void resolve_roots(const CclArgs &A, const Tile &t, const uint64_t *r
         const int pv = P[li];
         if ((pv & LIDX) != li) continue;
         const int id = gid(A, t, s, y);
-        P[li] = -((pv & TOUCH_BIT) ? gfind(ids, id) : id) - 1;
+        P[li] = -((pv & TOUCH_BIT) ? gfind_ro(ids, id) : id) - 1;
     }
     __syncthreads();
 }

@@ -73,21 +73,21 @@ struct Conv3K {
     int dgrad;
 };
 
-template <int TN>
+template <int TN, int TM>
 __global__ __launch_bounds__(256) void k_conv3(Conv3K a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t P = (int64_t)a.n * a.h * a.w;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 32;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * TM);
     if (base >= P) return;
     const int cin = a.c0 + a.c1;
     const int K = 9 * cin;
     const int r = lane & 15, kg = lane >> 4;
     const int hw = a.h * a.w;
-    int img[2], py[2], px[2];
-    bool valid[2];
+    int img[TM], py[TM], px[TM];
+    bool valid[TM];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < TM; ++mt) {
         const int64_t p = base + mt * 16 + r;
         valid[mt] = p < P;
         const int64_t pp = valid[mt] ? p : 0;
@@ -96,20 +96,20 @@ __global__ __launch_bounds__(256) void k_conv3(Conv3K a) {
         py[mt] = rem / a.w;
         px[mt] = rem - py[mt] * a.w;
     }
-    f32x4 acc[2][TN];
+    f32x4 acc[TM][TN];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < TM; ++mt)
 #pragma unroll
         for (int t = 0; t < TN; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kb = 0; kb < K; kb += 32) {
         const int k0 = kb + kg * 8;
-        bf16x8 A[2], B[TN];
+        bf16x8 A[TM], B[TN];
         if (k0 < K) {
             const int tap = k0 / cin;
             const int ci = k0 - tap * cin;
             const int dy = a.sgn * (tap / 3 - 1), dx = a.sgn * (tap % 3 - 1);
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
+            for (int mt = 0; mt < TM; ++mt) {
                 const int sy = py[mt] + dy, sx = px[mt] + dx;
                 if (valid[mt] && sy >= 0 && sy < a.h && sx >= 0 && sx < a.w) {
                     const int64_t sp = ((int64_t)img[mt] * a.h + sy) * a.w + sx;
@@ -121,18 +121,19 @@ __global__ __launch_bounds__(256) void k_conv3(Conv3K a) {
 #pragma unroll
             for (int t = 0; t < TN; ++t) B[t] = load8(a.wk + (int64_t)(t * 16 + r) * K + k0);
         } else {
-            A[0] = A[1] = zero8();
+#pragma unroll
+            for (int mt = 0; mt < TM; ++mt) A[mt] = zero8();
 #pragma unroll
             for (int t = 0; t < TN; ++t) B[t] = zero8();
         }
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < TM; ++mt)
 #pragma unroll
             for (int t = 0; t < TN; ++t) acc[mt][t] = mfma(A[mt], B[t], acc[mt][t]);
     }
     // D layout: lane holds rows 4*kg + e of column r
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < TM; ++mt) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t p = base + mt * 16 + kg * 4 + e;
@@ -163,16 +164,20 @@ static int launch_conv3(const Conv3K &a, hipStream_t s) {
     }
     const int64_t P = (int64_t)a.n * a.h * a.w;
     if (P <= 0) return RT_OK;
-    const dim3 grid((unsigned)((P + 127) / 128));
-    switch (a.nout / 16) {
-        case 1: hipLaunchKernelGGL(k_conv3<1>, grid, dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_conv3<2>, grid, dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_conv3<3>, grid, dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_conv3<4>, grid, dim3(256), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_conv3<5>, grid, dim3(256), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_conv3<6>, grid, dim3(256), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_conv3<7>, grid, dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_conv3<8>, grid, dim3(256), 0, s, a); break;
+    // a wave computes 16*TM pixels x nout channels; wider outputs take more
+    // pixels per wave so that each weight fragment feeds more matrix ops
+    const int tn = a.nout / 16;
+    const int tm = tn >= 4 ? 4 : 2;
+    const dim3 grid((unsigned)((P + 64 * tm - 1) / (64 * tm)));
+    switch (tn) {
+        case 1: hipLaunchKernelGGL((k_conv3<1, 2>), grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv3<2, 2>), grid, dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv3<3, 2>), grid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_conv3<4, 4>), grid, dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_conv3<5, 4>), grid, dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_conv3<6, 4>), grid, dim3(256), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_conv3<7, 4>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv3<8, 4>), grid, dim3(256), 0, s, a); break;
     }
     return hip_fail(hipGetLastError(), "k_conv3");
 }

@@ -38,6 +38,7 @@ constexpr int RS_ = 32;                 // small class: crop <= 32 x 32
 constexpr int RM_ = 64;                 // medium class: crop <= 64 x 64
 constexpr int CAP_S = (RS_ + 1) * RS_;  // plane size with the odd row stride
 constexpr int CAP_M = (RM_ + 1) * RM_;
+constexpr int CAP_L = 97 * 96;           // large class: crops of at most 9312 px (about 96 x 96) in LDS
 constexpr int HBINS = 256;
 constexpr int NEGV = INT_MIN;
 constexpr int GINF = 1 << 28;
@@ -680,10 +681,31 @@ __global__ __launch_bounds__(WAVE) void k_objects_m(const ObjArgs *args, ObjList
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
         if (q.cw > RM_ || q.ch > RM_) {
-            if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
+            if (threadIdx.x == 0) {
+                if (q.n <= CAP_L)
+                    L.list_l[atomicAdd(L.n_l, 1)] = code;
+                else
+                    L.big[atomicAdd(L.n_big, 1)] = code;
+            }
             continue;
         }
         process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist, Ts);
+    }
+}
+
+// large class: crops up to CAP_L pixels in LDS, scans without the register
+// path (one workgroup per CU for LDS)
+__global__ __launch_bounds__(WAVE) void k_objects_l(const ObjArgs *args, ObjLists L) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int red;
+    __shared__ int hist[HBINS + 1];
+    const int nobj = *L.n_l;
+    for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
+        const int code = L.list_l[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
+        const CropGeom q = crop_geom(a, g);
+        process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist, nullptr);
     }
 }
 
@@ -738,6 +760,14 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, args_dev, L);
     RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
+    RT_HIP(hipGetLastError());
+    const size_t lds_l = (size_t)CAP_L * 13;
+    static bool lds_l_set = false;
+    if (!lds_l_set) {
+        RT_HIP(hipFuncSetAttribute((const void *)k_objects_l, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l));
+        lds_l_set = true;
+    }
+    hipLaunchKernelGGL(k_objects_l, dim3(n_cu), dim3(WAVE), lds_l, s, args_dev, L);
     RT_HIP(hipGetLastError());
     if (L.big_slices < 1 || L.mid_slices < 1) {
         set_error("objects: no global scratch slice");

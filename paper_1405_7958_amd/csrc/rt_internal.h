@@ -237,6 +237,7 @@ struct ObjArgs {                   // one record per image
 struct ObjLists {                  // shared by the batch; entries are image << 25 | root
     const int32_t *obj, *n_obj;
     int32_t *list_m, *n_m;         // deferred to the medium LDS class
+    int32_t *list_l, *n_l;         // deferred to the large LDS class
     int32_t *big, *n_big;          // deferred to the global-memory classes
     int32_t *huge, *n_huge;        // crops above MID_MAX_PX pixels
     void *mid_scratch;             // many slices for crops up to MID_MAX_PX pixels

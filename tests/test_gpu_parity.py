@@ -242,6 +242,33 @@ def test_watershed_big_object(rt, oracle):
     assert_equal(to_np(lab), elab, "watershed big object")
 
 
+def test_watershed_every_object_class(rt, oracle):
+    """Components of every size class in one image: small (crop <= 32^2),
+    medium (<= 64^2), large LDS (<= 9312 px), global mid (<= 256^2) and the
+    whole-tile global class; each made of two or three overlapping discs so
+    the watershed has several seeds to split."""
+    d = dev()
+    yy, xx = np.mgrid[0:760, 0:900]
+
+    def discs(*cs):
+        m = np.zeros((760, 900), bool)
+        for cy, cx, r in cs:
+            m |= (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+        return m
+
+    fg = (discs((20, 20, 9), (20, 36, 8)) |                      # small
+          discs((60, 60, 18), (60, 95, 15)) |                    # medium
+          discs((150, 60, 26), (150, 120, 24)) |                 # large (LDS)
+          discs((330, 120, 70), (330, 250, 60), (380, 190, 40)) |  # global, mid slices
+          discs((560, 560, 150), (560, 760, 120), (700, 650, 50)))  # global, whole-tile slices
+    fg = fg.astype(np.uint8)
+    say("watershed classes")
+    lab, mask = rt.rt_watershed(to_dev(fg, d))
+    elab, emask = oracle.watershed(fg)
+    assert_equal(to_np(lab), elab, "watershed object classes")
+    assert_equal(to_np(mask), emask, "watershed object classes mask")
+
+
 def test_watershed_all_foreground(rt, oracle):
     d = dev()
     fg = np.ones((40, 50), np.uint8)
