@@ -5,13 +5,18 @@ nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20,
 seed 0), input resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-batch] [--copy-calibration MB]
+                  [--no-batch] [--no-surrogate] [--no-tune] [--copy-calibration MB]
+
+The launch knobs of the 4096 x 4096 tile are picked first by the autotuner
+(graph replay excluded, so that stage timing stays available).
 
 Roofline: the dominant kernel is the reconstruction round kernel (most of the
-GPU time of a tile).  The library records a pair of HIP events around every
-round launch on its own stream during the timed steps, and counts the 62 x 62
-tiles the rounds process; achieved = tile visits x 11532 algorithmic bytes
-(read Hq and R, write R: 3 bytes per interior pixel) / summed kernel time.
+GPU time of a tile).  After the timed steps, the same number of steps runs
+again with the library's stage timing on: HIP events at every stage boundary
+and a pair around every round launch, on the call's stream, plus a count of
+the 62 x 62 tiles the rounds process; achieved = tile visits x 11532
+algorithmic bytes (read Hq and R, write R: 3 bytes per interior pixel) /
+summed kernel time.  `value` comes from the uninstrumented steps.
 
 The "batch64" object times rt_segment_batch on the 64-tile batch of uneven
 slide-edge sizes (each side drawn from {512, 1024, 2048, 4096}), with knobs
@@ -170,6 +175,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default knobs for the 4096x4096 tile")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1405_7958_amd", "weights", "unet_surrogate.rtunet"))
     ap.add_argument("--train-crops", type=int, default=512)
     ap.add_argument("--train-epochs", type=float, default=2.0)
@@ -208,26 +214,42 @@ def main():
     out = (mask, lab, n, None)
     params = rtseg.default_params()
 
+    knobs = None
+    if not args.no_tune:
+        from paper_1405_7958_amd import tune
+        res = tune.autotune([rgb], ctx=ctx, reps=3, cache=None, allow_graph=False)
+        knobs = res["knobs"]
+        log(f"autotuned knobs for the 4096x4096 tile: {knobs} ({res['ms']:.3f} ms, {res['seconds']} s)")
     for i in range(args.warmup):
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    rtseg.rt_profile_enable(True, ctx)
-    rtseg.rt_profile_read(ctx)          # discard
-    rtseg.rt_profile_recon_rounds(ctx)  # discard
-    torch.cuda.synchronize()
+    # the timed steps run without instrumentation ...
     t0 = time.perf_counter()
     for i in range(args.steps):
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rtseg.rt_profile_enable(False, ctx)
-    calls, stages = rtseg.rt_profile_read(ctx)
-    r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
     n_obj = int(n.item())
     ms_step = (t1 - t0) * 1e3 / args.steps
     tiles_s = args.steps / (t1 - t0)
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/tile, {tiles_s:.1f} tiles/s, {n_obj} objects")
+    # ... then the same steps again with the library's HIP events at every
+    # stage boundary and around every reconstruction round launch
+    rtseg.rt_profile_enable(True, ctx)
+    rtseg.rt_profile_read(ctx)          # discard
+    rtseg.rt_profile_recon_rounds(ctx)  # discard
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rtseg.rt_profile_enable(False, ctx)
+    calls, stages = rtseg.rt_profile_read(ctx)
+    r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
+    ms_prof = (t3 - t2) * 1e3 / args.steps
+    log(f"instrumented steps: {ms_prof:.3f} ms/tile")
 
     N = w * h
     fg = int((lab > 0).sum().item())
@@ -293,7 +315,7 @@ def main():
                                "8000 nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20, seed 0",
                    "tile": [h, w], "objects": n_obj, "foreground_px": fg,
                    "pipeline_floor_frac": round(8 * N * tiles_s / (HBM_PEAK_GBS * 1e9), 5),
-                   "stages": per_stage},
+                   "knobs": knobs, "ms_per_step_instrumented": round(ms_prof, 4), "stages": per_stage},
         "roofline": roof,
         "batch64": batch,
         "surrogate": sur,

@@ -206,6 +206,12 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *                             the worklist counter; default 8
  *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;
  *                             default 64
+ *   "objects_path"      0..2  routing of components to the per-object kernels:
+ *                             0 crops <= 32^2 and <= 64^2 to the register-scan
+ *                             classes, up to 9312 px to the LDS class, larger
+ *                             to global memory; 1 skips the 64^2 register
+ *                             class; 2 sends every crop that fits to the LDS
+ *                             class; default 0
  *   "graph"             0|1   rt_segment_tile / rt_segment_batch replay the
  *                             launch sequence from captured HIP graphs (cached
  *                             per tile-size list, up to 4); default 0.  The

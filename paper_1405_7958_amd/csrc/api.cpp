@@ -316,6 +316,7 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
     ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_l), ctr + 9,
                 at<int32_t>(c, P.o_big), ctr + 2, at<int32_t>(c, P.o_huge), ctr + 8, at<void>(c, P.o_mid),
                 P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
+    OL.path = c->knobs.objects_path;
     if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr))) return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     c->prof_launches[5] += 2;
@@ -539,6 +540,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     }
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
+                                c->knobs.objects_path,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -1033,6 +1035,9 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     } else if (n == "recon_max_sweeps") {
         CHECK(value >= 1 && value <= 1024, "rt_set_knob: recon_max_sweeps must be 1..1024");
         c->knobs.recon_max_sweeps = value;
+    } else if (n == "objects_path") {
+        CHECK(value >= 0 && value <= 2, "rt_set_knob: objects_path must be 0..2");
+        c->knobs.objects_path = value;
     } else if (n == "graph") {
         CHECK(value == 0 || value == 1, "rt_set_knob: graph must be 0 or 1");
         c->knobs.graph = value;
@@ -1055,6 +1060,8 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.recon_round_batch;
     else if (n == "recon_max_sweeps")
         *value = c->knobs.recon_max_sweeps;
+    else if (n == "objects_path")
+        *value = c->knobs.objects_path;
     else if (n == "graph")
         *value = c->knobs.graph;
     else if (n == "graph_rounds")

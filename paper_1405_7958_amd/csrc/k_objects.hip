@@ -661,8 +661,15 @@ __global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjL
             erase_object(a, g, q);
             continue;
         }
-        if (q.cw > RS_ || q.ch > RS_) {
-            if (threadIdx.x == 0) L.list_m[atomicAdd(L.n_m, 1)] = code;
+        if (L.path == 2 || q.cw > RS_ || q.ch > RS_) {
+            if (threadIdx.x == 0) {
+                if (L.path == 0)
+                    L.list_m[atomicAdd(L.n_m, 1)] = code;
+                else if (q.n <= CAP_L)
+                    L.list_l[atomicAdd(L.n_l, 1)] = code;
+                else
+                    L.big[atomicAdd(L.n_big, 1)] = code;
+            }
             continue;
         }
         process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist, Ts);

@@ -54,6 +54,7 @@ struct Knobs {
     int recon_levels = 3;        // threshold levels of the connectivity lower bound
     int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
+    int objects_path = 0;        // per-object class routing (ObjLists::path)
     int graph = 0;               // replay segmentation batches from captured HIP graphs
     int graph_rounds = 24;       // reconstruction rounds inside the first graph
 };
@@ -246,6 +247,9 @@ struct ObjLists {                  // shared by the batch; entries are image << 
     void *big_scratch;             // a few slices for the largest crop of the batch
     size_t big_slice_bytes;
     int big_slices;
+    int path = 0;                  // 0: small / medium register classes, then large LDS;
+                                   // 1: small register class, then large LDS;
+                                   // 2: large LDS class for every crop that fits
 };
 constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
 // `before_big` (nullable) is recorded on `s` before the global-memory class starts.

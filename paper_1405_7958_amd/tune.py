@@ -3,8 +3,9 @@
 The knobs (rt_set_knob) change only speed, never results: the number of
 threshold levels of the connectivity bound that seeds ReconToNuclei, the
 propagation rounds launched between two host checks, the in-tile sweep
-budget, and whether a batch replays from captured HIP graphs (with how many
-reconstruction rounds inside the first graph).  The tuner times
+budget, the routing of components to the per-object kernels, and whether a
+batch replays from captured HIP graphs (with how many reconstruction rounds
+inside the first graph).  The tuner times
 rt_segment_batch on a sample of the caller's own tiles with coordinate
 descent over those knobs and keeps the fastest setting, cached in a JSON file
 keyed by device and tile-size signature.
@@ -27,8 +28,9 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_c
 
 SPACE = {
     "recon_levels": [0, 1, 2, 3, 4, 6, 8],
-    "recon_round_batch": [4, 8, 16],
-    "recon_max_sweeps": [32, 64, 128],
+    "recon_round_batch": [4, 8, 16, 32],
+    "recon_max_sweeps": [16, 32, 64, 128],
+    "objects_path": [0, 1, 2],
 }
 
 
@@ -65,12 +67,13 @@ def current(ctx=None) -> dict:
     return {k: rtseg.rt_get_knob(k, ctx=ctx) for k in rtseg.KNOBS}
 
 
-def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEFAULT_CACHE, verbose=False) -> dict:
+def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEFAULT_CACHE, verbose=False,
+             allow_graph: bool = True) -> dict:
     """Tunes the knobs of `ctx` for batches like `rgbs` (a list of device
     tiles) and leaves the best setting applied.  Returns
     {"knobs": ..., "ms": ..., "trials": [...]}."""
     ctx = ctx or rtseg.default_context(rgbs[0].device.index)
-    key = signature(rgbs)
+    key = signature(rgbs) + ("" if allow_graph else "|nograph")
     if cache and os.path.exists(cache):
         try:
             with open(cache) as f:
@@ -109,7 +112,7 @@ def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEF
     run()
     torch.cuda.synchronize()
     rounds = max(1, rtseg.rt_get_knob("last_rounds", ctx=ctx))
-    for budget in sorted({rounds, rounds + 2}):
+    for budget in (sorted({rounds, rounds + 2}) if allow_graph else []):
         cand = dict(best, graph=1, graph_rounds=budget)
         apply(cand, ctx)
         ms = _time(run, reps)
