@@ -267,7 +267,7 @@ struct TileIn {
 struct Plan {
     int n = 0, nlev = 0;
     size_t o_dec = 0, o_cl = 0, o_rec = 0, o_cf = 0, o_cc = 0, o_ob = 0, o_aux = 0;
-    size_t o_obj = 0, o_m = 0, o_l = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
+    size_t o_obj = 0, o_s = 0, o_m = 0, o_l = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
     int slices = 4, mid_slices = 8;
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
@@ -276,6 +276,18 @@ struct Plan {
 };
 
 constexpr int kSharedCounters = 16;
+
+// The context's side stream and fork/join events (created on first use,
+// default priority).
+int side_streams(rt_ctx *c, ObjStreams &par) {
+    if (!c->side_stream) RT_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    if (!c->fork_ev) RT_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    if (!c->join_ev) RT_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    par.side = c->side_stream;
+    par.fork = c->fork_ev;
+    par.join = c->join_ev;
+    return RT_OK;
+}
 
 // Stages 1-2a: deconvolution + histogram, level choice and the frame
 // connectivity bound (or the bare frame marker).
@@ -303,7 +315,7 @@ int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s
 
 // Stages 3-8: FillHoles, BWLabel with statistics, the per-object stage and
 // the object counts.
-int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
+int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool capturing = false) {
     int e;
     if (prof && (e = prof_mark(c, 3, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, P.o_cf), P.n, P.ccl_total, c->n_cu, s))) return e;
@@ -313,11 +325,15 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof) {
     c->prof_launches[4] += 3;
     if (prof && (e = prof_mark(c, 5, s))) return e;
     int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big, (kept), n_huge
-    ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_m), ctr + 1, at<int32_t>(c, P.o_l), ctr + 9,
-                at<int32_t>(c, P.o_big), ctr + 2, at<int32_t>(c, P.o_huge), ctr + 8, at<void>(c, P.o_mid),
-                P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
+    ObjLists OL{at<int32_t>(c, P.o_obj), ctr, at<int32_t>(c, P.o_s), ctr + 10, at<int32_t>(c, P.o_m), ctr + 1,
+                at<int32_t>(c, P.o_l), ctr + 9, at<int32_t>(c, P.o_big), ctr + 2, at<int32_t>(c, P.o_huge), ctr + 8,
+                at<void>(c, P.o_mid), P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
     OL.path = c->knobs.objects_path;
-    if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr))) return e;
+    ObjStreams par{};
+    if (!capturing && (e = side_streams(c, par))) return e;
+    if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr,
+                            capturing ? nullptr : &par)))
+        return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     c->prof_launches[5] += 2;
     c->prof_launches[6] += 2;
@@ -396,6 +412,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     P.o_big = L.add(sizeof(int32_t) * obj_cap);
     P.o_huge = L.add(sizeof(int32_t) * obj_cap);
     P.o_l = L.add(sizeof(int32_t) * obj_cap);
+    P.o_s = L.add(sizeof(int32_t) * obj_cap);
     P.o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     P.slice = al(big_object_bytes(big_w, big_h));
     P.o_slices = L.add(P.slice * P.slices);
@@ -575,7 +592,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
                 return e2;
             },
             &g->a);
-        if (!e) e = capture(c, [&](hipStream_t cs) { return enqueue_back(c, P, cs, false); }, &g->b);
+        if (!e) e = capture(c, [&](hipStream_t cs) { return enqueue_back(c, P, cs, false, true); }, &g->b);
         if (e) {
             destroy_graph(*g);
             return e;
@@ -647,6 +664,9 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->staging_done) (void)hipEventDestroy(c->staging_done);
     for (GraphPair &g : c->graphs) destroy_graph(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->round_events) (void)hipEventDestroy(ev);
     if (c->prof_visits) (void)hipFree(c->prof_visits);
@@ -801,7 +821,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     const size_t mo = max_obj_of(w, h);
     Layout L;
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 5);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 6);
     const size_t o_ctr = L.add(16 * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -857,9 +877,11 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
         return e;
     if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
-                at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
-    return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s);
+    ObjLists OL{obj, ctr, obj + 5 * mo, ctr + 10, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2,
+                obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
+    ObjStreams par{};
+    if ((e = side_streams(c, par))) return e;
+    return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, nullptr, &par);
 }
 
 int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h,
@@ -927,7 +949,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     const size_t o_f = L.add(N);
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
     const size_t mo = max_obj_of(w, h);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 5);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 6);
     const size_t o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -1016,9 +1038,11 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
         return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
     if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    ObjLists OL{obj, ctr, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2, obj + 3 * mo, ctr + 8,
-                at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
-    if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s))) return e;
+    ObjLists OL{obj, ctr, obj + 5 * mo, ctr + 10, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2,
+                obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
+    ObjStreams par{};
+    if ((e = side_streams(c, par))) return e;
+    if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, nullptr, &par))) return e;
     if (n_objects_dev) RT_HIP(hipMemcpyAsync(n_objects_dev, ctr + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     return RT_OK;
 }

@@ -644,32 +644,66 @@ __device__ __forceinline__ Crop<int32_t> lds_crop(unsigned char *smem, const Cro
 
 constexpr int CODE_MASK = (1 << 25) - 1;   // component code = image << 25 | root
 
-// small class: reads the component list, erases components below the first
-// area threshold, defers crops above 32 x 32
+// Routes every registered component to its class list (one thread per
+// component, appends aggregated per wave): components below the first area
+// threshold and crops up to 32 x 32 to the small class (which erases the
+// former), up to 64 x 64 to the medium class, up to CAP_L pixels to the large
+// LDS class, the rest to global memory.
+__device__ __forceinline__ void wave_append(bool want, int code, int32_t *list, int32_t *cnt) {
+    const uint64_t m = __ballot(want);
+    if (!m) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (want) list[base + __popcll(m & ((1ull << lane) - 1))] = code;
+}
+
+__global__ void k_objects_classify(const ObjArgs *args, ObjLists L) {
+    const int nobj = *L.n_obj;
+    const int stride = gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of iterations (ballots)
+    const int iters = (nobj + stride - 1) / stride;
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int it = 0; it < iters; ++it, o += stride) {
+        int cls = -1, code = 0;
+        if (o < nobj) {
+            code = L.obj[o];
+            const ObjArgs a = args[code >> 25];
+            const int g = code & CODE_MASK;
+            const CropGeom q = crop_geom(a, g);
+            if (a.st_area[g] < a.min_area_pre || (L.path != 2 && q.cw <= RS_ && q.ch <= RS_))
+                cls = 0;
+            else if (L.path == 0 && q.cw <= RM_ && q.ch <= RM_)
+                cls = 1;
+            else if (q.n <= CAP_L)
+                cls = 2;
+            else
+                cls = 3;
+        }
+        wave_append(cls == 0, code, L.list_s, L.n_s);
+        wave_append(cls == 1, code, L.list_m, L.n_m);
+        wave_append(cls == 2, code, L.list_l, L.n_l);
+        wave_append(cls == 3, code, L.big, L.n_big);
+    }
+}
+
+// small class: erases components below the first area threshold and
+// processes crops up to 32 x 32
 __global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
     __shared__ int Ts[2 * RS_ * (RS_ + 1)];
-    const int nobj = *L.n_obj;
+    const int nobj = *L.n_s;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
-        const int code = L.obj[o];
+        const int code = L.list_s[o];
         const ObjArgs a = args[code >> 25];
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
         if (a.st_area[g] < a.min_area_pre) {
             erase_object(a, g, q);
-            continue;
-        }
-        if (L.path == 2 || q.cw > RS_ || q.ch > RS_) {
-            if (threadIdx.x == 0) {
-                if (L.path == 0)
-                    L.list_m[atomicAdd(L.n_m, 1)] = code;
-                else if (q.n <= CAP_L)
-                    L.list_l[atomicAdd(L.n_l, 1)] = code;
-                else
-                    L.big[atomicAdd(L.n_big, 1)] = code;
-            }
             continue;
         }
         process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist, Ts);
@@ -712,6 +746,10 @@ __global__ __launch_bounds__(WAVE) void k_objects_l(const ObjArgs *args, ObjList
         const ObjArgs a = args[code >> 25];
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
+        if (q.n > CAP_L) {   // routed here only when it fits; keep the guard for the LDS bound
+            if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
+            continue;
+        }
         process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist, nullptr);
     }
 }
@@ -762,23 +800,39 @@ static size_t crop_bytes(int64_t n) { return (size_t)n * (8 + 4 + 4 + 1) + 256; 
 size_t big_object_bytes(int w, int h) { return crop_bytes((int64_t)h * (w | 1)); }
 size_t mid_object_bytes(int w, int h) { return std::min(big_object_bytes(w, h), crop_bytes(MID_MAX_PX)); }
 
-int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStream_t s, hipEvent_t before_big) {
-    const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
-    hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, s, args_dev, L);
-    RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
-    RT_HIP(hipGetLastError());
-    const size_t lds_l = (size_t)CAP_L * 13;
+int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStream_t s, hipEvent_t before_big,
+                   const ObjStreams *par) {
+    if (L.big_slices < 1 || L.mid_slices < 1) {
+        set_error("objects: no global scratch slice");
+        return RT_ENOMEM;
+    }
+    const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13, lds_l = (size_t)CAP_L * 13;
     static bool lds_l_set = false;
     if (!lds_l_set) {
         RT_HIP(hipFuncSetAttribute((const void *)k_objects_l, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l));
         lds_l_set = true;
     }
+    hipLaunchKernelGGL(k_objects_classify, dim3(n_cu * 4), dim3(256), 0, s, args_dev, L);
+    RT_HIP(hipGetLastError());
+    // The small class runs on a side stream beside the others when one is
+    // given.  The medium class (the longest per component) is enqueued first
+    // on the caller's stream, so it reaches the compute units before the
+    // many small components fill them.
+    hipStream_t t = s;
+    if (par && par->side) {
+        RT_HIP(hipEventRecord(par->fork, s));
+        RT_HIP(hipStreamWaitEvent(par->side, par->fork, 0));
+        t = par->side;
+    }
+    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
+    RT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, t, args_dev, L);
+    RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_l, dim3(n_cu), dim3(WAVE), lds_l, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    if (L.big_slices < 1 || L.mid_slices < 1) {
-        set_error("objects: no global scratch slice");
-        return RT_ENOMEM;
+    if (t != s) {
+        RT_HIP(hipEventRecord(par->join, t));
+        RT_HIP(hipStreamWaitEvent(s, par->join, 0));
     }
     if (before_big) RT_HIP(hipEventRecord(before_big, s));
     BigPass mid{L.big, L.n_big, L.huge, L.n_huge, (char *)L.mid_scratch, L.mid_slice_bytes, MID_MAX_PX};

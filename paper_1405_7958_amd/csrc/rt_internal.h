@@ -83,6 +83,8 @@ struct rt_ctx_impl {
     size_t stamps_cap = 0;
     Knobs knobs;
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
+    hipStream_t side_stream = nullptr;     // per-object classes beside the small class
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::vector<GraphPair> graphs;         // small cache of captured batches
     uint64_t graph_clock = 0;
     int64_t graph_replays = 0, graph_captures = 0;
@@ -237,6 +239,7 @@ struct ObjArgs {                   // one record per image
 };
 struct ObjLists {                  // shared by the batch; entries are image << 25 | root
     const int32_t *obj, *n_obj;
+    int32_t *list_s, *n_s;         // small class (and components to erase)
     int32_t *list_m, *n_m;         // deferred to the medium LDS class
     int32_t *list_l, *n_l;         // deferred to the large LDS class
     int32_t *big, *n_big;          // deferred to the global-memory classes
@@ -252,9 +255,15 @@ struct ObjLists {                  // shared by the batch; entries are image << 
                                    // 2: large LDS class for every crop that fits
 };
 constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
-// `before_big` (nullable) is recorded on `s` before the global-memory class starts.
+// Optional side stream for the small class, joined back into the caller's
+// stream with the two events before the global-memory classes.
+struct ObjStreams {
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+// `before_big` (nullable) is recorded on `s` at the end of the LDS classes.
 int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hipStream_t s,
-                   hipEvent_t before_big = nullptr);
+                   hipEvent_t before_big = nullptr, const ObjStreams *par = nullptr);
 size_t big_object_bytes(int w, int h);   // one slice for the largest crop of a w x h image
 size_t mid_object_bytes(int w, int h);   // one slice for a crop of at most MID_MAX_PX pixels
 // number of mid slices for a launch group of `pixels` pixels
