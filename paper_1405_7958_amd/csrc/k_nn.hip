@@ -157,6 +157,117 @@ __global__ __launch_bounds__(256) void k_conv3(Conv3K a) {
     }
 }
 
+// The same contraction with the input neighbourhood staged in LDS: a
+// workgroup covers 4*RW output rows x 32 columns of one image; its
+// (4*RW + 2) x 34 x cin input patch (zeros outside the image) is loaded once
+// with 16-byte coalesced reads, and every tap's A fragment is then read from
+// LDS instead of from L1/L2 nine times over.  Wave w computes rows
+// w*RW .. w*RW+RW-1, two 16-pixel M tiles per row.
+constexpr int PW = 34;   // patch width: 32 columns + halo
+
+template <int TN, int RW>
+__global__ __launch_bounds__(256) void k_conv3_lds(Conv3K a) {
+    extern __shared__ __align__(16) bf16_t patch[];
+    constexpr int TM = 2 * RW;
+    constexpr int TH = 4 * RW;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int cin = a.c0 + a.c1;
+    const int K = 9 * cin;
+    const int bx = blockIdx.x, by = blockIdx.y, img = blockIdx.z;
+    const int x0 = bx * 32, y0 = by * TH;
+    // ---- stage the input patch
+    const int c8 = cin / 8;
+    const int chunks = (TH + 2) * PW * c8;
+    for (int q = threadIdx.x; q < chunks; q += 256) {
+        const int cc = q % c8;
+        const int pix = q / c8;
+        const int pc = pix % PW, pr = pix / PW;
+        const int gy = y0 + pr - 1, gx = x0 + pc - 1;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < a.h && gx >= 0 && gx < a.w) {
+            const int64_t sp = ((int64_t)img * a.h + gy) * a.w + gx;
+            const int ci = cc * 8;
+            v = ci < a.c0 ? *reinterpret_cast<const uint4 *>(a.x0 + sp * a.c0 + ci)
+                          : *reinterpret_cast<const uint4 *>(a.x1 + sp * a.c1 + (ci - a.c0));
+        }
+        *reinterpret_cast<uint4 *>(patch + (int64_t)pix * cin + cc * 8) = v;
+    }
+    __syncthreads();
+    const int r = lane & 15, kg = lane >> 4;
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt)
+#pragma unroll
+        for (int t = 0; t < TN; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < K; kb += 32) {
+        const int k0 = kb + kg * 8;
+        bf16x8 A[TM], B[TN];
+        if (k0 < K) {
+            const int tap = k0 / cin;
+            const int ci = k0 - tap * cin;
+            const int dy = a.sgn * (tap / 3 - 1), dx = a.sgn * (tap % 3 - 1);
+#pragma unroll
+            for (int mt = 0; mt < TM; ++mt) {
+                const int row = wave * RW + (mt >> 1) + 1 + dy;
+                const int col = (mt & 1) * 16 + r + 1 + dx;
+                A[mt] = load8(patch + (row * PW + col) * cin + ci);
+            }
+#pragma unroll
+            for (int t = 0; t < TN; ++t) B[t] = load8(a.wk + (int64_t)(t * 16 + r) * K + k0);
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < TM; ++mt) A[mt] = zero8();
+#pragma unroll
+            for (int t = 0; t < TN; ++t) B[t] = zero8();
+        }
+#pragma unroll
+        for (int mt = 0; mt < TM; ++mt)
+#pragma unroll
+            for (int t = 0; t < TN; ++t) acc[mt][t] = mfma(A[mt], B[t], acc[mt][t]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt) {
+        const int y = y0 + wave * RW + (mt >> 1);
+        if (y >= a.h) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int x = x0 + (mt & 1) * 16 + kg * 4 + e;
+            if (x >= a.w) continue;
+            const int64_t p = ((int64_t)img * a.h + y) * a.w + x;
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                const int nn = t * 16 + r;
+                float v = acc[mt][t][e];
+                if (!a.dgrad) {
+                    v += a.bias[nn];
+                    if (a.relu) v = v > 0.f ? v : 0.f;
+                    if (a.y) a.y[p * a.nout + nn] = f2bf(v);
+                    if (a.yf) a.yf[p * a.nout + nn] = v;
+                } else if (nn < a.split) {
+                    a.d0[p * a.split + nn] = v;
+                } else {
+                    a.d1[p * (a.nout - a.split) + (nn - a.split)] = v;
+                }
+            }
+        }
+    }
+}
+
+template <int TN, int RW>
+static void launch_conv3_lds(const Conv3K &a, hipStream_t s) {
+    const int cin = a.c0 + a.c1;
+    const size_t lds = (size_t)(4 * RW + 2) * PW * cin * sizeof(bf16_t);
+    static bool set = false;
+    if (!set) {
+        (void)hipFuncSetAttribute((const void *)k_conv3_lds<TN, RW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)((4 * RW + 2) * PW * 128 * sizeof(bf16_t)));
+        set = true;
+    }
+    const dim3 grid((unsigned)((a.w + 31) / 32), (unsigned)((a.h + 4 * RW - 1) / (4 * RW)), (unsigned)a.n);
+    hipLaunchKernelGGL((k_conv3_lds<TN, RW>), grid, dim3(256), lds, s, a);
+}
+
 static int launch_conv3(const Conv3K &a, hipStream_t s) {
     if (a.nout % 16 || a.nout > 128 || a.nout < 16 || (a.c0 % 8) || (a.c1 % 8)) {
         set_error("nn conv3: unsupported channel counts (in %d+%d, out %d)", a.c0, a.c1, a.nout);
@@ -167,6 +278,18 @@ static int launch_conv3(const Conv3K &a, hipStream_t s) {
     // a wave computes 16*TM pixels x nout channels; wider outputs take more
     // pixels per wave so that each weight fragment feeds more matrix ops
     const int tn = a.nout / 16;
+    const int cin = a.c0 + a.c1;
+    if (cin <= 128 && a.n <= 65535) {
+        switch (tn) {
+            case 1: launch_conv3_lds<1, 1>(a, s); break;
+            case 2: launch_conv3_lds<2, 1>(a, s); break;
+            case 4: launch_conv3_lds<4, 2>(a, s); break;
+            case 8: launch_conv3_lds<8, 2>(a, s); break;
+            default: goto direct;
+        }
+        return hip_fail(hipGetLastError(), "k_conv3_lds");
+    }
+direct:
     const int tm = tn >= 4 ? 4 : 2;
     const dim3 grid((unsigned)((P + 64 * tm - 1) / (64 * tm)));
     switch (tn) {
