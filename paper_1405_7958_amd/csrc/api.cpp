@@ -428,8 +428,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     P.o_ob = L.add(sizeof(ObjArgs) * n);
     P.o_aux = L.add(sizeof(BatchAux) * n);
     const size_t rec_end = L.off;
-    const size_t recon_lists = al(sizeof(int32_t) * (2 * (size_t)P.rec_total + 4));
-    int e = ensure_arena(c, al(L.off) + recon_lists + 4096);
+    int e = ensure_arena(c, al(L.off) + recon_scratch_bytes(P.rec_total) + 4096);
     if (e) return e;
     if ((e = ensure_staging(c, rec_end - P.o_dec + 4096))) return e;
     c->arena.off = L.off;
@@ -548,16 +547,30 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     sp.scale = p->hq_scale;
     const ReconImg *rimgs = at<ReconImg>(c, P.o_rec);
     int rounds = 0;
+    const bool queue = c->knobs.recon_mode == 1;
     if (!use_graph) {
         if ((e = enqueue_front(c, P, sp, s, true))) return e;
-        if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &rounds))) return e;
+        if (queue) {
+            int aborted = 0;
+            if ((e = recon_queue(c, P.run, rimgs, n, RT_U8, 8, s)) ||
+                (e = recon_queue_aborted(c, P.run, s, &aborted)))
+                return e;
+            rounds = 1;
+            if (aborted) {
+                int more = 0;
+                if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
+                rounds += more;
+            }
+        } else if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &rounds))) {
+            return e;
+        }
         c->prof_launches[2] += rounds;
         c->last_rounds = rounds;
         return enqueue_back(c, P, s, true);
     }
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
-                                c->knobs.objects_path,
+                                c->knobs.objects_path, c->knobs.recon_mode,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -588,7 +601,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
             c,
             [&](hipStream_t cs) {
                 int e2 = enqueue_front(c, P, sp, cs, false);
-                if (!e2) e2 = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, budget, cs);
+                if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, RT_U8, 8, cs)
+                                    : recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, budget, cs);
                 return e2;
             },
             &g->a);
@@ -602,7 +616,18 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     }
     g->last_use = ++c->graph_clock;
     RT_HIP(hipGraphLaunch(g->a, s));
-    if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, budget, s, &rounds))) return e;
+    if (queue) {
+        int aborted = 0;
+        if ((e = recon_queue_aborted(c, P.run, s, &aborted))) return e;
+        rounds = 1;
+        if (aborted) {
+            int more = 0;
+            if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
+            rounds += more;
+        }
+    } else if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, budget, s, &rounds))) {
+        return e;
+    }
     c->last_rounds = rounds;
     RT_HIP(hipGraphLaunch(g->b, s));
     c->graph_replays++;
@@ -721,7 +746,7 @@ int rt_morph_recon(rt_ctx *c, int dtype, const void *marker, const void *mask, v
     const int64_t ntiles = recon_tiles(w, h);
     Layout L;
     const size_t o_args = L.add(sizeof(ReconImg));
-    if ((e = ensure_arena(c, al(L.off) + al(sizeof(int32_t) * (2 * ntiles + 4)) + 4096)) ||
+    if ((e = ensure_arena(c, al(L.off) + recon_scratch_bytes((int)ntiles) + 4096)) ||
         (e = ensure_staging(c, L.off + 4096)))
         return e;
     c->arena.off = L.off;
@@ -1059,6 +1084,9 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     } else if (n == "recon_max_sweeps") {
         CHECK(value >= 1 && value <= 1024, "rt_set_knob: recon_max_sweeps must be 1..1024");
         c->knobs.recon_max_sweeps = value;
+    } else if (n == "recon_mode") {
+        CHECK(value == 0 || value == 1, "rt_set_knob: recon_mode must be 0 or 1");
+        c->knobs.recon_mode = value;
     } else if (n == "objects_path") {
         CHECK(value >= 0 && value <= 2, "rt_set_knob: objects_path must be 0..2");
         c->knobs.objects_path = value;
@@ -1086,6 +1114,8 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.recon_max_sweeps;
     else if (n == "objects_path")
         *value = c->knobs.objects_path;
+    else if (n == "recon_mode")
+        *value = c->knobs.recon_mode;
     else if (n == "graph")
         *value = c->knobs.graph;
     else if (n == "graph_rounds")

@@ -107,8 +107,8 @@ __device__ __forceinline__ int shl0(int v) {  // lane i <- lane i+1 (lane 63: do
     return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
 }
 
-template <typename T, int CONN>
-__device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, int32_t *cnt_out, int (*Ts)[65]);
+template <typename T, int CONN, bool QUEUE, typename Push>
+__device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*Ts)[65], Push push);
 
 template <typename T, int CONN>
 __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
@@ -124,13 +124,119 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
     for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
         const int gtile = ra.first ? slot : ra.list_in[slot];
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
-        recon_tile<T, CONN>(ra, a, gtile, cnt_out, Ts);
+        recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, Ts, [&](const int *nb, int nn) {
+            for (int k = 0; k < nn; ++k)
+                if (atomicExch(ra.stamp + nb[k], ra.epoch) != ra.epoch) ra.list_out[atomicAdd(cnt_out, 1)] = nb[k];
+        });
         __syncthreads();
     }
 }
 
+// Work-queue variant: one persistent launch in which every wave takes a
+// ticket, waits for the tile pushed under that ticket, processes it and
+// pushes the neighbours its change reaches (a tile is in the queue at most
+// once: inq).  `pending` counts tiles pushed and not yet finished; the waves
+// leave when it reaches zero.  A waiting wave that sees no tile finished
+// anywhere for spin_limit wall-clock ticks (a stall: one tile visit takes far
+// less) raises `abort` and leaves; the host then finishes with ordinary
+// rounds, which accept any intermediate state.
+struct QueueArgs {
+    const ReconImg *imgs;
+    int n, total;
+    unsigned long long *ring;   // 2*total entries: ticket << 32 | tile
+    unsigned int *ctl;          // head, tail, pending, abort, finished
+    unsigned int *inq;
+    int max_sweeps;
+    long long spin_limit;
+    unsigned long long *visits; // nullable
+};
+
+constexpr unsigned long long RING_EMPTY = ~0ull;
+
 template <typename T, int CONN>
-__device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, int32_t *cnt_out, int (*Ts)[65]) {
+__global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
+    __shared__ int Ts[64][65];
+    const int lane = threadIdx.x;
+    const unsigned cap = 2u * (unsigned)q.total;
+    unsigned int *head = q.ctl, *tail = q.ctl + 1, *pending = q.ctl + 2, *abortf = q.ctl + 3, *done = q.ctl + 4;
+    for (;;) {
+        int item = -1;
+        if (lane == 0) {
+            const unsigned t = atomicAdd(head, 1u);
+            const unsigned slot = t % cap;
+            long long t0 = wall_clock64();
+            unsigned seen = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (unsigned spin = 0;; ++spin) {
+                const unsigned long long e =
+                    __hip_atomic_load(q.ring + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)(e >> 32) == t) {
+                    item = (int)(e & 0xffffffffull);
+                    break;
+                }
+                // the shared counters are polled less often than the own slot
+                if (spin & 7u) {
+                    __builtin_amdgcn_s_sleep(8);
+                    continue;
+                }
+                if (__hip_atomic_load(pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                    item = -2;
+                    break;
+                }
+                const unsigned now_done = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (now_done != seen) {   // progress elsewhere: restart the stall timer
+                    seen = now_done;
+                    t0 = wall_clock64();
+                } else if (wall_clock64() - t0 > q.spin_limit) {
+                    atomicExch(abortf, 1u);
+                    item = -2;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        item = __shfl(item, 0, 64);
+        if (item < 0) break;
+        __threadfence();   // acquire: the pusher's tile writes are visible
+        if (lane == 0) {
+            atomicExch(q.inq + item, 0u);
+            if (q.visits) atomicAdd(q.visits, 1ull);
+        }
+        const ReconImg a = q.imgs[recon_img_of(q.imgs, q.n, item)];
+        recon_tile<T, CONN, true>(a, item, q.max_sweeps, Ts, [&](const int *nb, int nn) {
+            for (int k = 0; k < nn; ++k) {
+                if (atomicExch(q.inq + nb[k], 1u) == 0u) {
+                    atomicAdd(pending, 1u);
+                    const unsigned t = atomicAdd(tail, 1u);
+                    __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb[k],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        });
+        __syncthreads();
+        if (lane == 0) {
+            atomicAdd(done, 1u);
+            atomicSub(pending, 1u);
+        }
+    }
+}
+
+__global__ void k_queue_init(QueueArgs q) {
+    const int cap = 2 * q.total;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
+        q.ring[i] = i < q.total ? (((unsigned long long)i << 32) | (unsigned)i) : RING_EMPTY;
+        if (i < q.total) q.inq[i] = 1u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        q.ctl[0] = 0u;
+        q.ctl[1] = (unsigned)q.total;
+        q.ctl[2] = (unsigned)q.total;
+        q.ctl[3] = 0u;
+        q.ctl[4] = 0u;
+    }
+}
+
+template <typename T, int CONN, bool QUEUE, typename Push>
+__device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*Ts)[65], Push push) {
     const int lane = threadIdx.x;
     const int tile = gtile - a.unit0;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -170,7 +276,7 @@ __device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, in
 
     bool any_change = false;
     bool converged = false;
-    for (int sweep = 0; sweep < ra.max_sweeps; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         bool ch = false;
         // down and up, lane = column; ring lanes never change and feed their
         // values to the DPP shifts like any other lane
@@ -270,6 +376,7 @@ __device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, in
     const bool row_inner = lane >= 1 && lane <= 62;
     const bool cL = row_inner && Ts[lane][1] != oL, cR = row_inner && Ts[lane][62] != oR;
     const uint64_t mT = __ballot(cT), mB = __ballot(cB), mL = __ballot(cL), mR = __ballot(cR);
+    if constexpr (QUEUE) __threadfence();   // release the tile's writes before announcing them
     if (lane == 0) {
         int nb[9];
         int nn = 0;
@@ -287,10 +394,8 @@ __device__ void recon_tile(const RoundArgs &ra, const ReconImg &a, int gtile, in
             if ((mB >> 1) & 1ull) add(-1, 1);    // (1, 62)
             if ((mB >> 62) & 1ull) add(1, 1);    // (62, 62)
         }
-        if (!converged) nb[nn++] = gtile;  // sweep budget exhausted: continue next round
-        for (int k = 0; k < nn; ++k) {
-            if (atomicExch(ra.stamp + nb[k], ra.epoch) != ra.epoch) ra.list_out[atomicAdd(cnt_out, 1)] = nb[k];
-        }
+        if (!converged) nb[nn++] = gtile;  // sweep budget exhausted: continue later
+        push(nb, nn);
     }
 }
 
@@ -436,6 +541,13 @@ int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run) {
     run.lists = lists;
     run.cnt = lists + 2 * (size_t)total;
     run.total = total;
+    run.ring = (unsigned long long *)c->arena.take(sizeof(unsigned long long) * 2 * (size_t)std::max(total, 1));
+    run.qctl = (unsigned int *)c->arena.take(sizeof(unsigned int) * 8);
+    run.inq = (unsigned int *)c->arena.take(sizeof(unsigned int) * (size_t)std::max(total, 1));
+    if (!run.ring || !run.qctl || !run.inq) {
+        set_error("recon: scratch arena too small");
+        return RT_ENOMEM;
+    }
     return RT_OK;
 }
 
@@ -491,6 +603,56 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
     return RT_OK;
 }
 
+int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
+                hipStream_t s) {
+    if (run.total <= 0) return RT_OK;
+    QueueArgs q;
+    q.imgs = imgs_dev;
+    q.n = n;
+    q.total = run.total;
+    q.ring = run.ring;
+    q.ctl = run.qctl;
+    q.inq = run.inq;
+    q.max_sweeps = c->knobs.recon_max_sweeps;
+    q.spin_limit = 200000;   // 2 ms at the 100 MHz wall clock
+    q.visits = c->prof_on ? c->prof_visits : nullptr;
+    const int gi = (int)std::min<int64_t>((2 * (int64_t)run.total + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_queue_init, dim3(gi), dim3(256), 0, s, q);
+    RT_HIP(hipGetLastError());
+    hipEvent_t ev_end = nullptr;
+    if (c->prof_on) {
+        while (c->round_events.size() < c->round_used + 2) {
+            hipEvent_t ev;
+            RT_HIP(hipEventCreate(&ev));
+            c->round_events.push_back(ev);
+        }
+        RT_HIP(hipEventRecord(c->round_events[c->round_used], s));
+        ev_end = c->round_events[c->round_used + 1];
+        c->round_used += 2;
+    }
+    // every wave resident: 2 waves per SIMD fit the kernel's registers
+    const int grid = std::min(run.total, c->n_cu * 8);
+    if (dtype == RT_U8) {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<uint8_t, 8>), dim3(grid), dim3(64), 0, s, q);
+        else hipLaunchKernelGGL((k_recon_queue<uint8_t, 4>), dim3(grid), dim3(64), 0, s, q);
+    } else {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<int32_t, 8>), dim3(grid), dim3(64), 0, s, q);
+        else hipLaunchKernelGGL((k_recon_queue<int32_t, 4>), dim3(grid), dim3(64), 0, s, q);
+    }
+    RT_HIP(hipGetLastError());
+    if (ev_end) RT_HIP(hipEventRecord(ev_end, s));
+    return RT_OK;
+}
+
+int recon_queue_aborted(rt_ctx_impl *c, const ReconRun &run, hipStream_t s, int *aborted) {
+    *aborted = 0;
+    if (run.total <= 0) return RT_OK;
+    RT_HIP(hipMemcpyAsync(c->pinned, run.qctl + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    *aborted = c->pinned[0] != 0;
+    return RT_OK;
+}
+
 int recon_pending(rt_ctx_impl *c, const ReconRun &run, int k, hipStream_t s, int *pending) {
     if (run.total <= 0) {
         *pending = 0;
@@ -532,7 +694,15 @@ int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int
     const size_t mark = c->arena.off;
     ReconRun run;
     int e = recon_prepare(c, total, run);
-    if (!e) e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
+    if (!e && c->knobs.recon_mode == 1) {
+        int aborted = 0;
+        e = recon_queue(c, run, imgs_dev, n, dtype, conn, s);
+        if (!e) e = recon_queue_aborted(c, run, s, &aborted);
+        if (!e && aborted) e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
+        else if (rounds_out) *rounds_out = 1;
+    } else if (!e) {
+        e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
+    }
     c->arena.off = mark;
     return e;
 }

@@ -55,6 +55,7 @@ struct Knobs {
     int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
     int objects_path = 0;        // per-object class routing (ObjLists::path)
+    int recon_mode = 0;          // 0: rounds with host checks; 1: one work-queue launch
     int graph = 0;               // replay segmentation batches from captured HIP graphs
     int graph_rounds = 24;       // reconstruction rounds inside the first graph
 };
@@ -182,12 +183,27 @@ struct ReconRun {
     int32_t *lists = nullptr;      // two lists of `total` tile ids
     int32_t *cnt = nullptr;        // 3 rotating counters
     int total = 0;
+    unsigned long long *ring = nullptr;   // work queue: 2*total entries
+    unsigned int *qctl = nullptr;         // head, tail, pending, abort, finished
+    unsigned int *inq = nullptr;          // per tile: queued
 };
+// bytes recon_prepare takes from the arena for `total` tiles
+inline size_t recon_scratch_bytes(int total) {
+    const size_t t = (size_t)(total > 0 ? total : 1);
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al(sizeof(int32_t) * (2 * t + 4)) + al(8 * 2 * t) + al(32) + al(4 * t) + 1024;
+}
 int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run);
 // Enqueues rounds k0 .. k1-1 (no synchronisation; capturable).  All images
 // share dtype and connectivity.
 int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
                  int k1, hipStream_t s);
+// Enqueues the work-queue propagation (one persistent launch; capturable).
+int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
+                hipStream_t s);
+// After recon_queue: whether a wave gave up waiting (synchronises `s`); the
+// caller then finishes with recon_finish from round 0.
+int recon_queue_aborted(rt_ctx_impl *c, const ReconRun &run, hipStream_t s, int *aborted);
 // Reads the number of tiles queued for round k (synchronises `s`).
 int recon_pending(rt_ctx_impl *c, const ReconRun &run, int k, hipStream_t s, int *pending);
 // Runs rounds from k0 on until no tile is queued (synchronises `s` every

@@ -31,6 +31,7 @@ SPACE = {
     "recon_round_batch": [4, 8, 16, 32],
     "recon_max_sweeps": [16, 32, 64, 128],
     "objects_path": [0, 1, 2],
+    "recon_mode": [0, 1],
 }
 
 
