@@ -303,7 +303,7 @@ int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s
     if (prof && (e = prof_mark(c, 1, s))) return e;
     if (P.nlev > 0) {
         if ((e = launch_batch_levels(at<BatchAux>(c, P.o_aux), P.n, P.nlev, s))) return e;
-        if ((e = launch_ccl(at<CclArgs>(c, P.o_cl), P.n, P.ccl_total, c->n_cu, s))) return e;
+        if ((e = launch_ccl(at<CclArgs>(c, P.o_cl), P.n, P.ccl_total, c->n_cu, s, CclPred::Level, CclOut::LevelBound, P.nlev))) return e;
         c->prof_launches[1] += 4;
     } else {
         if ((e = launch_batch_frame_marker(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
@@ -318,10 +318,10 @@ int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s
 int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool capturing = false) {
     int e;
     if (prof && (e = prof_mark(c, 3, s))) return e;
-    if ((e = launch_ccl(at<CclArgs>(c, P.o_cf), P.n, P.ccl_total, c->n_cu, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, P.o_cf), P.n, P.ccl_total, c->n_cu, s, CclPred::TophatBg, CclOut::FillHoles))) return e;
     c->prof_launches[3] += 3;
     if (prof && (e = prof_mark(c, 4, s))) return e;
-    if ((e = launch_ccl(at<CclArgs>(c, P.o_cc), P.n, P.ccl_total, c->n_cu, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, P.o_cc), P.n, P.ccl_total, c->n_cu, s, CclPred::NonZero, CclOut::Labels))) return e;
     c->prof_launches[4] += 3;
     if (prof && (e = prof_mark(c, 5, s))) return e;
     int32_t *ctr = at<int32_t>(c, P.o_ctr);  // n_obj, n_m, n_big, (kept), n_huge
@@ -785,7 +785,7 @@ int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t
     A.pitch_f = pitch;
     Stager sg{c};
     if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
-    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s);
+    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::Zero, CclOut::FillHoles);
 }
 
 int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
@@ -819,7 +819,7 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     }
     Stager sg{c};
     if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
-    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s);
+    return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::NonZero, CclOut::Labels);
 }
 
 int rt_area_filter(rt_ctx *c, const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int32_t w, int32_t h,
@@ -901,7 +901,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
         (e = sg.flush(s)))
         return e;
     if ((e = launch_fill_i32(ctr, 0, 16, s))) return e;
-    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::NonZero, CclOut::Labels))) return e;
     ObjLists OL{obj, ctr, obj + 5 * mo, ctr + 10, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2,
                 obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     ObjStreams par{};
@@ -1061,8 +1061,8 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     if ((e = sg.put(std::vector<CclArgs>{B}, o_cf)) || (e = sg.put(std::vector<CclArgs>{A}, o_cc)) ||
         (e = sg.put(std::vector<ObjArgs>{O}, o_ob)) || (e = sg.flush(s)))
         return e;
-    if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
-    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cf), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::Zero, CclOut::FillHoles))) return e;
+    if ((e = launch_ccl(at<CclArgs>(c, o_cc), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::NonZero, CclOut::Labels))) return e;
     ObjLists OL{obj, ctr, obj + 5 * mo, ctr + 10, obj + mo, ctr + 1, obj + 4 * mo, ctr + 9, obj + 2 * mo, ctr + 2,
                 obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     ObjStreams par{};

@@ -2,33 +2,70 @@
 // in which every pixel starts as its own tree, adjacent trees are merged, and
 // labels are read off by flattening the trees).
 //
-// One wavefront per 64 x 64 tile.  A row of the tile is one 64-bit ballot
-// mask, so the forest is built over horizontal runs instead of pixels: the
-// pixels of a run share its first pixel as parent by construction (bit
-// arithmetic, no atomics), and only runs of adjacent rows that touch are
-// united (LDS atomicMin, the root is always the smallest index, so labels are
-// canonical by construction).  Three launches:
+// One wavefront per 64 x 64 tile.  A row of the tile is one 64-bit mask, so
+// the forest is built over horizontal runs instead of pixels: the pixels of a
+// run share its first pixel as parent by construction (bit arithmetic, no
+// atomics), and only runs of adjacent rows that touch are united (LDS
+// atomicMin, the root is always the smallest index, so labels are canonical
+// by construction).  Two run starts of one row are at least two pixels apart,
+// so the forest needs one LDS slot per pixel pair (8 KB per tile).  Three
+// launches:
 //   local  : build the tile forest; publish only its roots and its edge
 //            pixels to the global id array (id 0 = virtual node, pixel p has
 //            id p + 1);
-//   merge  : one wave per tile unites, across its right and bottom edges,
-//            each pair of touching edge runs once (global atomicMin);
-//   flatten: rebuild the tile forest (it costs 1 byte/pixel of input instead
-//            of 4 bytes/pixel of stored local roots), find each local root's
-//            global root once, and write the per-pixel result.
+//   merge  : one wave per tile edge unites, across the tile's right or
+//            bottom edge, each pair of touching edge runs once (global
+//            atomicMin);
+//   flatten: BWLabel rebuilds the tile forest (it costs 1 byte/pixel of
+//            input instead of 4 bytes/pixel of stored local roots), finds
+//            each local root's global root once, and writes the labels;
+//            FillHoles and the bound look up only the border runs' roots and
+//            flood the frame-connected set inside the tile.
 // Modes: BWLabel (labels, per-component area and bounding box, component
 // list), FillHoles (background components joined to a virtual frame node),
 // and the multi-level frame-connectivity lower bound that starts the
-// grayscale reconstruction.
+// grayscale reconstruction.  In the multi-level mode a workgroup holds one
+// wave per threshold level of the same tile: the levels' forests and global
+// unions proceed side by side, and the flatten combines the levels' frame-
+// connected pixel sets in LDS before one write of the bound.
+//
+// Every kernel is specialised for its predicate and output, so each one is
+// straight-line code for its own mode.  Tile rows are read with 16-byte loads
+// (four per lane cover the tile) and turned into row masks lane-locally.
 #include "rt_internal.h"
 
 namespace rtseg {
 
 constexpr int CT = 64;                 // tile edge = wavefront size
 constexpr int MAXLEV = 8;
+constexpr int NSLOT = CT * CT / 2;     // forest slots: one per pixel pair of a row
 constexpr int FRAME_BIT = 1 << 30;     // tags a local root whose component touches the image frame
 constexpr int TOUCH_BIT = 1 << 29;     // tags a local root whose component touches the tile border
 constexpr int LIDX = 0xfff;
+constexpr int NLIST = 128;             // components touching a tile border: at most 126 (one per two border pixels)
+constexpr int WAVE_LDS = CT * 8 + NSLOT * 4 + NLIST * 4 + 16;   // bytes per wave: row masks, forest, root list
+constexpr int NHASH = 128;             // per-tile component table of the statistics pass
+constexpr int LABELS_LDS = WAVE_LDS + NHASH * 7 * 4;
+
+extern __shared__ uint64_t ccl_smem[];
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (CT - 1); }
+
+struct WaveMem {
+    uint64_t *rows;   // rows[y] bit x = member (x, y)
+    int *P;           // forest over run starts, indexed by slot()
+    int *list;        // border-touching roots of the tile
+    int *count;       // their number
+};
+
+__device__ __forceinline__ WaveMem wave_mem(int wave) {
+    uint64_t *base = ccl_smem + (size_t)wave * (WAVE_LDS / 8);
+    int *P = (int *)(base + CT);
+    return {base, P, P + NSLOT, P + NSLOT + NLIST};
+}
+
+// forest slot of the run start at tile index li = y * 64 + s
+__device__ __forceinline__ int slot(int li) { return (li >> 6) * (CT / 2) + ((li & (CT - 1)) >> 1); }
 
 __device__ __forceinline__ int ld_agent(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -36,12 +73,12 @@ __device__ __forceinline__ int ld_agent(const int32_t *p) {
 
 // Finds with path halving: a node is re-pointed to its grandparent with
 // atomicMin, so parent pointers only ever move to a smaller ancestor and a
-// concurrent link can never be undone.
+// concurrent link can never be undone.  Nodes are tile indices of run starts.
 __device__ __forceinline__ int lfind(int *P, int x) {
-    int p = __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    int p = __hip_atomic_load(P + slot(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     while (p != x) {
-        const int gp = __hip_atomic_load(P + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (gp != p) atomicMin(P + x, gp);
+        const int gp = __hip_atomic_load(P + slot(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gp != p) atomicMin(P + slot(x), gp);
         x = p;
         p = gp;
     }
@@ -58,7 +95,7 @@ __device__ __forceinline__ void lunite(int *P, int a, int b) {
             a = b;
             b = t;
         }
-        int old = atomicMin(P + a, b);
+        int old = atomicMin(P + slot(a), b);
         if (old == a) return;
         a = old;
     }
@@ -88,10 +125,54 @@ __device__ __forceinline__ int gfind_ro(const int32_t *ids, int x) {
     return x;
 }
 
+// Both finds of a union walk their chains in the same loop, so that their
+// dependent loads overlap (path halving on each, as gfind).
+// Up to four read-only finds walked together (x[k] < 0: unused).  On
+// return x[k] holds the root.
+__device__ __forceinline__ void gfind4_ro(const int32_t *ids, int x[4]) {
+    bool act[4];
+    int q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        act[k] = x[k] >= 0;
+        q[k] = act[k] ? ids[x[k]] : 0;
+    }
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!act[k]) continue;
+            if (q[k] == x[k]) {
+                act[k] = false;
+            } else {
+                x[k] = q[k];
+                any = true;
+            }
+        }
+        if (!any) return;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (act[k]) q[k] = ids[x[k]];
+    }
+}
+
 __device__ __forceinline__ void gunite(int32_t *ids, int a, int b) {
     for (;;) {
-        a = gfind(ids, a);
-        b = gfind(ids, b);
+        int pa = ld_agent(ids + a), pb = ld_agent(ids + b);
+        while (pa != a || pb != b) {
+            const int ga = pa != a ? ld_agent(ids + pa) : a;
+            const int gb = pb != b ? ld_agent(ids + pb) : b;
+            if (pa != a) {
+                if (ga != pa) atomicMin(ids + a, ga);
+                a = pa;
+                pa = ga;
+            }
+            if (pb != b) {
+                if (gb != pb) atomicMin(ids + b, gb);
+                b = pb;
+                pb = gb;
+            }
+        }
         if (a == b) return;
         if (a < b) {
             int t = a;
@@ -115,17 +196,58 @@ __device__ __forceinline__ int run_start_of(uint64_t m, int b) {   // m has bit 
     return z ? 64 - __builtin_clzll(z) : 0;
 }
 __device__ __forceinline__ uint64_t bits_upto(int e) { return e >= 63 ? ~0ull : (2ull << e) - 1; }
+__device__ __forceinline__ uint64_t run_bits(int s, int len) { return bits_upto(s + len - 1) & ~((1ull << s) - 1); }
+
+// The runs of m that hold a bit of s (s within m): adding s to m clears each
+// run from its lowest seed to its end (the carry stops at the first zero);
+// the same on the bit-reversed masks covers each run from its start to its
+// highest seed.
+__device__ __forceinline__ uint64_t run_fill(uint64_t m, uint64_t s) {
+    s &= m;
+    const uint64_t up = (m & ~(m + s)) | s;
+    const uint64_t mr = __builtin_bitreverse64(m), sr = __builtin_bitreverse64(s);
+    return up | __builtin_bitreverse64((mr & ~(mr + sr)) | sr);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Grows f (lane = row, within the row masks m) to everything connected to it
+// inside the tile: each step takes the neighbour rows' pixels (and their
+// diagonal neighbours for 8-connectivity) and fills whole runs, until no row
+// changes.  The set only grows, so the loop ends.
+__device__ uint64_t flood_rows(uint64_t m, uint64_t f, int conn) {
+    const int lane = lane_id();
+    f = run_fill(m, f);
+    for (;;) {
+        const uint64_t a = shfl64(f, lane > 0 ? lane - 1 : 0);
+        const uint64_t b = shfl64(f, lane < CT - 1 ? lane + 1 : CT - 1);
+        uint64_t nb = (lane > 0 ? a : 0ull) | (lane < CT - 1 ? b : 0ull);
+        if (conn == 8) nb |= (nb << 1) | (nb >> 1);
+        const uint64_t g = run_fill(m, f | nb);
+        const bool grew = g != f;
+        f = g;
+        if (!__any(grew)) return f;
+    }
+}
 
 // ---- predicate --------------------------------------------------------------
+template <CclPred PR>
+__device__ __forceinline__ bool pred_val(const CclArgs &A, uint32_t a, uint32_t b, int level) {
+    if constexpr (PR == CclPred::NonZero) return a != 0;
+    else if constexpr (PR == CclPred::Zero) return a == 0;
+    else if constexpr (PR == CclPred::TophatBg) return (int)a - (int)b < A.t;
+    else return (int)a >= level;
+}
+
+template <CclPred PR>
 __device__ __forceinline__ bool eval_pred(const CclArgs &A, int x, int y, int level) {
-    switch (A.pred) {
-        case CclPred::NonZero: return A.a[(int64_t)y * A.pitch_a + x] != 0;
-        case CclPred::Zero: return A.a[(int64_t)y * A.pitch_a + x] == 0;
-        case CclPred::TophatBg:
-            return (int)A.a[(int64_t)y * A.pitch_a + x] - (int)A.b[(int64_t)y * A.pitch_b + x] < A.t;
-        case CclPred::Level: return (int)A.a[(int64_t)y * A.pitch_a + x] >= level;
-    }
-    return false;
+    const uint32_t a = A.a[(int64_t)y * A.pitch_a + x];
+    const uint32_t b = PR == CclPred::TophatBg ? A.b[(int64_t)y * A.pitch_b + x] : 0u;
+    return pred_val<PR>(A, a, b, level);
 }
 
 struct Tile {
@@ -160,58 +282,65 @@ __device__ __forceinline__ int gid(const CclArgs &A, const Tile &t, int x, int y
     return (t.y0 + y) * A.w + t.x0 + x + 1;
 }
 
-// Column `lane` of the tile, held by that lane: predicate bits (non-Level
-// modes) or the packed uint8 values (Level mode), 4 per word.
-struct Col {
-    uint32_t v[16];
-};
-
-__device__ void load_col(const CclArgs &A, const Tile &t, Col &c) {
-    const int lane = threadIdx.x;
-    const int x = t.x0 + lane;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) c.v[k] = 0;
-    if (lane >= t.tw) return;
-#pragma unroll
-    for (int y = 0; y < CT; ++y) {
-        if (y < t.th) {
-            uint32_t v;
-            if (A.pred == CclPred::Level)
-                v = A.a[(int64_t)(t.y0 + y) * A.pitch_a + x];
-            else
-                v = eval_pred(A, x, t.y0 + y, 0) ? 1u : 0u;
-            c.v[y >> 2] |= v << ((y & 3) * 8);
-        }
-    }
+__device__ __forceinline__ bool aligned16(const void *p, int64_t pitch) {
+    return (((uintptr_t)p | (uintptr_t)pitch) & 15) == 0;
 }
 
-__device__ __forceinline__ bool col_bit(const CclArgs &A, const Col &c, int y, int level) {
-    uint32_t v = (c.v[y >> 2] >> ((y & 3) * 8)) & 255u;
-    return A.pred == CclPred::Level ? (int)v >= level : v != 0;
+__device__ __forceinline__ uint32_t byte_of(const uint4 &q, int i) {
+    const uint32_t w = i < 4 ? q.x : i < 8 ? q.y : i < 12 ? q.z : q.w;
+    return (w >> ((i & 3) * 8)) & 255u;
 }
 
-// rows[y] = ballot over lanes (= columns) of the member bit at row y
-__device__ void make_rows(const CclArgs &A, const Tile &t, const Col &c, int level, uint64_t *rows) {
-    const int lane = threadIdx.x;
-    uint64_t mine = 0;
+// Loads the 16 bytes at p (nvalid of them inside the image; the rest read 0).
+__device__ __forceinline__ uint4 load16(const uint8_t *p, int nvalid, bool wide) {
+    if (wide && nvalid == 16) return *(const uint4 *)p;
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nvalid; ++i) w[i >> 2] |= (uint32_t)p[i] << ((i & 3) * 8);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// rows[y] = member mask of tile row y.  Lane l reads rows l/4 + 16k (k < 4),
+// columns 16 (l % 4) .. +15, and writes those 16 bits of the row mask.
+template <CclPred PR>
+__device__ void build_rows(const CclArgs &A, const Tile &t, int level, uint64_t *rows) {
+    const int ln = lane_id();
+    const int c = ln & 3;
+    const int nvalid = max(0, min(16, t.tw - 16 * c));
+    const bool wide_a = aligned16(A.a, A.pitch_a);
+    const bool wide_b = PR == CclPred::TophatBg && aligned16(A.b, A.pitch_b);
+    uint4 qa[4], qb[4];
 #pragma unroll
-    for (int y = 0; y < CT; ++y) {
-        bool b = y < t.th && lane < t.tw && col_bit(A, c, y, level);
-        uint64_t m = __ballot(b);
-        if (lane == y) mine = m;
+    for (int k = 0; k < 4; ++k) {
+        const int y = (ln >> 2) + 16 * k;
+        const int nv = y < t.th ? nvalid : 0;
+        const int64_t gy = t.y0 + y;
+        const int gx = t.x0 + 16 * c;
+        qa[k] = load16(A.a + gy * A.pitch_a + gx, nv, wide_a);
+        if constexpr (PR == CclPred::TophatBg) qb[k] = load16(A.b + gy * A.pitch_b + gx, nv, wide_b);
+        else qb[k] = make_uint4(0, 0, 0, 0);
     }
-    rows[lane] = mine;
+    uint16_t *r16 = (uint16_t *)rows;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int y = (ln >> 2) + 16 * k;
+        const int nv = y < t.th ? nvalid : 0;
+        uint32_t bits = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) bits |= (pred_val<PR>(A, byte_of(qa[k], i), byte_of(qb[k], i), level) ? 1u : 0u) << i;
+        bits &= (1u << nv) - 1u;
+        r16[y * 4 + c] = (uint16_t)bits;
+    }
     __syncthreads();
 }
 
-// Tile forest over runs: after the call, P[y*64+s] = local root (index of a
-// run start) for every run start s of row y.  Lane = row.
+// Tile forest over runs: after the call, P[slot(y*64+s)] = local root (tile
+// index of a run start) for every run start s of row y.  Lane = row.
 __device__ void run_forest(const uint64_t *rows, int *P, int conn) {
-    const int y = threadIdx.x;
+    const int y = lane_id();
     const uint64_t m = rows[y];
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        int s = __builtin_ctzll(st);
-        P[y * CT + s] = y * CT + s;
+        const int li = y * CT + __builtin_ctzll(st);
+        P[slot(li)] = li;
     }
     __syncthreads();
     if (y > 0) {
@@ -235,89 +364,84 @@ __device__ void run_forest(const uint64_t *rows, int *P, int conn) {
     }
     __syncthreads();
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        int s = __builtin_ctzll(st);
-        P[y * CT + s] = lfind(P, y * CT + s);
+        const int li = y * CT + __builtin_ctzll(st);
+        P[slot(li)] = lfind(P, li);
     }
     __syncthreads();
 }
 
 __device__ __forceinline__ int root_of(const uint64_t *rows, const int *P, int x, int y) {
-    return P[y * CT + run_start_of(rows[y], x)] & LIDX;
+    return P[slot(y * CT + run_start_of(rows[y], x))] & LIDX;
 }
 
 // Tags the roots of components that reach the tile border.  Only those can
 // be joined to other tiles; a component that touches the image frame touches
 // the tile border too.  Lane = row.
 __device__ void mark_touch(const Tile &t, const uint64_t *rows, int *P) {
-    const int y = threadIdx.x;
+    const int y = lane_id();
     const uint64_t m = rows[y];
     if (y < t.th && m) {
         if (y == 0 || y == t.th - 1) {
             for (uint64_t st = run_starts(m); st; st &= st - 1)
-                atomicOr(P + (P[y * CT + __builtin_ctzll(st)] & LIDX), TOUCH_BIT);
+                atomicOr(P + slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), TOUCH_BIT);
         } else {
-            if (m & 1ull) atomicOr(P + root_of(rows, P, 0, y), TOUCH_BIT);
-            if ((m >> (t.tw - 1)) & 1ull) atomicOr(P + root_of(rows, P, t.tw - 1, y), TOUCH_BIT);
+            if (m & 1ull) atomicOr(P + slot(root_of(rows, P, 0, y)), TOUCH_BIT);
+            if ((m >> (t.tw - 1)) & 1ull) atomicOr(P + slot(root_of(rows, P, t.tw - 1, y)), TOUCH_BIT);
         }
     }
     __syncthreads();
 }
 
+// The wave's threshold level in the multi-level mode (idle waves: an empty
+// set, level 256).
+template <CclPred PR>
+__device__ __forceinline__ int wave_level(const CclArgs &A, int wave) {
+    if constexpr (PR == CclPred::Level) return wave < A.n_levels ? A.levels[wave] : 256;
+    else return 0;
+}
+
 // ---------------------------------------------------------------------------
 // local phase
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
-
-__global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, int total) {
-    __shared__ uint64_t rows[CT];
-    __shared__ int P[CT * CT];
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const CclArgs A = args[img_of(args, n, u)];
-        ccl_local_tile(A, u - A.unit0, rows, P);
-    }
-}
-
-__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
+template <CclPred PR, CclOut OU>
+__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, const WaveMem &M, int wave) {
     const Tile t = tile_of(A, b);
-    const int lane = threadIdx.x;
-    if (b == 0 && lane == 0) {  // the virtual node of every level is its own root
-        const int nl = A.pred == CclPred::Level ? A.n_levels : 1;
-        for (int l = 0; l < nl; ++l) A.ids[(int64_t)l * ((int64_t)A.w * A.h + 1)] = 0;
-    }
-    Col c;
-    load_col(A, t, c);
-    const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
+    const int lane = lane_id();
+    const bool live = PR != CclPred::Level || wave < A.n_levels;
     const int64_t nid = (int64_t)A.w * A.h + 1;
+    int32_t *ids = A.ids + (live ? wave : 0) * nid;
+    if (live && b == 0 && lane == 0) ids[0] = 0;   // the virtual node is its own root
+    build_rows<PR>(A, t, wave_level<PR>(A, wave), M.rows);
+    uint64_t *rows = M.rows;
+    int *P = M.P;
+    run_forest(rows, P, A.conn);
+    mark_touch(t, rows, P);
+    const int y = lane;
+    const uint64_t m = rows[y];
     const bool tile_on_frame = t.x0 == 0 || t.y0 == 0 || t.x0 + t.tw == A.w || t.y0 + t.th == A.h;
-    for (int lev = 0; lev < nlev; ++lev) {
-        const int level = A.pred == CclPred::Level ? A.levels[lev] : 0;
-        int32_t *ids = A.ids + lev * nid;
-        make_rows(A, t, c, level, rows);
-        run_forest(rows, P, A.conn);
-        mark_touch(t, rows, P);
-        const int y = lane;
-        const uint64_t m = rows[y];
-        if (A.frame_virtual && tile_on_frame) {
-            if (y < t.th && m) {
-                if (t.y0 + y == 0 || t.y0 + y == A.h - 1) {
-                    for (uint64_t st = run_starts(m); st; st &= st - 1)
-                        atomicOr(P + (P[y * CT + __builtin_ctzll(st)] & LIDX), FRAME_BIT);
-                } else {
-                    if (t.x0 == 0 && (m & 1ull)) atomicOr(P + root_of(rows, P, 0, y), FRAME_BIT);
-                    if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
-                        atomicOr(P + root_of(rows, P, t.tw - 1, y), FRAME_BIT);
-                }
+    if (A.frame_virtual && tile_on_frame) {
+        if (y < t.th && m) {
+            if (t.y0 + y == 0 || t.y0 + y == A.h - 1) {
+                for (uint64_t st = run_starts(m); st; st &= st - 1)
+                    atomicOr(P + slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), FRAME_BIT);
+            } else {
+                if (t.x0 == 0 && (m & 1ull)) atomicOr(P + slot(root_of(rows, P, 0, y)), FRAME_BIT);
+                if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
+                    atomicOr(P + slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
             }
-            __syncthreads();
         }
-        // roots (lane = row)
-        for (uint64_t st = run_starts(m); st; st &= st - 1) {
-            int s = __builtin_ctzll(st);
-            int li = y * CT + s;
-            int pv = P[li];
-            if ((pv & LIDX) != li) continue;
-            int id = gid(A, t, s, y);
-            if (pv & TOUCH_BIT) ids[id] = (pv & FRAME_BIT) ? 0 : id;
+        __syncthreads();
+    }
+    if (!live) return;
+    // roots (lane = row)
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        const int s = __builtin_ctzll(st);
+        const int li = y * CT + s;
+        const int pv = P[slot(li)];
+        if ((pv & LIDX) != li) continue;
+        const int id = gid(A, t, s, y);
+        if (pv & TOUCH_BIT) ids[id] = (pv & FRAME_BIT) ? 0 : id;
+        if constexpr (OU == CclOut::Labels) {
             if (A.st_area) {
                 A.st_area[id] = 0;
                 A.st_x0[id] = 0x7fffffff;
@@ -326,35 +450,44 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, uint64_t
                 A.st_y1[id] = -1;
             }
         }
-        // edge pixels that are not roots: left / right columns (lane = row)
-        if (m & 1ull) {
-            int r = root_of(rows, P, 0, y);
-            if (r != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r & 63, r >> 6);
+    }
+    // edge pixels that are not roots: left / right columns (lane = row)
+    if (m & 1ull) {
+        const int r = root_of(rows, P, 0, y);
+        if (r != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r & 63, r >> 6);
+    }
+    if (t.tw > 1 && ((m >> (t.tw - 1)) & 1ull)) {
+        const int r = root_of(rows, P, t.tw - 1, y);
+        if (r != y * CT + t.tw - 1) ids[gid(A, t, t.tw - 1, y)] = gid(A, t, r & 63, r >> 6);
+    }
+    // top / bottom rows (lane = column)
+    {
+        const int x = lane;
+        if ((rows[0] >> x) & 1ull) {
+            const int r = root_of(rows, P, x, 0);
+            if (r != x) ids[gid(A, t, x, 0)] = gid(A, t, r & 63, r >> 6);
         }
-        if (t.tw > 1 && ((m >> (t.tw - 1)) & 1ull)) {
-            int r = root_of(rows, P, t.tw - 1, y);
-            int li = y * CT + t.tw - 1;
-            if (r != li) ids[gid(A, t, t.tw - 1, y)] = gid(A, t, r & 63, r >> 6);
+        const int yb = t.th - 1;
+        if (yb > 0 && ((rows[yb] >> x) & 1ull)) {
+            const int r = root_of(rows, P, x, yb);
+            if (r != yb * CT + x) ids[gid(A, t, x, yb)] = gid(A, t, r & 63, r >> 6);
         }
-        // top / bottom rows (lane = column)
-        {
-            const int x = lane;
-            if ((rows[0] >> x) & 1ull) {
-                int r = root_of(rows, P, x, 0);
-                if (r != x) ids[gid(A, t, x, 0)] = gid(A, t, r & 63, r >> 6);
-            }
-            const int yb = t.th - 1;
-            if (yb > 0 && ((rows[yb] >> x) & 1ull)) {
-                int r = root_of(rows, P, x, yb);
-                if (r != yb * CT + x) ids[gid(A, t, x, yb)] = gid(A, t, r & 63, r >> 6);
-            }
-        }
+    }
+}
+
+template <CclPred PR, CclOut OU>
+__global__ __launch_bounds__(CT * MAXLEV) void k_ccl_local(const CclArgs *args, int n, int total) {
+    const int wave = threadIdx.x / CT;
+    const WaveMem M = wave_mem(wave);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        ccl_local_tile<PR, OU>(A, u - A.unit0, M, wave);
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// merge phase: one wave per tile, its right and bottom edges
+// merge phase: one wave per tile (and level), its right and bottom edges
 // ---------------------------------------------------------------------------
 // unites the pairs (a(i), b(i+d)), d in {-1,0,1} (8-conn) or {0} (4-conn),
 // along an edge; a/b bit i = member at position i (b has two extra members
@@ -391,181 +524,342 @@ __device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bo
     }
 }
 
-__device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b);
-
-__global__ __launch_bounds__(CT) void k_ccl_merge(const CclArgs *args, int n, int total) {
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const CclArgs A = args[img_of(args, n, u)];
-        ccl_merge_tile(A, u - A.unit0);
+// Wave 2l handles the right edge and wave 2l + 1 the bottom edge of the
+// tile at level l, so the two edges' unions overlap.
+template <CclPred PR>
+__device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b, int wave) {
+    const Tile t = tile_of(A, b);
+    const int lane = lane_id();
+    const int lev = PR == CclPred::Level ? wave >> 1 : 0;
+    const bool right_edge = (wave & 1) == 0;
+    if (PR == CclPred::Level && lev >= A.n_levels) return;
+    const int64_t nid = (int64_t)A.w * A.h + 1;
+    const int level = wave_level<PR>(A, lev);
+    int32_t *ids = A.ids + lev * nid;
+    if (right_edge) {   // a = column x0+63, b = column x0+64, position = row
+        if (t.x0 + CT >= A.w) return;
+        const int xa = t.x0 + CT - 1, xb = t.x0 + CT;
+        const bool ok = lane < t.th;
+        const bool a = ok && eval_pred<PR>(A, xa, t.y0 + lane, level);
+        const bool b = ok && eval_pred<PR>(A, xb, t.y0 + lane, level);
+        const bool bm1 = t.y0 > 0 && eval_pred<PR>(A, xb, t.y0 - 1, level);
+        const bool b64 = t.y0 + CT < A.h && eval_pred<PR>(A, xb, t.y0 + CT, level);
+        const uint64_t am = __ballot(a), bm = __ballot(b);
+        if (ok)
+            edge_unions(ids, am, bm, bm1, b64, A.conn, lane, (t.y0 + lane) * A.w + xa + 1, t.y0 * A.w + xb + 1, A.w);
+    } else {  // a = row y0+63, b = row y0+64, position = column
+        if (t.y0 + CT >= A.h) return;
+        const int ya = t.y0 + CT - 1, yb = t.y0 + CT;
+        const bool ok = lane < t.tw;
+        const bool a = ok && eval_pred<PR>(A, t.x0 + lane, ya, level);
+        const bool b = ok && eval_pred<PR>(A, t.x0 + lane, yb, level);
+        const bool bm1 = t.x0 > 0 && eval_pred<PR>(A, t.x0 - 1, yb, level);
+        const bool b64 = t.x0 + CT < A.w && eval_pred<PR>(A, t.x0 + CT, yb, level);
+        const uint64_t am = __ballot(a), bm = __ballot(b);
+        if (ok) edge_unions(ids, am, bm, bm1, b64, A.conn, lane, ya * A.w + t.x0 + lane + 1, yb * A.w + t.x0 + 1, 1);
     }
 }
 
-__device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b) {
-    const Tile t = tile_of(A, b);
-    const int lane = threadIdx.x;
-    const int nlev = A.pred == CclPred::Level ? A.n_levels : 1;
-    const int64_t nid = (int64_t)A.w * A.h + 1;
-    const bool right = t.x0 + CT < A.w;
-    const bool bottom = t.y0 + CT < A.h;
-    if (!right && !bottom) return;
-    for (int lev = 0; lev < nlev; ++lev) {
-        const int level = A.pred == CclPred::Level ? A.levels[lev] : 0;
-        int32_t *ids = A.ids + lev * nid;
-        if (right) {   // a = column x0+63, b = column x0+64, position = row
-            const int xa = t.x0 + CT - 1, xb = t.x0 + CT;
-            bool a = lane < t.th && eval_pred(A, xa, t.y0 + lane, level);
-            bool b = lane < t.th && eval_pred(A, xb, t.y0 + lane, level);
-            uint64_t am = __ballot(a), bm = __ballot(b);
-            bool bm1 = t.y0 > 0 && eval_pred(A, xb, t.y0 - 1, level);
-            bool b64 = t.y0 + CT < A.h && eval_pred(A, xb, t.y0 + CT, level);
-            if (lane < t.th)
-                edge_unions(ids, am, bm, bm1, b64, A.conn, lane, (t.y0 + lane) * A.w + xa + 1,
-                            t.y0 * A.w + xb + 1, A.w);
-        }
-        if (bottom) {  // a = row y0+63, b = row y0+64, position = column
-            const int ya = t.y0 + CT - 1, yb = t.y0 + CT;
-            bool a = lane < t.tw && eval_pred(A, t.x0 + lane, ya, level);
-            bool b = lane < t.tw && eval_pred(A, t.x0 + lane, yb, level);
-            uint64_t am = __ballot(a), bm = __ballot(b);
-            bool bm1 = t.x0 > 0 && eval_pred(A, t.x0 - 1, yb, level);
-            bool b64 = t.x0 + CT < A.w && eval_pred(A, t.x0 + CT, yb, level);
-            if (lane < t.tw)
-                edge_unions(ids, am, bm, bm1, b64, A.conn, lane, ya * A.w + t.x0 + lane + 1, yb * A.w + t.x0 + 1, 1);
-        }
+template <CclPred PR, CclOut OU>
+__global__ __launch_bounds__(2 * CT * MAXLEV) void k_ccl_merge(const CclArgs *args, int n, int total) {
+    const int wave = threadIdx.x / CT;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        ccl_merge_tile<PR>(A, u - A.unit0, wave);
     }
 }
 
 // ---------------------------------------------------------------------------
 // flatten phase + outputs
 // ---------------------------------------------------------------------------
-// Replaces, for every local root r, P[r] by -(global root id) - 1.  A
-// component that does not reach the tile border is complete: its root is
-// its global root.  The others look theirs up.
-__device__ void resolve_roots(const CclArgs &A, const Tile &t, const uint64_t *rows, int *P, int32_t *ids) {
+// Sets, for every run start r, P[r] = -(global root id of its component) - 1.
+// A component that does not reach the tile border is complete: its root is
+// its global root.  The roots of the others are gathered into a list and
+// looked up one per lane, so that their global finds overlap.
+__device__ void resolve_roots(const CclArgs &A, const Tile &t, const WaveMem &M, const int32_t *ids, bool live) {
+    const uint64_t *rows = M.rows;
+    int *P = M.P;
+    if (lane_id() == 0) *M.count = 0;
     mark_touch(t, rows, P);
-    const int y = threadIdx.x;
-    const uint64_t m = rows[y];
+    const int y = lane_id();
+    const uint64_t m = live ? rows[y] : 0ull;
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
         const int s = __builtin_ctzll(st);
         const int li = y * CT + s;
-        const int pv = P[li];
+        const int pv = P[slot(li)];
         if ((pv & LIDX) != li) continue;
-        const int id = gid(A, t, s, y);
-        P[li] = -((pv & TOUCH_BIT) ? gfind_ro(ids, id) : id) - 1;
+        if (pv & TOUCH_BIT)
+            M.list[atomicAdd(M.count, 1)] = li;
+        else
+            P[slot(li)] = -gid(A, t, s, y) - 1;
+    }
+    __syncthreads();
+    const int nl = *M.count;
+    for (int i = y; i < nl; i += CT) {
+        const int li = M.list[i];
+        P[slot(li)] = -gfind_ro(ids, gid(A, t, li & (CT - 1), li >> 6)) - 1;
+    }
+    __syncthreads();
+    // the other runs copy their root's entry (roots are only read here)
+    for (uint64_t st = run_starts(m); st; st &= st - 1) {
+        const int li = y * CT + __builtin_ctzll(st);
+        const int r = P[slot(li)];
+        if (r >= 0) P[slot(li)] = P[slot(r & LIDX)];
     }
     __syncthreads();
 }
 
+// global root of the run that starts at tile index li (after resolve_roots)
+__device__ __forceinline__ int global_of_run(const int *P, int li) { return -P[slot(li)] - 1; }
+
 __device__ __forceinline__ int global_of(const uint64_t *rows, const int *P, int x, int y) {
-    int r = P[y * CT + run_start_of(rows[y], x)];
-    if (r < 0) return -r - 1;
-    return -P[r] - 1;
+    return global_of_run(P, y * CT + run_start_of(rows[y], x));
 }
 
-__device__ __forceinline__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P);
-
-__global__ __launch_bounds__(CT) void k_ccl_flatten(const CclArgs *args, int n, int total) {
-    __shared__ uint64_t rows[CT];
-    __shared__ int P[CT * CT];
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const CclArgs A = args[img_of(args, n, u)];
-        ccl_flatten_tile(A, u - A.unit0, rows, P);
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ void ccl_flatten_tile(const CclArgs &A, int b, uint64_t *rows, int *P) {
-    const Tile t = tile_of(A, b);
-    const int lane = threadIdx.x;
-    Col c;
-    load_col(A, t, c);
-    const int64_t nid = (int64_t)A.w * A.h + 1;
-    const int x = lane;
-
-    if (A.out == CclOut::LevelBound) {
-        uint32_t best[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) best[k] = 0;
-        for (int lev = 0; lev < A.n_levels; ++lev) {
-            const int level = A.levels[lev];
-            make_rows(A, t, c, level, rows);
-            run_forest(rows, P, A.conn);
-            resolve_roots(A, t, rows, P, A.ids + lev * nid);
-#pragma unroll
-            for (int y = 0; y < CT; ++y) {
-                if (y >= t.th || !((rows[y] >> x) & 1ull)) continue;
-                if (global_of(rows, P, x, y) != 0) continue;
-                const uint32_t cur = (best[y >> 2] >> ((y & 3) * 8)) & 255u;
-                if ((uint32_t)level > cur)
-                    best[y >> 2] = (best[y >> 2] & ~(255u << ((y & 3) * 8))) | ((uint32_t)level << ((y & 3) * 8));
-            }
-            __syncthreads();
-        }
-        if (x < t.tw) {
-            const int gx = t.x0 + x;
-#pragma unroll
-            for (int y = 0; y < CT; ++y) {
-                if (y >= t.th) continue;
-                const int gy = t.y0 + y;
-                int v = (best[y >> 2] >> ((y & 3) * 8)) & 255;
-                if (gx == 0 || gy == 0 || gx == A.w - 1 || gy == A.h - 1) {
-                    int j = (c.v[y >> 2] >> ((y & 3) * 8)) & 255;   // frame marker J = Hq
-                    v = v > j ? v : j;
-                }
-                A.bound[(int64_t)gy * A.pitch_r + gx] = (uint8_t)v;
-            }
-        }
+// Stores 16 bytes (nvalid of them inside the image).
+__device__ __forceinline__ void store16(uint8_t *p, const uint32_t w[4], int nvalid, bool wide) {
+    if (wide && nvalid == 16) {
+        *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
         return;
     }
+    for (int i = 0; i < nvalid; ++i) p[i] = (uint8_t)(w[i >> 2] >> ((i & 3) * 8));
+}
 
-    make_rows(A, t, c, 0, rows);
+// FillHoles and the multi-level bound need only the members whose component
+// reaches the virtual frame node.  Such a component reaches the tile border,
+// so its border pixels carry it: each run of a border row and each vertical
+// run of a border column looks up its global root once (the local phase
+// published every border pixel), the runs whose root is the frame node seed
+// the set, and a flood inside the tile row masks completes it.  No forest is
+// rebuilt.  The result rows go to the wave's LDS rows; wave l of the
+// multi-level mode holds level l.
+template <CclPred PR, CclOut OU>
+__device__ __forceinline__ void ccl_flatten_fc_tile(const CclArgs &A, int b, int wave) {
+    const Tile t = tile_of(A, b);
+    const int lane = lane_id();
+    const bool live = PR != CclPred::Level || wave < A.n_levels;
+    const int64_t nid = (int64_t)A.w * A.h + 1;
+    uint64_t *rows = ccl_smem + wave * CT;
+    build_rows<PR>(A, t, wave_level<PR>(A, wave), rows);
+    const uint64_t m = rows[lane];
+    const uint64_t top = rows[0], bot = rows[t.th - 1];
+    const uint64_t above = lane > 0 ? rows[lane - 1] : 0ull;
+    const int xr = t.tw - 1;
+    int x[4] = {-1, -1, -1, -1};
+    if (live) {
+        if ((run_starts(top) >> lane) & 1ull) x[0] = gid(A, t, lane, 0);
+        if (t.th > 1 && ((run_starts(bot) >> lane) & 1ull)) x[1] = gid(A, t, lane, t.th - 1);
+        if ((m & 1ull) && !(above & 1ull)) x[2] = gid(A, t, 0, lane);
+        if (xr > 0 && ((m >> xr) & 1ull) && !((above >> xr) & 1ull)) x[3] = gid(A, t, xr, lane);
+    }
+    gfind4_ro(A.ids + (live ? wave : 0) * nid, x);
+    const uint64_t s_top = __ballot(x[0] == 0), s_bot = __ballot(x[1] == 0);
+    const uint64_t lcol = run_fill(__ballot(m & 1ull), __ballot(x[2] == 0));
+    const uint64_t rcol = xr > 0 ? run_fill(__ballot((m >> xr) & 1ull), __ballot(x[3] == 0)) : 0ull;
+    uint64_t f = ((lcol >> lane) & 1ull) | (((rcol >> lane) & 1ull) << xr);
+    if (lane == 0) f |= s_top;
+    if (lane == t.th - 1) f |= s_bot;
+    f = flood_rows(m, f, A.conn);
+    __syncthreads();
+    rows[lane] = f;
+    __syncthreads();
+
+    const bool wide = OU == CclOut::LevelBound ? aligned16(A.bound, A.pitch_r) : aligned16(A.fill, A.pitch_f);
+    const int nw = OU == CclOut::LevelBound ? blockDim.x / CT : 1;
+    int lv[MAXLEV];
+    if constexpr (OU == CclOut::LevelBound) {
+#pragma unroll
+        for (int l = 0; l < MAXLEV; ++l) lv[l] = l < A.n_levels && l < nw ? A.levels[l] : 0;
+    }
+    for (int i = (int)threadIdx.x; i < CT * 4; i += nw * CT) {   // 16-pixel chunks
+        const int y = i >> 2, c = i & 3;
+        const int nvalid = y < t.th ? max(0, min(16, t.tw - 16 * c)) : 0;
+        if (nvalid == 0) continue;
+        const int64_t gy = t.y0 + y;
+        const int gx = t.x0 + 16 * c;
+        uint32_t w[4] = {0, 0, 0, 0};
+        if constexpr (OU == CclOut::FillHoles) {
+            // F = input | not frame-connected: members of the background
+            // components that reach the frame are the only zeros
+            const uint32_t fc = (uint32_t)(rows[y] >> (16 * c)) & 0xffffu;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w[k >> 2] |= (((fc >> k) & 1u) ? 0u : 1u) << ((k & 3) * 8);
+            store16(A.fill + gy * A.pitch_f + gx, w, nvalid, wide);
+        } else {
+            uint32_t fcl[MAXLEV];
+#pragma unroll
+            for (int l = 0; l < MAXLEV; ++l) fcl[l] = l < nw ? (uint32_t)(ccl_smem[l * CT + y] >> (16 * c)) & 0xffffu : 0u;
+            const bool frame_row = gy == 0 || gy == A.h - 1;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                int v = 0;
+#pragma unroll
+                for (int l = 0; l < MAXLEV; ++l)
+                    if ((fcl[l] >> k) & 1u) v = max(v, lv[l]);
+                const int xg = gx + k;
+                if (k < nvalid && (frame_row || xg == 0 || xg == A.w - 1))
+                    v = max(v, (int)A.a[gy * A.pitch_a + xg]);   // frame marker J = Hq
+                w[k >> 2] |= (uint32_t)v << ((k & 3) * 8);
+            }
+            store16(A.bound + gy * A.pitch_r + gx, w, nvalid, wide);
+        }
+    }
+}
+
+// BWLabel output: labels, background zeros of the output mask, and the
+// per-component statistics.  A tile's runs are first summed per component in
+// an LDS table (a few entries per tile), so each component costs one set of
+// global atomics per tile instead of one per run; components are registered
+// with one counter update per wave.
+__device__ __forceinline__ void ccl_flatten_labels_tile(const CclArgs &A, int b) {
+    const Tile t = tile_of(A, b);
+    const int lane = lane_id();
+    const WaveMem M = wave_mem(0);
+    uint64_t *rows = M.rows;
+    int *P = M.P;
+    build_rows<CclPred::NonZero>(A, t, 0, rows);
     run_forest(rows, P, A.conn);
-    resolve_roots(A, t, rows, P, A.ids);
-    if (x < t.tw) {
-        const int gx = t.x0 + x;
-        for (int y = 0; y < t.th; ++y) {
-            const int64_t gy = t.y0 + y;
-            const bool mem = (rows[y] >> x) & 1ull;
-            if (A.out == CclOut::Labels) {
+    resolve_roots(A, t, M, A.ids, true);
+    {
+        const int x = lane;
+        if (x < t.tw) {
+            const int gx = t.x0 + x;
+#pragma unroll 4
+            for (int y = 0; y < t.th; ++y) {
+                const int64_t gy = t.y0 + y;
+                const bool mem = (rows[y] >> x) & 1ull;
                 A.labels[gy * A.pitch_l + gx] = mem ? global_of(rows, P, x, y) : 0;
                 if (!mem && A.bg_zero_mask) A.bg_zero_mask[gy * A.pitch_m + gx] = 0;
-            } else {  // FillHoles: members are background pixels of the input
-                A.fill[gy * A.pitch_f + gx] = mem ? (global_of(rows, P, x, y) != 0 ? 1 : 0) : 1;
             }
         }
     }
-    if (A.out != CclOut::Labels || (!A.st_area && !A.obj_list)) return;
-    // per-run statistics and component registration (lane = row)
+    if (!A.st_area && !A.obj_list) return;
+    int *key = (int *)(ccl_smem + WAVE_LDS / 8);
+    int *area = key + NHASH, *x0 = area + NHASH, *x1 = x0 + NHASH, *y0 = x1 + NHASH, *y1 = y0 + NHASH;
+    int *reg = y1 + NHASH;
+    for (int i = lane; i < NHASH; i += CT) {
+        key[i] = -1;
+        area[i] = 0;
+        x0[i] = 0x7fffffff;
+        x1[i] = -1;
+        y0[i] = 0x7fffffff;
+        y1[i] = -1;
+        reg[i] = 0;
+    }
+    __syncthreads();
+    // per run (lane = row)
     const int y = lane;
     const uint64_t m = rows[y];
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
         const int s = __builtin_ctzll(st);
         const int len = run_len(m, s);
-        const int g = global_of(rows, P, s, y);
-        if (A.st_area) {
-            atomicAdd(A.st_area + g, len);
-            atomicMin(A.st_x0 + g, t.x0 + s);
-            atomicMax(A.st_x1 + g, t.x0 + s + len - 1);
-            atomicMin(A.st_y0 + g, t.y0 + y);
-            atomicMax(A.st_y1 + g, t.y0 + y);
+        const int g = global_of_run(P, y * CT + s);
+        const bool is_root = g == gid(A, t, s, y);
+        int k = (int)(((uint32_t)g * 2654435761u) >> 25) & (NHASH - 1);
+        bool ok = false;
+        for (int probe = 0; probe < NHASH; ++probe) {
+            const int old = atomicCAS(key + k, -1, g);
+            if (old == -1 || old == g) {
+                ok = true;
+                break;
+            }
+            k = (k + 1) & (NHASH - 1);
         }
-        if (A.obj_list && P[y * CT + s] < 0 && g == gid(A, t, s, y))
-            A.obj_list[atomicAdd(A.n_obj, 1)] = (A.img << 25) | g;
+        if (ok) {
+            atomicAdd(area + k, len);
+            atomicMin(x0 + k, t.x0 + s);
+            atomicMax(x1 + k, t.x0 + s + len - 1);
+            atomicMin(y0 + k, t.y0 + y);
+            atomicMax(y1 + k, t.y0 + y);
+            if (is_root) reg[k] = 1;
+        } else {   // table full: this run goes to global memory directly
+            if (A.st_area) {
+                atomicAdd(A.st_area + g, len);
+                atomicMin(A.st_x0 + g, t.x0 + s);
+                atomicMax(A.st_x1 + g, t.x0 + s + len - 1);
+                atomicMin(A.st_y0 + g, t.y0 + y);
+                atomicMax(A.st_y1 + g, t.y0 + y);
+            }
+            if (A.obj_list && is_root) A.obj_list[atomicAdd(A.n_obj, 1)] = (A.img << 25) | g;
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < NHASH; i += CT) {
+        const int g = key[i];
+        bool r = false;
+        if (g >= 0) {
+            if (A.st_area) {
+                atomicAdd(A.st_area + g, area[i]);
+                atomicMin(A.st_x0 + g, x0[i]);
+                atomicMax(A.st_x1 + g, x1[i]);
+                atomicMin(A.st_y0 + g, y0[i]);
+                atomicMax(A.st_y1 + g, y1[i]);
+            }
+            r = A.obj_list && reg[i];
+        }
+        const uint64_t bm = __ballot(r);
+        if (bm) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(A.n_obj, __popcll(bm));
+            base = __shfl(base, 0);
+            if (r) A.obj_list[base + __popcll(bm & ((1ull << lane) - 1))] = (A.img << 25) | g;
+        }
+    }
+}
+
+template <CclPred PR, CclOut OU>
+__global__ __launch_bounds__(CT * MAXLEV) void k_ccl_flatten(const CclArgs *args, int n, int total) {
+    const int wave = threadIdx.x / CT;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const CclArgs A = args[img_of(args, n, u)];
+        if constexpr (OU == CclOut::Labels)
+            ccl_flatten_labels_tile(A, u - A.unit0);
+        else
+            ccl_flatten_fc_tile<PR, OU>(A, u - A.unit0, wave);
+        __syncthreads();
     }
 }
 
 int ccl_tiles(int w, int h) { return ((w + CT - 1) / CT) * ((h + CT - 1) / CT); }
 
-int launch_ccl(const CclArgs *args_dev, int n, int total, int n_cu, hipStream_t s) {
-    if (total <= 0) return RT_OK;
-    const int grid = std::min(total, n_cu * 16);
-    hipLaunchKernelGGL(k_ccl_local, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
+template <CclPred PR, CclOut OU>
+static int launch_ccl_t(const CclArgs *args_dev, int n, int total, int n_cu, hipStream_t s, int nw) {
+    const size_t lds_local = (size_t)nw * WAVE_LDS;
+    const size_t lds_flat = OU == CclOut::Labels ? (size_t)LABELS_LDS : (size_t)nw * CT * 8;
+    static bool attr_set = false;
+    if (!attr_set && lds_local > 64 * 1024) {
+        RT_HIP(hipFuncSetAttribute((const void *)k_ccl_local<PR, OU>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   MAXLEV * WAVE_LDS));
+        attr_set = true;
+    }
+    const int grid = std::min(total, n_cu * 32);
+    hipLaunchKernelGGL((k_ccl_local<PR, OU>), dim3(grid), dim3(CT * nw), lds_local, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ccl_merge, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
+    hipLaunchKernelGGL((k_ccl_merge<PR, OU>), dim3(grid), dim3(2 * CT * nw), 0, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid), dim3(CT), 0, s, args_dev, n, total);
+    hipLaunchKernelGGL((k_ccl_flatten<PR, OU>), dim3(grid), dim3(CT * nw), lds_flat, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
     return RT_OK;
+}
+
+int launch_ccl(const CclArgs *args_dev, int n, int total, int n_cu, hipStream_t s, CclPred pred, CclOut out,
+               int n_levels) {
+    if (total <= 0) return RT_OK;
+    if (pred == CclPred::Level && out == CclOut::LevelBound) {
+        if (n_levels < 1 || n_levels > MAXLEV) {
+            set_error("ccl: %d threshold levels (1..%d)", n_levels, MAXLEV);
+            return RT_EINVAL;
+        }
+        return launch_ccl_t<CclPred::Level, CclOut::LevelBound>(args_dev, n, total, n_cu, s, n_levels);
+    }
+    if (pred == CclPred::TophatBg && out == CclOut::FillHoles)
+        return launch_ccl_t<CclPred::TophatBg, CclOut::FillHoles>(args_dev, n, total, n_cu, s, 1);
+    if (pred == CclPred::Zero && out == CclOut::FillHoles)
+        return launch_ccl_t<CclPred::Zero, CclOut::FillHoles>(args_dev, n, total, n_cu, s, 1);
+    if (pred == CclPred::NonZero && out == CclOut::Labels)
+        return launch_ccl_t<CclPred::NonZero, CclOut::Labels>(args_dev, n, total, n_cu, s, 1);
+    set_error("ccl: unsupported predicate / output pair");
+    return RT_EUNSUPPORTED;
 }
 
 }  // namespace rtseg

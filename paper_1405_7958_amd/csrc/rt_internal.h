@@ -160,7 +160,10 @@ struct CclArgs {
     int unit0;                     // first 64 x 64 tile of this image
 };
 int ccl_tiles(int w, int h);   // number of 64 x 64 CCL tiles of a w x h image
-int launch_ccl(const CclArgs *args_dev, int n, int total_units, int n_cu, hipStream_t s);
+// All records of one launch share the predicate and output (and, in the
+// multi-level mode, the number of levels).
+int launch_ccl(const CclArgs *args_dev, int n, int total_units, int n_cu, hipStream_t s, CclPred pred, CclOut out,
+               int n_levels = 1);
 
 // ---------------------------------------------------------------------------
 // reconstruction rounds
