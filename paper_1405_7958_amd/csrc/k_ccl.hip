@@ -8,8 +8,7 @@
 // atomics), and only runs of adjacent rows that touch are united (LDS
 // atomicMin, the root is always the smallest index, so labels are canonical
 // by construction).  Two run starts of one row are at least two pixels apart,
-// so the forest needs one LDS slot per pixel pair (8 KB per tile).  Three
-// launches:
+// so the forest needs one LDS slot per pixel pair.  Three launches:
 //   local  : build the tile forest; publish only its roots and its edge
 //            pixels to the global id array (id 0 = virtual node, pixel p has
 //            id p + 1);
@@ -24,10 +23,11 @@
 // Modes: BWLabel (labels, per-component area and bounding box, component
 // list), FillHoles (background components joined to a virtual frame node),
 // and the multi-level frame-connectivity lower bound that starts the
-// grayscale reconstruction.  In the multi-level mode a workgroup holds one
-// wave per threshold level of the same tile: the levels' forests and global
-// unions proceed side by side, and the flatten combines the levels' frame-
-// connected pixel sets in LDS before one write of the bound.
+// grayscale reconstruction.  In the multi-level mode the local phase takes
+// one wave per (tile, level) and the merge one wave per (level, edge) of a
+// tile, so the levels' forests and global unions proceed side by side; the
+// flatten holds one wave per level of a tile in a workgroup and combines the
+// levels' frame-connected pixel sets in LDS before one write of the bound.
 //
 // Every kernel is specialised for its predicate and output, so each one is
 // straight-line code for its own mode.  Tile rows are read with 16-byte loads
@@ -39,13 +39,14 @@ namespace rtseg {
 constexpr int CT = 64;                 // tile edge = wavefront size
 constexpr int MAXLEV = 8;
 constexpr int NSLOT = CT * CT / 2;     // forest slots: one per pixel pair of a row
-constexpr int FRAME_BIT = 1 << 30;     // tags a local root whose component touches the image frame
-constexpr int TOUCH_BIT = 1 << 29;     // tags a local root whose component touches the tile border
+constexpr int FRAME_BIT = 1 << 12;     // tags a local root whose component touches the image frame
+constexpr int TOUCH_BIT = 1 << 13;     // tags a local root whose component touches the tile border
 constexpr int LIDX = 0xfff;
 constexpr int NLIST = 128;             // components touching a tile border: at most 126 (one per two border pixels)
 constexpr int WAVE_LDS = CT * 8 + NSLOT * 4 + NLIST * 4 + 16;   // bytes per wave: row masks, forest, root list
 constexpr int NHASH = 128;             // per-tile component table of the statistics pass
 constexpr int LABELS_LDS = WAVE_LDS + NHASH * 7 * 4;
+constexpr int LOCAL_LDS = CT * 8 + NSLOT * 2;   // local phase: row masks + 16-bit forest
 
 extern __shared__ uint64_t ccl_smem[];
 
@@ -71,21 +72,60 @@ __device__ __forceinline__ int ld_agent(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Finds with path halving: a node is re-pointed to its grandparent with
-// atomicMin, so parent pointers only ever move to a smaller ancestor and a
-// concurrent link can never be undone.  Nodes are tile indices of run starts.
-__device__ __forceinline__ int lfind(int *P, int x) {
-    int p = __hip_atomic_load(P + slot(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Forest entries: the tile index of the parent run start (12 bits) and the
+// two tags.  The local phase keeps them in 16 bits (4 KB per tile, which
+// doubles the waves an LDS budget holds); the BWLabel flatten keeps 32 bits,
+// because it replaces the roots' entries by global ids.  A link at a root is
+// an atomic minimum (for 16-bit entries a compare-and-swap of the 32-bit word
+// that holds two of them); path halving may use plain stores, because a
+// non-root entry only ever moves to another ancestor.
+__device__ __forceinline__ int p_load(const int *P, int i) {
+    return __hip_atomic_load(P + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void p_halve(int *P, int i, int v) { atomicMin(P + i, v); }
+__device__ __forceinline__ int p_link(int *P, int i, int v) { return atomicMin(P + i, v); }
+__device__ __forceinline__ void p_or(int *P, int i, int bits) { atomicOr(P + i, bits); }
+
+__device__ __forceinline__ int p_load(const uint16_t *P, int i) {
+    return __hip_atomic_load(P + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void p_halve(uint16_t *P, int i, int v) {
+    __hip_atomic_store(P + i, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int p_link(uint16_t *P, int i, int v) {   // atomic min, returns the old entry
+    uint32_t *w = (uint32_t *)P + (i >> 1);
+    const int sh = (i & 1) * 16;
+    uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const int cur = (int)((old >> sh) & 0xffffu);
+        if (cur <= v) return cur;
+        const uint32_t nw = (old & ~(0xffffu << sh)) | ((uint32_t)v << sh);
+        const uint32_t got = atomicCAS(w, old, nw);
+        if (got == old) return cur;
+        old = got;
+    }
+}
+__device__ __forceinline__ void p_or(uint16_t *P, int i, int bits) {
+    atomicOr((uint32_t *)P + (i >> 1), (uint32_t)bits << ((i & 1) * 16));
+}
+
+// Finds with path halving: a node is re-pointed to its grandparent, so
+// parent pointers only ever move to an ancestor and a concurrent link can
+// never be undone.  Nodes are tile indices of run starts.
+template <typename PT>
+__device__ __forceinline__ int lfind(PT *P, int x) {
+    int p = p_load(P, slot(x));
     while (p != x) {
-        const int gp = __hip_atomic_load(P + slot(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (gp != p) atomicMin(P + slot(x), gp);
+        const int gp = p_load(P, slot(p));
+        if (gp != p) p_halve(P, slot(x), gp);
         x = p;
         p = gp;
     }
     return x;
 }
 
-__device__ __forceinline__ void lunite(int *P, int a, int b) {
+template <typename PT>
+__device__ __forceinline__ void lunite(PT *P, int a, int b) {
     for (;;) {
         a = lfind(P, a);
         b = lfind(P, b);
@@ -95,7 +135,7 @@ __device__ __forceinline__ void lunite(int *P, int a, int b) {
             a = b;
             b = t;
         }
-        int old = atomicMin(P + slot(a), b);
+        const int old = p_link(P, slot(a), b);
         if (old == a) return;
         a = old;
     }
@@ -335,12 +375,13 @@ __device__ void build_rows(const CclArgs &A, const Tile &t, int level, uint64_t 
 
 // Tile forest over runs: after the call, P[slot(y*64+s)] = local root (tile
 // index of a run start) for every run start s of row y.  Lane = row.
-__device__ void run_forest(const uint64_t *rows, int *P, int conn) {
+template <typename PT>
+__device__ void run_forest(const uint64_t *rows, PT *P, int conn) {
     const int y = lane_id();
     const uint64_t m = rows[y];
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
         const int li = y * CT + __builtin_ctzll(st);
-        P[slot(li)] = li;
+        P[slot(li)] = (PT)li;
     }
     __syncthreads();
     if (y > 0) {
@@ -365,28 +406,30 @@ __device__ void run_forest(const uint64_t *rows, int *P, int conn) {
     __syncthreads();
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
         const int li = y * CT + __builtin_ctzll(st);
-        P[slot(li)] = lfind(P, li);
+        P[slot(li)] = (PT)lfind(P, li);
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ int root_of(const uint64_t *rows, const int *P, int x, int y) {
+template <typename PT>
+__device__ __forceinline__ int root_of(const uint64_t *rows, const PT *P, int x, int y) {
     return P[slot(y * CT + run_start_of(rows[y], x))] & LIDX;
 }
 
 // Tags the roots of components that reach the tile border.  Only those can
 // be joined to other tiles; a component that touches the image frame touches
 // the tile border too.  Lane = row.
-__device__ void mark_touch(const Tile &t, const uint64_t *rows, int *P) {
+template <typename PT>
+__device__ void mark_touch(const Tile &t, const uint64_t *rows, PT *P) {
     const int y = lane_id();
     const uint64_t m = rows[y];
     if (y < t.th && m) {
         if (y == 0 || y == t.th - 1) {
             for (uint64_t st = run_starts(m); st; st &= st - 1)
-                atomicOr(P + slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), TOUCH_BIT);
+                p_or(P, slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), TOUCH_BIT);
         } else {
-            if (m & 1ull) atomicOr(P + slot(root_of(rows, P, 0, y)), TOUCH_BIT);
-            if ((m >> (t.tw - 1)) & 1ull) atomicOr(P + slot(root_of(rows, P, t.tw - 1, y)), TOUCH_BIT);
+            if (m & 1ull) p_or(P, slot(root_of(rows, P, 0, y)), TOUCH_BIT);
+            if ((m >> (t.tw - 1)) & 1ull) p_or(P, slot(root_of(rows, P, t.tw - 1, y)), TOUCH_BIT);
         }
     }
     __syncthreads();
@@ -404,16 +447,16 @@ __device__ __forceinline__ int wave_level(const CclArgs &A, int wave) {
 // local phase
 // ---------------------------------------------------------------------------
 template <CclPred PR, CclOut OU>
-__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, const WaveMem &M, int wave) {
+__device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave) {
     const Tile t = tile_of(A, b);
     const int lane = lane_id();
     const bool live = PR != CclPred::Level || wave < A.n_levels;
     const int64_t nid = (int64_t)A.w * A.h + 1;
     int32_t *ids = A.ids + (live ? wave : 0) * nid;
     if (live && b == 0 && lane == 0) ids[0] = 0;   // the virtual node is its own root
-    build_rows<PR>(A, t, wave_level<PR>(A, wave), M.rows);
-    uint64_t *rows = M.rows;
-    int *P = M.P;
+    uint64_t *rows = ccl_smem;
+    uint16_t *P = (uint16_t *)(ccl_smem + CT);
+    build_rows<PR>(A, t, wave_level<PR>(A, wave), rows);
     run_forest(rows, P, A.conn);
     mark_touch(t, rows, P);
     const int y = lane;
@@ -423,11 +466,11 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, const Wa
         if (y < t.th && m) {
             if (t.y0 + y == 0 || t.y0 + y == A.h - 1) {
                 for (uint64_t st = run_starts(m); st; st &= st - 1)
-                    atomicOr(P + slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), FRAME_BIT);
+                    p_or(P, slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), FRAME_BIT);
             } else {
-                if (t.x0 == 0 && (m & 1ull)) atomicOr(P + slot(root_of(rows, P, 0, y)), FRAME_BIT);
+                if (t.x0 == 0 && (m & 1ull)) p_or(P, slot(root_of(rows, P, 0, y)), FRAME_BIT);
                 if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
-                    atomicOr(P + slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
+                    p_or(P, slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
             }
         }
         __syncthreads();
@@ -475,13 +518,13 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, const Wa
     }
 }
 
+// One wave per (tile, level): unit u is tile u / nw at level u % nw.
 template <CclPred PR, CclOut OU>
-__global__ __launch_bounds__(CT * MAXLEV) void k_ccl_local(const CclArgs *args, int n, int total) {
-    const int wave = threadIdx.x / CT;
-    const WaveMem M = wave_mem(wave);
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const CclArgs A = args[img_of(args, n, u)];
-        ccl_local_tile<PR, OU>(A, u - A.unit0, M, wave);
+__global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, int total, int nw) {
+    for (int u = blockIdx.x; u < total * nw; u += gridDim.x) {
+        const int tu = u / nw;
+        const CclArgs A = args[img_of(args, n, tu)];
+        ccl_local_tile<PR, OU>(A, tu - A.unit0, u - tu * nw);
         __syncthreads();
     }
 }
@@ -560,6 +603,7 @@ __device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b, int wave
     }
 }
 
+// One workgroup per tile, one wave per (level, edge).
 template <CclPred PR, CclOut OU>
 __global__ __launch_bounds__(2 * CT * MAXLEV) void k_ccl_merge(const CclArgs *args, int n, int total) {
     const int wave = threadIdx.x / CT;
@@ -824,20 +868,15 @@ int ccl_tiles(int w, int h) { return ((w + CT - 1) / CT) * ((h + CT - 1) / CT); 
 
 template <CclPred PR, CclOut OU>
 static int launch_ccl_t(const CclArgs *args_dev, int n, int total, int n_cu, hipStream_t s, int nw) {
-    const size_t lds_local = (size_t)nw * WAVE_LDS;
     const size_t lds_flat = OU == CclOut::Labels ? (size_t)LABELS_LDS : (size_t)nw * CT * 8;
-    static bool attr_set = false;
-    if (!attr_set && lds_local > 64 * 1024) {
-        RT_HIP(hipFuncSetAttribute((const void *)k_ccl_local<PR, OU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   MAXLEV * WAVE_LDS));
-        attr_set = true;
-    }
-    const int grid = std::min(total, n_cu * 32);
-    hipLaunchKernelGGL((k_ccl_local<PR, OU>), dim3(grid), dim3(CT * nw), lds_local, s, args_dev, n, total);
+    const int cap = n_cu * 128;
+    hipLaunchKernelGGL((k_ccl_local<PR, OU>), dim3(std::min(total * nw, cap)), dim3(CT), LOCAL_LDS, s, args_dev, n,
+                       total, nw);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_ccl_merge<PR, OU>), dim3(grid), dim3(2 * CT * nw), 0, s, args_dev, n, total);
+    hipLaunchKernelGGL((k_ccl_merge<PR, OU>), dim3(std::min(total, cap)), dim3(2 * CT * nw), 0, s, args_dev, n, total);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_ccl_flatten<PR, OU>), dim3(grid), dim3(CT * nw), lds_flat, s, args_dev, n, total);
+    hipLaunchKernelGGL((k_ccl_flatten<PR, OU>), dim3(std::min(total, cap)), dim3(CT * nw), lds_flat, s, args_dev, n,
+                       total);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -184,19 +184,19 @@ __device__ void recon_scans(const Crop<L> &m, V *val, const int32_t *M) {
     for (;;) {
         bool ch = false;
         for (int r = 0; r < m.ch; ++r) {
-            for (int c = lane; c < m.cw; c += WAVE) ch |= relax1(m, val, M, r, c);
+            for (int c = lane; c < m.cw; c += blockDim.x) ch |= relax1(m, val, M, r, c);
             __syncthreads();
         }
         for (int r = m.ch - 1; r >= 0; --r) {
-            for (int c = lane; c < m.cw; c += WAVE) ch |= relax1(m, val, M, r, c);
+            for (int c = lane; c < m.cw; c += blockDim.x) ch |= relax1(m, val, M, r, c);
             __syncthreads();
         }
         for (int c = 0; c < m.cw; ++c) {
-            for (int r = lane; r < m.ch; r += WAVE) ch |= relax1(m, val, M, r, c);
+            for (int r = lane; r < m.ch; r += blockDim.x) ch |= relax1(m, val, M, r, c);
             __syncthreads();
         }
         for (int c = m.cw - 1; c >= 0; --c) {
-            for (int r = lane; r < m.ch; r += WAVE) ch |= relax1(m, val, M, r, c);
+            for (int r = lane; r < m.ch; r += blockDim.x) ch |= relax1(m, val, M, r, c);
             __syncthreads();
         }
         if (!wave_or(ch)) break;
@@ -245,65 +245,71 @@ __device__ __forceinline__ bool reg_scan(int (&v)[R], const int (&mk)[R], bool f
     return ch;
 }
 
-// Tv, Tm: two R x (R+1) LDS arrays of the calling kernel.  The crop is first
-// staged there with a strided copy (NEGV outside the crop and outside the
-// component), so the unrolled register loads use constant LDS offsets.
+// Within one wave: LDS operations of a wavefront complete in order, so
+// ordering the compiler's memory operations suffices.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In place on the crop plane V, whose row stride is R + 1: the plane is the
+// R x (R+1) block the transposes go through.  Entries of V and M outside the
+// crop rows and columns, and entries of M outside the component, are set to
+// NEGV first (V is NEGV outside the component already; no later step reads
+// M there).  Wave 0 holds the registers and runs the sweeps; the other waves
+// of the workgroup wait.
 template <int R, typename L>
-__device__ __forceinline__ void reg_recon(const Crop<L> &m, int32_t *V, const int32_t *M, int *Tv, int *Tm) {
-    const int lane = threadIdx.x;
+__device__ __forceinline__ void reg_recon(const Crop<L> &m, int32_t *V, int32_t *M) {
     constexpr int TS = R + 1;
-    for (int k = lane; k < R * R; k += WAVE) {
-        const int j = k / R, c = k % R;
-        int vv = NEGV, mm = NEGV;
-        if (c < m.cw && j < m.ch) {
-            const int i = j * m.st + c;
-            vv = V[i];
-            if (m.fl[i] & F_IN) mm = M[i];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = tid; k < R * TS; k += nt) {
+        const int j = k / TS, c = k - j * TS;
+        if (j >= m.ch || c >= m.cw) {
+            V[k] = NEGV;
+            M[k] = NEGV;
+        } else if (!(m.fl[k] & F_IN)) {
+            M[k] = NEGV;
         }
-        Tv[j * TS + c] = vv;
-        Tm[j * TS + c] = mm;
     }
     __syncthreads();
-    const int cl = lane & (R - 1);
-    const bool first = cl == 0, last = cl == R - 1;
-    int v[R], mc[R], mr[R];
+    if (tid < WAVE) {
+        const int cl = tid & (R - 1);
+        const bool first = cl == 0, last = cl == R - 1;
+        int v[R], mc[R], mr[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        v[j] = Tv[j * TS + cl];
-        mc[j] = Tm[j * TS + cl];
-        mr[j] = Tm[cl * TS + j];
-    }
-    __syncthreads();
-    for (;;) {
-        bool ch = reg_scan<R>(v, mc, first, last);
+        for (int j = 0; j < R; ++j) {
+            v[j] = V[j * TS + cl];
+            mc[j] = M[j * TS + cl];
+            mr[j] = M[cl * TS + j];
+        }
+        wave_sync();
+        for (;;) {
+            bool ch = reg_scan<R>(v, mc, first, last);
 #pragma unroll
-        for (int j = 0; j < R; ++j) Tv[j * TS + cl] = v[j];
-        __syncthreads();
+            for (int j = 0; j < R; ++j) V[j * TS + cl] = v[j];
+            wave_sync();
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = Tv[cl * TS + i];
-        __syncthreads();
-        ch |= reg_scan<R>(v, mr, first, last);
+            for (int i = 0; i < R; ++i) v[i] = V[cl * TS + i];
+            wave_sync();
+            ch |= reg_scan<R>(v, mr, first, last);
 #pragma unroll
-        for (int i = 0; i < R; ++i) Tv[cl * TS + i] = v[i];
-        __syncthreads();
+            for (int i = 0; i < R; ++i) V[cl * TS + i] = v[i];
+            wave_sync();
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = Tv[j * TS + cl];
-        __syncthreads();
-        if (!wave_or(ch)) break;
-    }
-    // Tv holds the result (row-major); copy the crop back
-    for (int k = lane; k < R * R; k += WAVE) {
-        const int j = k / R, c = k % R;
-        if (c < m.cw && j < m.ch) V[j * m.st + c] = Tv[j * TS + c];
+            for (int j = 0; j < R; ++j) v[j] = V[j * TS + cl];
+            wave_sync();
+            if (!__any(ch)) break;
+        }
     }
     __syncthreads();
 }
 
 // V <- recon of V under M: registers when the crop fits R x R, else LDS scans
 template <int R, typename L>
-__device__ __forceinline__ void recon_any(const Crop<L> &m, int32_t *V, const int32_t *M, int *Ts) {
+__device__ __forceinline__ void recon_any(const Crop<L> &m, int32_t *V, int32_t *M) {
     if constexpr (R > 0) {
-        reg_recon<R, L>(m, V, M, Ts, Ts + R * (R + 1));
+        reg_recon<R, L>(m, V, M);
     } else {
         recon_scans<L, int32_t>(m, V, M);
     }
@@ -321,7 +327,7 @@ __device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e)
     const L lmask = one - 1;
     for (;;) {
         bool ch = false;
-        for (int pos = b + threadIdx.x; pos < e; pos += WAVE) {
+        for (int pos = b + threadIdx.x; pos < e; pos += blockDim.x) {
             const int i = list[pos];
             const L cur = m.B[i];
             L best = cur <= -2 ? -cur - 2 : (L)-1;  // -1 = none yet (as unsigned compare below)
@@ -358,7 +364,7 @@ __device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e)
         }
         if (!wave_or(ch)) break;
     }
-    for (int pos = b + threadIdx.x; pos < e; pos += WAVE) {
+    for (int pos = b + threadIdx.x; pos < e; pos += blockDim.x) {
         const int i = list[pos];
         const L cur = m.B[i];
         if (cur <= -2) m.B[i] = (-cur - 2) & lmask;
@@ -368,13 +374,13 @@ __device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e)
 
 // ---- the whole per-component stage ---------------------------------------------
 template <int R, typename L>
-__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int *Ts) {
+__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist) {
     const int lane = threadIdx.x;
     const int area = a.st_area[g];
     // ---- load the component
     bool zero = false;
 #pragma unroll 8
-    for (int i = lane; i < m.n; i += WAVE) {
+    for (int i = lane; i < m.n; i += blockDim.x) {
         const int c = i % m.st, r = i / m.st;
         bool in = false;
         if (c < m.cw) {
@@ -385,7 +391,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     }
     const bool has_zero = wave_or(zero);
     // ---- exact distance transform: column distances, then a pruned row search
-    for (int c = lane; c < m.cw; c += WAVE) {
+    for (int c = lane; c < m.cw; c += blockDim.x) {
         int run = GINF;
         for (int r = 0; r < m.ch; ++r) {
             const int i = r * m.st + c;
@@ -400,7 +406,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         }
     }
     __syncthreads();
-    for (int i = lane; i < m.n; i += WAVE) {
+    for (int i = lane; i < m.n; i += blockDim.x) {
         const int c = i % m.st, r = i / m.st;
         if (c >= m.cw || !(m.fl[i] & F_IN)) {
             m.dq[i] = 0;
@@ -425,27 +431,27 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     __syncthreads();
     // ---- seeds
     if (a.seeds) {
-        for (int i = lane; i < m.n; i += WAVE) {
+        for (int i = lane; i < m.n; i += blockDim.x) {
             const int c = i % m.st, r = i / m.st;
             if ((m.fl[i] & F_IN) && a.seeds[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c]) m.fl[i] |= F_RM;
         }
         __syncthreads();
     } else {
-        for (int i = lane; i < m.n; i += WAVE) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
+        for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
         __syncthreads();
-        recon_any<R, L>(m, m.A, m.dq, Ts);  // g = h-maxima of Dq
-        for (int i = lane; i < m.n; i += WAVE) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
+        recon_any<R, L>(m, m.A, m.dq);  // g = h-maxima of Dq
+        for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
         __syncthreads();
         if constexpr (R > 0)
-            recon_any<R, L>(m, (int32_t *)m.B, m.A, Ts);   // recon of g-1 under g
+            recon_any<R, L>(m, (int32_t *)m.B, m.A);   // recon of g-1 under g
         else
             recon_scans<L, L>(m, m.B, m.A);
-        for (int i = lane; i < m.n; i += WAVE)
+        for (int i = lane; i < m.n; i += blockDim.x)
             if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
         __syncthreads();
     }
     if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
-        for (int i = lane; i < m.n; i += WAVE) {
+        for (int i = lane; i < m.n; i += blockDim.x) {
             if (!(m.fl[i] & F_IN)) continue;
             const int c = i % m.st, r = i / m.st;
             const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
@@ -455,7 +461,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     }
     crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
     int nroots = 0;
-    for (int i = lane; i < m.n; i += WAVE) nroots += (m.B[i] == (L)i);
+    for (int i = lane; i < m.n; i += blockDim.x) nroots += (m.B[i] == (L)i);
     int tot = 0;
     {
         if (lane == 0) *red = 0;
@@ -469,7 +475,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     if (tot <= 1) {
         // one seed (or none with external seeds): the whole component gets one
         // label, nothing is cut, and the relabelled component is the component
-        for (int i = lane; i < m.n; i += WAVE) {
+        for (int i = lane; i < m.n; i += blockDim.x) {
             if (!(m.fl[i] & F_IN)) continue;
             const int c = i % m.st, r = i / m.st;
             const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
@@ -481,12 +487,12 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         return;
     }
     // ---- lambda = recon of (Dq on seeds) under Dq
-    for (int i = lane; i < m.n; i += WAVE) m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
+    for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
     __syncthreads();
-    recon_any<R, L>(m, m.A, m.dq, Ts);
+    recon_any<R, L>(m, m.A, m.dq);
     // ---- flood, level by level from the highest lambda
     int lmax = NEGV, lmin = INT_MAX;
-    for (int i = lane; i < m.n; i += WAVE)
+    for (int i = lane; i < m.n; i += blockDim.x)
         if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) {
             lmax = max(lmax, m.A[i]);
             lmin = min(lmin, m.A[i]);
@@ -498,16 +504,16 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         const int range = lmax - lmin + 1;
         if (range <= HBINS) {
             // counting sort of the unlabelled pixels by decreasing lambda
-            for (int k = lane; k <= HBINS; k += WAVE) hist[k] = 0;
+            for (int k = lane; k <= HBINS; k += blockDim.x) hist[k] = 0;
             __syncthreads();
-            for (int i = lane; i < m.n; i += WAVE)
+            for (int i = lane; i < m.n; i += blockDim.x)
                 if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) atomicAdd(hist + 1 + (lmax - m.A[i]), 1);
             __syncthreads();
             if (lane == 0)
                 for (int k = 1; k <= HBINS; ++k) hist[k] += hist[k - 1];
             __syncthreads();
             // hist[k] = start of bin k; scatter with a moving cursor per bin
-            for (int i = lane; i < m.n; i += WAVE)
+            for (int i = lane; i < m.n; i += blockDim.x)
                 if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV) {
                     const int pos = atomicAdd(hist + (lmax - m.A[i]), 1);
                     list[pos] = i;
@@ -525,14 +531,14 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             for (int L0 = lmax; L0 != NEGV;) {
                 if (lane == 0) *red = 0;
                 __syncthreads();
-                for (int i = lane; i < m.n; i += WAVE)
+                for (int i = lane; i < m.n; i += blockDim.x)
                     if ((m.fl[i] & F_IN) && m.B[i] == -1 && m.A[i] == L0) list[atomicAdd(red, 1)] = i;
                 __syncthreads();
                 const int cnt = *red;
                 __syncthreads();
                 flood_level<L>(m, list, 0, cnt);
                 int nxt = NEGV;
-                for (int i = lane; i < m.n; i += WAVE)
+                for (int i = lane; i < m.n; i += blockDim.x)
                     if ((m.fl[i] & F_IN) && m.B[i] < 0 && m.A[i] != NEGV && m.A[i] < L0) nxt = max(nxt, m.A[i]);
                 L0 = wave_max(nxt, red);
             }
@@ -541,22 +547,22 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // ---- leftovers (external seeds only): their own components
     if (a.seeds) {
         bool left = false;
-        for (int i = lane; i < m.n; i += WAVE)
+        for (int i = lane; i < m.n; i += blockDim.x)
             if ((m.fl[i] & F_IN) && m.B[i] < 0) {
                 m.fl[i] |= F_M;
                 left = true;
             }
         if (wave_or(left)) {
             crop_ccl<L, int32_t>(m, F_M, m.A);
-            for (int i = lane; i < m.n; i += WAVE)
+            for (int i = lane; i < m.n; i += blockDim.x)
                 if (m.fl[i] & F_M) m.B[i] = m.A[i];
             __syncthreads();
         }
-        for (int i = lane; i < m.n; i += WAVE) m.fl[i] &= (uint8_t)~F_M;
+        for (int i = lane; i < m.n; i += blockDim.x) m.fl[i] &= (uint8_t)~F_M;
         __syncthreads();
     }
     // ---- cut: keep p iff no neighbour in the component has a smaller label
-    for (int i = lane; i < m.n; i += WAVE) {
+    for (int i = lane; i < m.n; i += blockDim.x) {
         if (!(m.fl[i] & F_IN)) continue;
         const int c = i % m.st, r = i / m.st;
         const L lab = m.B[i];
@@ -573,13 +579,13 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // ---- relabel the kept pixels, area of each piece, write out
     crop_ccl<L, int32_t>(m, F_M, m.A);
     int32_t *cnt = m.dq;
-    for (int i = lane; i < m.n; i += WAVE) cnt[i] = 0;
+    for (int i = lane; i < m.n; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
-    for (int i = lane; i < m.n; i += WAVE)
+    for (int i = lane; i < m.n; i += blockDim.x)
         if (m.fl[i] & F_M) atomicAdd(cnt + m.A[i], 1);
     __syncthreads();
     int kept = 0;
-    for (int i = lane; i < m.n; i += WAVE) {
+    for (int i = lane; i < m.n; i += blockDim.x) {
         if (!(m.fl[i] & F_IN)) continue;
         const int c = i % m.st, r = i / m.st;
         const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
@@ -612,6 +618,14 @@ __device__ __forceinline__ CropGeom crop_geom(const ObjArgs &a, int g) {
     q.ch = cy1 - q.cy0 + 1;
     q.st = q.cw | 1;
     q.n = q.st * q.ch;
+    return q;
+}
+
+// The register classes use the row stride R + 1 of the in-place register
+// reconstruction (the plane capacity is R x (R + 1)).
+__device__ __forceinline__ CropGeom with_stride(CropGeom q, int st) {
+    q.st = st;
+    q.n = st * q.ch;
     return q;
 }
 
@@ -695,7 +709,6 @@ __global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjL
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
-    __shared__ int Ts[2 * RS_ * (RS_ + 1)];
     const int nobj = *L.n_s;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int code = L.list_s[o];
@@ -706,15 +719,14 @@ __global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjL
             erase_object(a, g, q);
             continue;
         }
-        process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, q), &red, hist, Ts);
+        process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, with_stride(q, RS_ + 1)), &red, hist);
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_objects_m(const ObjArgs *args, ObjLists L) {
+__global__ __launch_bounds__(2 * WAVE) void k_objects_m(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
-    __shared__ int Ts[2 * RM_ * (RM_ + 1)];
     const int nobj = *L.n_m;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int code = L.list_m[o];
@@ -730,7 +742,7 @@ __global__ __launch_bounds__(WAVE) void k_objects_m(const ObjArgs *args, ObjList
             }
             continue;
         }
-        process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, q), &red, hist, Ts);
+        process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, with_stride(q, RM_ + 1)), &red, hist);
     }
 }
 
@@ -750,7 +762,7 @@ __global__ __launch_bounds__(WAVE) void k_objects_l(const ObjArgs *args, ObjList
             if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
             continue;
         }
-        process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist, nullptr);
+        process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist);
     }
 }
 
@@ -790,7 +802,7 @@ __global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, BigPa
         m.cx0 = q.cx0;
         m.cy0 = q.cy0;
         m.n = q.n;
-        process_object<0, int64_t>(a, g, m, &red, hist, nullptr);
+        process_object<0, int64_t>(a, g, m, &red, hist);
     }
 }
 
@@ -824,7 +836,7 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
         RT_HIP(hipStreamWaitEvent(par->side, par->fork, 0));
         t = par->side;
     }
-    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(WAVE), lds_m, s, args_dev, L);
+    hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(2 * WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, t, args_dev, L);
     RT_HIP(hipGetLastError());
