@@ -201,7 +201,15 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  * them, only speed does):
  *   "recon_levels"      0..8  threshold levels of the frame-connectivity lower
  *                             bound that starts ReconToNuclei (0 = start from
- *                             the frame marker alone); default 3
+ *                             the frame marker alone); default 2
+ *   "recon_level_mode"  0|1   choice of those levels from the Hq histogram:
+ *                             0: the values at which the share of pixels at
+ *                             or above falls below 0.75 .. 0.33 (evenly
+ *                             spaced); 1: consecutive values v0 - n + 2 ..
+ *                             v0 + 1, v0 the highest value with a share of at
+ *                             least recon_level_frac / 1000 at or above it
+ *                             (n = 1: v0); default 1
+ *   "recon_level_frac"  1..999 per mille for recon_level_mode 1; default 500
  *   "recon_round_batch" 1..64 propagation rounds launched between two reads of
  *                             the worklist counter; default 8
  *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;

@@ -283,9 +283,13 @@ int side_streams(rt_ctx *c, ObjStreams &par) {
     if (!c->side_stream) RT_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
     if (!c->fork_ev) RT_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
     if (!c->join_ev) RT_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    if (!c->side_stream2) RT_HIP(hipStreamCreateWithFlags(&c->side_stream2, hipStreamNonBlocking));
+    if (!c->join2_ev) RT_HIP(hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming));
     par.side = c->side_stream;
+    par.side2 = c->side_stream2;
     par.fork = c->fork_ev;
     par.join = c->join_ev;
+    par.join2 = c->join2_ev;
     return RT_OK;
 }
 
@@ -302,7 +306,9 @@ int enqueue_front(rt_ctx *c, const Plan &P, const StainParams &sp, hipStream_t s
     c->prof_launches[0] += 3;
     if (prof && (e = prof_mark(c, 1, s))) return e;
     if (P.nlev > 0) {
-        if ((e = launch_batch_levels(at<BatchAux>(c, P.o_aux), P.n, P.nlev, s))) return e;
+        if ((e = launch_batch_levels(at<BatchAux>(c, P.o_aux), P.n, P.nlev, c->knobs.recon_level_mode,
+                                     c->knobs.recon_level_frac, s)))
+            return e;
         if ((e = launch_ccl(at<CclArgs>(c, P.o_cl), P.n, P.ccl_total, c->n_cu, s, CclPred::Level, CclOut::LevelBound, P.nlev))) return e;
         c->prof_launches[1] += 4;
     } else {
@@ -570,7 +576,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     }
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
-                                c->knobs.objects_path, c->knobs.recon_mode,
+                                c->knobs.objects_path, c->knobs.recon_mode, c->knobs.recon_level_mode,
+                                c->knobs.recon_level_frac,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -692,6 +699,8 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+    if (c->side_stream2) (void)hipStreamDestroy(c->side_stream2);
+    if (c->join2_ev) (void)hipEventDestroy(c->join2_ev);
     for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->round_events) (void)hipEventDestroy(ev);
     if (c->prof_visits) (void)hipFree(c->prof_visits);
@@ -1078,6 +1087,12 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     if (n == "recon_levels") {
         CHECK(value >= 0 && value <= 8, "rt_set_knob: recon_levels must be 0..8");
         c->knobs.recon_levels = value;
+    } else if (n == "recon_level_mode") {
+        CHECK(value == 0 || value == 1, "rt_set_knob: recon_level_mode must be 0 or 1");
+        c->knobs.recon_level_mode = value;
+    } else if (n == "recon_level_frac") {
+        CHECK(value >= 1 && value <= 999, "rt_set_knob: recon_level_frac must be 1..999");
+        c->knobs.recon_level_frac = value;
     } else if (n == "recon_round_batch") {
         CHECK(value >= 1 && value <= 64, "rt_set_knob: recon_round_batch must be 1..64");
         c->knobs.recon_round_batch = value;
@@ -1108,6 +1123,10 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
     std::string n(name);
     if (n == "recon_levels")
         *value = c->knobs.recon_levels;
+    else if (n == "recon_level_mode")
+        *value = c->knobs.recon_level_mode;
+    else if (n == "recon_level_frac")
+        *value = c->knobs.recon_level_frac;
     else if (n == "recon_round_batch")
         *value = c->knobs.recon_round_batch;
     else if (n == "recon_max_sweeps")

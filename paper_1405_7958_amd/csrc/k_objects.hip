@@ -733,13 +733,8 @@ __global__ __launch_bounds__(2 * WAVE) void k_objects_m(const ObjArgs *args, Obj
         const ObjArgs a = args[code >> 25];
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
-        if (q.cw > RM_ || q.ch > RM_) {
-            if (threadIdx.x == 0) {
-                if (q.n <= CAP_L)
-                    L.list_l[atomicAdd(L.n_l, 1)] = code;
-                else
-                    L.big[atomicAdd(L.n_big, 1)] = code;
-            }
+        if (q.cw > RM_ || q.ch > RM_) {   // routed here only when it fits; the global class takes any crop
+            if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
             continue;
         }
         process_object<RM_, int32_t>(a, g, lds_crop<CAP_M>(smem, with_stride(q, RM_ + 1)), &red, hist);
@@ -747,8 +742,9 @@ __global__ __launch_bounds__(2 * WAVE) void k_objects_m(const ObjArgs *args, Obj
 }
 
 // large class: crops up to CAP_L pixels in LDS, scans without the register
-// path (one workgroup per CU for LDS)
-__global__ __launch_bounds__(WAVE) void k_objects_l(const ObjArgs *args, ObjLists L) {
+// path (one workgroup per CU for LDS); four waves per component, so a row
+// of the directional scans is one pass
+__global__ __launch_bounds__(4 * WAVE) void k_objects_l(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
@@ -826,25 +822,29 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
     }
     hipLaunchKernelGGL(k_objects_classify, dim3(n_cu * 4), dim3(256), 0, s, args_dev, L);
     RT_HIP(hipGetLastError());
-    // The small class runs on a side stream beside the others when one is
-    // given.  The medium class (the longest per component) is enqueued first
-    // on the caller's stream, so it reaches the compute units before the
-    // many small components fill them.
-    hipStream_t t = s;
-    if (par && par->side) {
+    // With side streams the three LDS classes run side by side: the medium
+    // class on the caller's stream, the small class and the large class on
+    // one side stream each (a large component is the longest single piece
+    // of work, the many small ones fill the compute units around it).
+    hipStream_t t = s, u = s;
+    if (par && par->side && par->side2) {
         RT_HIP(hipEventRecord(par->fork, s));
         RT_HIP(hipStreamWaitEvent(par->side, par->fork, 0));
+        RT_HIP(hipStreamWaitEvent(par->side2, par->fork, 0));
         t = par->side;
+        u = par->side2;
     }
+    hipLaunchKernelGGL(k_objects_l, dim3(n_cu), dim3(4 * WAVE), lds_l, u, args_dev, L);
+    RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(2 * WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, t, args_dev, L);
     RT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_objects_l, dim3(n_cu), dim3(WAVE), lds_l, s, args_dev, L);
-    RT_HIP(hipGetLastError());
     if (t != s) {
         RT_HIP(hipEventRecord(par->join, t));
         RT_HIP(hipStreamWaitEvent(s, par->join, 0));
+        RT_HIP(hipEventRecord(par->join2, u));
+        RT_HIP(hipStreamWaitEvent(s, par->join2, 0));
     }
     if (before_big) RT_HIP(hipEventRecord(before_big, s));
     BigPass mid{L.big, L.n_big, L.huge, L.n_huge, (char *)L.mid_scratch, L.mid_slice_bytes, MID_MAX_PX};

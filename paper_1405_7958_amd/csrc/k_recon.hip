@@ -460,7 +460,31 @@ __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, i
     if (threadIdx.x == 0) *a.kept = 0;
 }
 
-__global__ void k_batch_levels(const BatchAux *aux, int n_levels) {
+// Band selection: v0 = the highest value with at least frac of the pixels at
+// or above it, and the levels v0 - n + 2 .. v0 + 1 (n = 1: v0 alone).  The
+// reconstruction of the frame marker under Hq is the largest value at which
+// a pixel is still joined to the frame, so wherever the upper level sets of a
+// noisy background stop spanning the tile, the result has one plateau that
+// covers most of the background at the last spanning level; the level set
+// at that value then holds about half of the pixels.  Levels at and just
+// above that value make the bound exact on the plateau and on the thin
+// clusters that stay joined to the frame one step higher, which otherwise
+// take the longest propagation.
+__device__ void select_levels_band(const uint32_t *hist, int n_levels, int frac_permille, int32_t *levels) {
+    double total = 0;
+    for (int v = 0; v < 256; ++v) total += hist[v];
+    const double need = total * frac_permille / 1000.0;
+    double above = total;   // pixels with value >= v
+    int v0 = 0;
+    for (int v = 0; v < 256; ++v) {
+        if (above >= need) v0 = v;
+        above -= hist[v];
+    }
+    const int top = n_levels == 1 ? v0 : min(v0 + 1, 255);
+    for (int k = 0; k < n_levels; ++k) levels[k] = max(1, top - (n_levels - 1 - k));
+}
+
+__global__ void k_batch_levels(const BatchAux *aux, int n_levels, int mode, int frac_permille) {
     __shared__ uint32_t H[256];
     const BatchAux a = aux[blockIdx.x];
     for (int v = threadIdx.x; v < 256; v += blockDim.x) {
@@ -469,7 +493,12 @@ __global__ void k_batch_levels(const BatchAux *aux, int n_levels) {
         H[v] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) select_levels(H, n_levels, a.levels);
+    if (threadIdx.x == 0) {
+        if (mode == 1)
+            select_levels_band(H, n_levels, frac_permille, a.levels);
+        else
+            select_levels(H, n_levels, a.levels);
+    }
 }
 
 __global__ void k_batch_end(const BatchAux *aux, int n) {
@@ -510,8 +539,8 @@ int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ct
     hipLaunchKernelGGL(k_batch_begin, dim3(n + 1), dim3(256), 0, s, aux, n, shared_ctr, n_ctr);
     return hip_fail(hipGetLastError(), "k_batch_begin");
 }
-int launch_batch_levels(const BatchAux *aux, int n, int n_levels, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_levels, dim3(n), dim3(64), 0, s, aux, n_levels);
+int launch_batch_levels(const BatchAux *aux, int n, int n_levels, int mode, int frac_permille, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_levels, dim3(n), dim3(64), 0, s, aux, n_levels, mode, frac_permille);
     return hip_fail(hipGetLastError(), "k_batch_levels");
 }
 int launch_batch_frame_marker(const BatchAux *aux, int n, hipStream_t s) {

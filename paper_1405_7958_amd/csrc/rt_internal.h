@@ -51,7 +51,9 @@ struct Arena {
 };
 
 struct Knobs {
-    int recon_levels = 3;        // threshold levels of the connectivity lower bound
+    int recon_levels = 2;        // threshold levels of the connectivity lower bound
+    int recon_level_mode = 1;    // 0: Hq quantiles 0.75..0.33; 1: band of consecutive values at recon_level_frac
+    int recon_level_frac = 500;  // per mille of pixels with Hq >= the band's second-highest level
     int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
     int objects_path = 0;        // per-object class routing (ObjLists::path)
@@ -86,6 +88,8 @@ struct rt_ctx_impl {
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
     hipStream_t side_stream = nullptr;     // per-object classes beside the small class
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipStream_t side_stream2 = nullptr;    // the large LDS class beside the other two
+    hipEvent_t join2_ev = nullptr;
     std::vector<GraphPair> graphs;         // small cache of captured batches
     uint64_t graph_clock = 0;
     int64_t graph_replays = 0, graph_captures = 0;
@@ -230,7 +234,7 @@ struct BatchAux {
     int64_t out_pitch;
 };
 int launch_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr, hipStream_t s);
-int launch_batch_levels(const BatchAux *aux, int n, int n_levels, hipStream_t s);
+int launch_batch_levels(const BatchAux *aux, int n, int n_levels, int mode, int frac_permille, hipStream_t s);
 int launch_batch_frame_marker(const BatchAux *aux, int n, hipStream_t s);
 int launch_batch_end(const BatchAux *aux, int n, hipStream_t s);
 int launch_batch_zero_maps(const BatchAux *aux, int n, hipStream_t s);
@@ -277,8 +281,8 @@ constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
 // Optional side stream for the small class, joined back into the caller's
 // stream with the two events before the global-memory classes.
 struct ObjStreams {
-    hipStream_t side;
-    hipEvent_t fork, join;
+    hipStream_t side, side2;
+    hipEvent_t fork, join, join2;
 };
 // `before_big` (nullable) is recorded on `s` at the end of the LDS classes.
 int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hipStream_t s,

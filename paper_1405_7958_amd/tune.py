@@ -27,7 +27,9 @@ from . import rtseg
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 SPACE = {
-    "recon_levels": [0, 1, 2, 3, 4, 6, 8],
+    "recon_level_mode": [1, 0],
+    "recon_level_frac": [500, 450, 550, 400, 600],
+    "recon_levels": [2, 1, 3, 4, 6, 8, 0],
     "recon_round_batch": [4, 8, 16, 32],
     "recon_max_sweeps": [16, 32, 64, 128],
     "objects_path": [0, 1, 2],

@@ -338,6 +338,28 @@ def test_segment_4k(rt, oracle):
     assert n > 5000
 
 
+@pytest.mark.parametrize("knobs", [dict(recon_levels=3, recon_level_mode=0), dict(recon_levels=2, recon_level_mode=1),
+                                   dict(recon_levels=8, recon_level_mode=1, recon_level_frac=300),
+                                   dict(recon_levels=1, recon_level_mode=1, recon_level_frac=950),
+                                   dict(recon_levels=5, recon_level_mode=1, recon_level_frac=1),
+                                   dict(recon_levels=0)])
+def test_segment_level_choices(rt, oracle, knobs):
+    """The threshold levels of the reconstruction's lower bound change only
+    speed: every choice gives the oracle's result."""
+    d = dev()
+    ctx = rt.Context(0)
+    for k, v in knobs.items():
+        rt.rt_set_knob(k, v, ctx=ctx)
+    for spec in (synth.spec_small(5), synth.spec_stream(2)):
+        rgb, _, _ = synth.make_tile(spec)
+        say("segment level choice", knobs, rgb.shape)
+        mask, lab, n, hq = rt.rt_segment_tile(to_dev(rgb, d), want_hq=True, ctx=ctx)
+        emask, elab, en = oracle.segment_from_hq(to_np(hq))
+        assert_equal(to_np(mask), emask, f"{knobs} mask")
+        assert_equal(to_np(lab), elab, f"{knobs} labels")
+        assert int(to_np(n)[0]) == en
+
+
 def test_segment_repeatable(rt):
     d = dev()
     rgb, _, _ = synth.make_tile(synth.spec_small(3))
