@@ -245,12 +245,13 @@ __device__ __forceinline__ bool reg_scan(int (&v)[R], const int (&mk)[R], bool f
     return ch;
 }
 
-// Within one wave: LDS operations of a wavefront complete in order, so
-// ordering the compiler's memory operations suffices.
+// Within one wave: the hardware performs a wavefront's LDS operations in
+// order, so it suffices that every earlier LDS access has completed and that
+// the compiler moves no memory access across this point (a lane reads what
+// other lanes of the wave wrote, which per-thread alias analysis cannot see).
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // In place on the crop plane V, whose row stride is R + 1: the plane is the
@@ -372,6 +373,20 @@ __device__ void flood_level(const Crop<L> &m, const int32_t *list, int b, int e)
     __syncthreads();
 }
 
+// number of roots (B[i] == i) of a crop CCL
+template <typename L>
+__device__ int count_roots(const Crop<L> &m, int *red) {
+    int nroots = 0;
+    for (int i = threadIdx.x; i < m.n; i += blockDim.x) nroots += (m.B[i] == (L)i);
+    if (threadIdx.x == 0) *red = 0;
+    __syncthreads();
+    if (nroots) atomicAdd(red, nroots);
+    __syncthreads();
+    const int tot = *red;
+    __syncthreads();
+    return tot;
+}
+
 // ---- the whole per-component stage ---------------------------------------------
 template <int R, typename L>
 __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist) {
@@ -429,47 +444,61 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         m.dq[i] = isqrt_exact(4 * best);
     }
     __syncthreads();
-    // ---- seeds
-    if (a.seeds) {
-        for (int i = lane; i < m.n; i += blockDim.x) {
-            const int c = i % m.st, r = i / m.st;
-            if ((m.fl[i] & F_IN) && a.seeds[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c]) m.fl[i] |= F_RM;
-        }
-        __syncthreads();
-    } else {
-        for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
-        __syncthreads();
-        recon_any<R, L>(m, m.A, m.dq);  // g = h-maxima of Dq
-        for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
-        __syncthreads();
-        if constexpr (R > 0)
-            recon_any<R, L>(m, (int32_t *)m.B, m.A);   // recon of g-1 under g
-        else
-            recon_scans<L, L>(m, m.B, m.A);
-        for (int i = lane; i < m.n; i += blockDim.x)
-            if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
-        __syncthreads();
-    }
-    if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
-        for (int i = lane; i < m.n; i += blockDim.x) {
-            if (!(m.fl[i] & F_IN)) continue;
-            const int c = i % m.st, r = i / m.st;
-            const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
-            a.fg_out[o] = 1;
-            a.seeds_out[o] = (m.fl[i] & F_RM) ? 1 : 0;
+    // ---- one regional maximum of Dq means one seed (register classes, when
+    // no seed map is wanted): each regional maximum of the h-maxima transform
+    // g = recon(Dq - h under Dq) contains a regional maximum of Dq (a plateau
+    // of g at value v holds a point with Dq - h = v, and the component of
+    // {Dq >= v + h} through it stays inside the plateau, so its top is a
+    // regional maximum of Dq), so g has at most as many.  Regional maxima of
+    // Dq: Dq - recon(Dq - 1 under Dq) > 0.
+    int tot = 2;
+    if constexpr (R == RS_) {
+        if (!a.seeds && !a.fg_out) {
+            for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - 1 : NEGV;
+            __syncthreads();
+            recon_any<R, L>(m, m.A, m.dq);
+            for (int i = lane; i < m.n; i += blockDim.x)
+                if ((m.fl[i] & F_IN) && m.dq[i] - m.A[i] > 0) m.fl[i] |= F_M;
+            __syncthreads();
+            crop_ccl<L, L>(m, F_M, m.B);
+            tot = count_roots(m, red);
+            for (int i = lane; i < m.n; i += blockDim.x) m.fl[i] &= (uint8_t)~F_M;
+            __syncthreads();
         }
     }
-    crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
-    int nroots = 0;
-    for (int i = lane; i < m.n; i += blockDim.x) nroots += (m.B[i] == (L)i);
-    int tot = 0;
-    {
-        if (lane == 0) *red = 0;
-        __syncthreads();
-        if (nroots) atomicAdd(red, nroots);
-        __syncthreads();
-        tot = *red;
-        __syncthreads();
+    if (tot > 1) {
+        // ---- seeds
+        if (a.seeds) {
+            for (int i = lane; i < m.n; i += blockDim.x) {
+                const int c = i % m.st, r = i / m.st;
+                if ((m.fl[i] & F_IN) && a.seeds[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c]) m.fl[i] |= F_RM;
+            }
+            __syncthreads();
+        } else {
+            for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
+            __syncthreads();
+            recon_any<R, L>(m, m.A, m.dq);  // g = h-maxima of Dq
+            for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
+            __syncthreads();
+            if constexpr (R > 0)
+                recon_any<R, L>(m, (int32_t *)m.B, m.A);   // recon of g-1 under g
+            else
+                recon_scans<L, L>(m, m.B, m.A);
+            for (int i = lane; i < m.n; i += blockDim.x)
+                if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
+            __syncthreads();
+        }
+        if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
+            for (int i = lane; i < m.n; i += blockDim.x) {
+                if (!(m.fl[i] & F_IN)) continue;
+                const int c = i % m.st, r = i / m.st;
+                const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+                a.fg_out[o] = 1;
+                a.seeds_out[o] = (m.fl[i] & F_RM) ? 1 : 0;
+            }
+        }
+        crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
+        tot = count_roots(m, red);
     }
     const bool area_ok = area >= a.min_area && (a.max_area < 0 || area <= a.max_area);
     if (tot <= 1) {
@@ -834,7 +863,7 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
         t = par->side;
         u = par->side2;
     }
-    hipLaunchKernelGGL(k_objects_l, dim3(n_cu), dim3(4 * WAVE), lds_l, u, args_dev, L);
+    hipLaunchKernelGGL(k_objects_l, dim3(std::max(1, n_cu / 4)), dim3(4 * WAVE), lds_l, u, args_dev, L);
     RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(2 * WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
