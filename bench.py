@@ -5,10 +5,13 @@ nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20,
 seed 0), input resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-batch] [--no-surrogate] [--no-tune] [--copy-calibration MB]
+                  [--no-batch] [--no-surrogate] [--no-tune] [--knobs K=V,...]
+                  [--copy-calibration MB]
 
 The launch knobs of the 4096 x 4096 tile are picked first by the autotuner
-(graph replay excluded, so that stage timing stays available).
+(graph replay excluded, so that stage timing stays available), unless --knobs
+gives them (profiler runs pass the set a tuned run reported, so that no
+tuning trial enters the kernel statistics).
 
 Roofline: the dominant kernel is the reconstruction round kernel (most of the
 GPU time of a tile).  After the timed steps, the same number of steps runs
@@ -176,6 +179,8 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default knobs for the 4096x4096 tile")
+    ap.add_argument("--knobs", default="", metavar="K=V,...",
+                    help="knobs for the 4096x4096 tile instead of autotuning (e.g. the set a tuned run reported)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1405_7958_amd", "weights", "unet_surrogate.rtunet"))
     ap.add_argument("--train-crops", type=int, default=512)
     ap.add_argument("--train-epochs", type=float, default=2.0)
@@ -215,7 +220,14 @@ def main():
     params = rtseg.default_params()
 
     knobs = None
-    if not args.no_tune:
+    if args.knobs:
+        knobs = {}
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            rtseg.rt_set_knob(k.strip(), int(v), ctx=ctx)
+            knobs[k.strip()] = int(v)
+        log(f"knobs for the 4096x4096 tile: {knobs}")
+    elif not args.no_tune:
         from paper_1405_7958_amd import tune
         res = tune.autotune([rgb], ctx=ctx, reps=3, cache=None, allow_graph=False)
         knobs = res["knobs"]
@@ -264,11 +276,16 @@ def main():
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9 if r_launches else 0.0
     log(f"recon round kernel: {r_launches} launches, {ms_launch * 1e3:.1f} us/launch, "
         f"{r_visits / max(1, r_launches):.0f} tile visits/launch, {achieved:.1f} GB/s")
+    # counter traffic of the round kernel, measured for one knob set: it holds
+    # for this run when the knobs that change a launch's work agree
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            traffic = tj.get("bytes_per_launch")
+            used = knobs or {k: rtseg.rt_get_knob(k, ctx=ctx) for k in rtseg.KNOBS}
+            same = all(int(used.get(k, -1)) == int(v) for k, v in tj.get("knobs", {}).items()
+                       if k in ("recon_levels", "recon_level_mode", "recon_level_frac", "recon_round_batch"))
+            traffic = tj.get("bytes_per_launch") if same and tj.get("knobs") else None
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
