@@ -252,14 +252,39 @@ __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*T
     mr.clear();
     const int gx = x0 - 1 + lane;
     const bool col_inner = lane >= 1 && lane <= 62;
+    if (sizeof(T) == 1 && a.domain == nullptr) {
+        // every load first (clamped addresses, no branch between them), so
+        // that they are all in flight together; then the out-of-image values
+        // become NEG
+        const bool col_ok = gx >= 0 && gx < a.w;
+        const int gxc = min(max(gx, 0), a.w - 1);
+        T rv[64], mv[64];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        const int gy = y0 - 1 + j;
-        r[j] = gval<T>(a, rr, gx, gy);
-        // ring pixels are read-only: they carry mask NEG
-        const int mv = (col_inner && j >= 1 && j <= 62) ? gval<T>(a, mask, gx, gy) : NEG;
-        mc.set(j, mv);
-        Ts[j][lane] = mv;
+        for (int j = 0; j < 64; ++j) {
+            const int64_t o = (int64_t)min(max(y0 - 1 + j, 0), a.h - 1) * a.pitch + gxc;
+            rv[j] = rr[o];
+            mv[j] = mask[o];
+        }
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            const int gy = y0 - 1 + j;
+            const bool ok = col_ok && gy >= 0 && gy < a.h;
+            r[j] = ok ? (int)rv[j] : NEG;
+            // ring pixels are read-only: they carry mask NEG
+            const int m = (ok && col_inner && j >= 1 && j <= 62) ? (int)mv[j] : NEG;
+            mc.set(j, m);
+            Ts[j][lane] = m;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            const int gy = y0 - 1 + j;
+            r[j] = gval<T>(a, rr, gx, gy);
+            // ring pixels are read-only: they carry mask NEG
+            const int mv = (col_inner && j >= 1 && j <= 62) ? gval<T>(a, mask, gx, gy) : NEG;
+            mc.set(j, mv);
+            Ts[j][lane] = mv;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -377,26 +402,29 @@ __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*T
     const bool cL = row_inner && Ts[lane][1] != oL, cR = row_inner && Ts[lane][62] != oR;
     const uint64_t mT = __ballot(cT), mB = __ballot(cB), mL = __ballot(cL), mR = __ballot(cR);
     if constexpr (QUEUE) __threadfence();   // release the tile's writes before announcing them
-    if (lane == 0) {
-        int nb[9];
-        int nn = 0;
-        auto add = [&](int dx, int dy) {
-            int nx = tx + dx, ny = ty + dy;
-            if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = a.unit0 + ny * a.ntx + nx;
-        };
-        if (mT) add(0, -1);
-        if (mB) add(0, 1);
-        if (mL) add(-1, 0);
-        if (mR) add(1, 0);
-        if (CONN == 8) {
-            if ((mT >> 1) & 1ull) add(-1, -1);   // interior corner (1, 1)
-            if ((mT >> 62) & 1ull) add(1, -1);   // (62, 1)
-            if ((mB >> 1) & 1ull) add(-1, 1);    // (1, 62)
-            if ((mB >> 62) & 1ull) add(1, 1);    // (62, 62)
-        }
-        if (!converged) nb[nn++] = gtile;  // sweep budget exhausted: continue later
-        push(nb, nn);
+    // the list is the same in every lane; lane k pushes entry k
+    int nb[9];
+    int nn = 0;
+    auto add = [&](int dx, int dy) {
+        int nx = tx + dx, ny = ty + dy;
+        if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = a.unit0 + ny * a.ntx + nx;
+    };
+    if (mT) add(0, -1);
+    if (mB) add(0, 1);
+    if (mL) add(-1, 0);
+    if (mR) add(1, 0);
+    if (CONN == 8) {
+        if ((mT >> 1) & 1ull) add(-1, -1);   // interior corner (1, 1)
+        if ((mT >> 62) & 1ull) add(1, -1);   // (62, 1)
+        if ((mB >> 1) & 1ull) add(-1, 1);    // (1, 62)
+        if ((mB >> 62) & 1ull) add(1, 1);    // (62, 62)
     }
+    if (!converged) nb[nn++] = gtile;  // sweep budget exhausted: continue later
+    int mine = -1;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (k == lane && k < nn) mine = nb[k];
+    if (lane < nn) push(&mine, 1);
 }
 
 // R0 = min(marker, mask) (out may alias marker)
