@@ -258,12 +258,17 @@ __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*T
         // become NEG
         const bool col_ok = gx >= 0 && gx < a.w;
         const int gxc = min(max(gx, 0), a.w - 1);
+        // the images are in global memory: global loads from a uniform base
+        // and a 32-bit offset instead of generic ones with 64-bit addresses
+        typedef const __attribute__((address_space(1))) T *gptr;
+        const gptr grr = (gptr)rr, gmask = (gptr)mask;
         T rv[64], mv[64];
 #pragma unroll
         for (int j = 0; j < 64; ++j) {
-            const int64_t o = (int64_t)min(max(y0 - 1 + j, 0), a.h - 1) * a.pitch + gxc;
-            rv[j] = rr[o];
-            mv[j] = mask[o];
+            // uniform row start, per-lane 32-bit column
+            const int64_t row = (int64_t)min(max(y0 - 1 + j, 0), a.h - 1) * a.pitch;
+            rv[j] = (grr + row)[gxc];
+            mv[j] = (gmask + row)[gxc];
         }
 #pragma unroll
         for (int j = 0; j < 64; ++j) {
