@@ -124,9 +124,15 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
     for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
         const int gtile = ra.first ? slot : ra.list_in[slot];
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
-        recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, Ts, [&](const int *nb, int nn) {
-            for (int k = 0; k < nn; ++k)
-                if (atomicExch(ra.stamp + nb[k], ra.epoch) != ra.epoch) ra.list_out[atomicAdd(cnt_out, 1)] = nb[k];
+        // every lane calls push; one counter update per wave for its new entries
+        recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, Ts, [&](int item, bool valid) {
+            const bool fresh = valid && atomicExch(ra.stamp + item, ra.epoch) != ra.epoch;
+            const uint64_t m = __ballot(fresh);
+            if (!m) return;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(cnt_out, __popcll(m));
+            base = __shfl(base, 0, 64);
+            if (fresh) ra.list_out[base + __popcll(m & ((1ull << lane) - 1))] = item;
         });
         __syncthreads();
     }
@@ -202,14 +208,12 @@ __global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
             if (q.visits) atomicAdd(q.visits, 1ull);
         }
         const ReconImg a = q.imgs[recon_img_of(q.imgs, q.n, item)];
-        recon_tile<T, CONN, true>(a, item, q.max_sweeps, Ts, [&](const int *nb, int nn) {
-            for (int k = 0; k < nn; ++k) {
-                if (atomicExch(q.inq + nb[k], 1u) == 0u) {
-                    atomicAdd(pending, 1u);
-                    const unsigned t = atomicAdd(tail, 1u);
-                    __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb[k],
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+        recon_tile<T, CONN, true>(a, item, q.max_sweeps, Ts, [&](int nb, bool valid) {
+            if (valid && atomicExch(q.inq + nb, 1u) == 0u) {
+                atomicAdd(pending, 1u);
+                const unsigned t = atomicAdd(tail, 1u);
+                __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         });
         __syncthreads();
@@ -429,7 +433,7 @@ __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*T
 #pragma unroll
     for (int k = 0; k < 9; ++k)
         if (k == lane && k < nn) mine = nb[k];
-    if (lane < nn) push(&mine, 1);
+    push(mine, lane < nn);
 }
 
 // R0 = min(marker, mask) (out may alias marker)
