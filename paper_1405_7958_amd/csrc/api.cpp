@@ -335,10 +335,13 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool captur
                 at<int32_t>(c, P.o_l), ctr + 9, at<int32_t>(c, P.o_big), ctr + 2, at<int32_t>(c, P.o_huge), ctr + 8,
                 at<void>(c, P.o_mid), P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
     OL.path = c->knobs.objects_path;
+    // side streams also under capture: a stream that waits on an event
+    // recorded in the capturing stream joins the capture, so the graph keeps
+    // the three per-object classes as parallel branches
     ObjStreams par{};
-    if (!capturing && (e = side_streams(c, par))) return e;
-    if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr,
-                            capturing ? nullptr : &par)))
+    (void)capturing;
+    if ((e = side_streams(c, par))) return e;
+    if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr, &par)))
         return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     c->prof_launches[5] += 2;

@@ -330,6 +330,27 @@ def test_segment_dense_and_low_contrast(rt, oracle):
         _check_tile(rt, oracle, rgb, d, f"stream tile {i} {spec.kind}")
 
 
+def test_segment_many_components_per_tile(rt, oracle):
+    """About 320 components per 64 x 64 tile (kept 5 x 5 squares beside
+    1-px dots that the first area filter erases): more than the per-tile
+    statistics table holds, so part of the statistics and registrations take
+    the direct path."""
+    d = dev()
+    rgb = np.empty((256, 256, 3), np.uint8)
+    rgb[...] = (230, 180, 200)
+    nuc = np.array([120, 70, 150], np.uint8)
+    for cy in range(0, 256, 8):
+        for cx in range(0, 256, 8):
+            if ((cy // 8) + (cx // 8)) % 2 == 0:
+                rgb[cy + 1:cy + 6, cx + 1:cx + 6] = nuc
+            else:
+                for dy in (1, 3, 5):
+                    for dx in (1, 3, 5):
+                        rgb[cy + dy, cx + dx] = nuc
+    n = _check_tile(rt, oracle, rgb, d, "many components")
+    assert n > 400
+
+
 def test_segment_4k(rt, oracle):
     """The 4096 x 4096 workload, full-size, whole-image comparison."""
     d = dev()
