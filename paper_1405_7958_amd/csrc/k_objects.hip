@@ -306,13 +306,94 @@ __device__ __forceinline__ void reg_recon(const Crop<L> &m, int32_t *V, int32_t 
     __syncthreads();
 }
 
-// V <- recon of V under M: registers when the crop fits R x R, else LDS scans
+// ---- windowed register reconstruction (crops larger than 64 x 64 in LDS) ----
+// The crop is covered by 64 x 64 windows at stride 62, so that every pair of
+// 8-neighbours lies inside some window.  Each wave takes windows in turn,
+// loads one into registers (lane = column), sweeps it to its local fixpoint
+// with the scans of reg_recon (through its own 16-bit transpose buffer), and
+// raises the plane with an LDS atomic maximum.  Every step only raises values
+// towards the result, so windows may overlap and run side by side; passes
+// repeat until one changes nothing, and then every neighbour pair satisfies
+// the reconstruction's fixpoint condition.
+constexpr int WIN = 64, WSTEP = 62, WTS = 65;
+constexpr int16_t WNEG = INT16_MIN;   // NEGV in the 16-bit buffers (values here stay far inside int16)
+
+__device__ __forceinline__ int16_t to16(int v) { return v == NEGV ? WNEG : (int16_t)v; }
+__device__ __forceinline__ int from16(int16_t v) { return v == WNEG ? NEGV : (int)v; }
+
+template <typename L>
+__device__ void win_recon(const Crop<L> &m, int32_t *V, int32_t *M, int16_t *tw, int *flag) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wave = tid / WAVE, nwaves = nt / WAVE, lane = tid & (WAVE - 1);
+    for (int i = tid; i < m.n; i += nt)
+        if (!(m.fl[i] & F_IN)) M[i] = NEGV;   // no later step reads M outside the component
+    const int nwx = max(1, (m.cw - 2 + WSTEP - 1) / WSTEP), nwy = max(1, (m.ch - 2 + WSTEP - 1) / WSTEP);
+    const int nwin = nwx * nwy;
+    int16_t *T = tw + wave * WIN * WTS;
+    const bool first = lane == 0, last = lane == WIN - 1;
+    for (;;) {
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        for (int wi = wave; wi < nwin; wi += nwaves) {
+            const int wx = (wi % nwx) * WSTEP, wy = (wi / nwx) * WSTEP;
+            const int x = wx + lane;
+            int v[WIN], mc[WIN], mr[WIN];
+#pragma unroll
+            for (int j = 0; j < WIN; ++j) {
+                const int y = wy + j;
+                const bool in = x < m.cw && y < m.ch;
+                v[j] = in ? V[y * m.st + x] : NEGV;
+                mc[j] = in ? M[y * m.st + x] : NEGV;
+                const int yr = wy + lane, xr = wx + j;   // transposed: lane = row
+                mr[j] = (yr < m.ch && xr < m.cw) ? M[yr * m.st + xr] : NEGV;
+            }
+            bool any = false;
+            for (;;) {
+                bool ch = reg_scan<WIN>(v, mc, first, last);
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) T[j * WTS + lane] = to16(v[j]);
+                wave_sync();
+#pragma unroll
+                for (int i = 0; i < WIN; ++i) v[i] = from16(T[lane * WTS + i]);
+                wave_sync();
+                ch |= reg_scan<WIN>(v, mr, first, last);
+#pragma unroll
+                for (int i = 0; i < WIN; ++i) T[lane * WTS + i] = to16(v[i]);
+                wave_sync();
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) v[j] = from16(T[j * WTS + lane]);
+                wave_sync();
+                if (!__any(ch)) break;
+                any = true;
+            }
+            if (any) {
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) {
+                    const int y = wy + j;
+                    if (x < m.cw && y < m.ch && v[j] != NEGV) atomicMax(V + y * m.st + x, v[j]);
+                }
+                if (lane == 0) atomicOr(flag, 1);
+            }
+        }
+        __syncthreads();
+        const int again = *flag;
+        __syncthreads();
+        if (!again) break;
+    }
+}
+
+// V <- recon of V under M: registers when the crop fits R x R; windows of
+// registers for the larger LDS crops (tw given); else LDS scans
 template <int R, typename L>
-__device__ __forceinline__ void recon_any(const Crop<L> &m, int32_t *V, int32_t *M) {
+__device__ __forceinline__ void recon_any(const Crop<L> &m, int32_t *V, int32_t *M, int16_t *tw = nullptr,
+                                          int *flag = nullptr) {
     if constexpr (R > 0) {
         reg_recon<R, L>(m, V, M);
     } else {
-        recon_scans<L, int32_t>(m, V, M);
+        if (tw)
+            win_recon<L>(m, V, M, tw, flag);
+        else
+            recon_scans<L, int32_t>(m, V, M);
     }
 }
 
@@ -389,7 +470,7 @@ __device__ int count_roots(const Crop<L> &m, int *red) {
 
 // ---- the whole per-component stage ---------------------------------------------
 template <int R, typename L>
-__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist) {
+__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int16_t *tw = nullptr) {
     const int lane = threadIdx.x;
     const int area = a.st_area[g];
     // ---- load the component
@@ -477,11 +558,11 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         } else {
             for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
             __syncthreads();
-            recon_any<R, L>(m, m.A, m.dq);  // g = h-maxima of Dq
+            recon_any<R, L>(m, m.A, m.dq, tw, red);  // g = h-maxima of Dq
             for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
             __syncthreads();
-            if constexpr (R > 0)
-                recon_any<R, L>(m, (int32_t *)m.B, m.A);   // recon of g-1 under g
+            if constexpr (R > 0 || sizeof(L) == 4)
+                recon_any<R, L>(m, (int32_t *)m.B, m.A, tw, red);   // recon of g-1 under g
             else
                 recon_scans<L, L>(m, m.B, m.A);
             for (int i = lane; i < m.n; i += blockDim.x)
@@ -518,7 +599,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // ---- lambda = recon of (Dq on seeds) under Dq
     for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = ((m.fl[i] & F_IN) && (m.fl[i] & F_RM)) ? m.dq[i] : NEGV;
     __syncthreads();
-    recon_any<R, L>(m, m.A, m.dq);
+    recon_any<R, L>(m, m.A, m.dq, tw, red);
     // ---- flood, level by level from the highest lambda
     int lmax = NEGV, lmin = INT_MAX;
     for (int i = lane; i < m.n; i += blockDim.x)
@@ -787,7 +868,8 @@ __global__ __launch_bounds__(4 * WAVE) void k_objects_l(const ObjArgs *args, Obj
             if (threadIdx.x == 0) L.big[atomicAdd(L.n_big, 1)] = code;
             continue;
         }
-        process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist);
+        process_object<0, int32_t>(a, g, lds_crop<CAP_L>(smem, q), &red, hist,
+                                   (int16_t *)(smem + (size_t)CAP_L * 13));
     }
 }
 
@@ -843,7 +925,8 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
         set_error("objects: no global scratch slice");
         return RT_ENOMEM;
     }
-    const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13, lds_l = (size_t)CAP_L * 13;
+    const size_t lds_s = (size_t)CAP_S * 13, lds_m = (size_t)CAP_M * 13;
+    const size_t lds_l = (size_t)CAP_L * 13 + 4 * WIN * WTS * sizeof(int16_t);   // planes + 4 window buffers
     static bool lds_l_set = false;
     if (!lds_l_set) {
         RT_HIP(hipFuncSetAttribute((const void *)k_objects_l, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l));
