@@ -815,7 +815,7 @@ __global__ void k_objects_classify(const ObjArgs *args, ObjLists L) {
 
 // small class: erases components below the first area threshold and
 // processes crops up to 32 x 32
-__global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjLists L) {
+__global__ __launch_bounds__(WAVE, 3) void k_objects_s(const ObjArgs *args, ObjLists L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int red;
     __shared__ int hist[HBINS + 1];
