@@ -214,12 +214,15 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *                             the worklist counter; default 8
  *   "recon_max_sweeps"  1..1024 in-tile sweeps before a tile re-queues itself;
  *                             default 64
- *   "recon_mode"        0|1   0: reconstruction in rounds (all queued tiles per
+ *   "recon_mode"        0..2  0: reconstruction in rounds (all queued tiles per
  *                             launch, host checks between round batches);
  *                             1: one persistent work-queue launch (waves take
  *                             tiles from a device queue and push neighbours;
  *                             if a wave waits longer than 2 ms the remaining
- *                             work runs in rounds); default 0
+ *                             work runs in rounds); 2: recon_queue_after
+ *                             rounds as launches, then the work queue seeded
+ *                             with the tiles they left queued; default 0
+ *   "recon_queue_after" 1..64 rounds before the work queue in mode 2; default 2
  *   "objects_path"      0..2  routing of components to the per-object kernels:
  *                             0 crops <= 32^2 and <= 64^2 to the register-scan
  *                             classes, up to 9312 px to the LDS class, larger

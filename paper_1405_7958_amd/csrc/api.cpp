@@ -556,15 +556,19 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     sp.scale = p->hq_scale;
     const ReconImg *rimgs = at<ReconImg>(c, P.o_rec);
     int rounds = 0;
-    const bool queue = c->knobs.recon_mode == 1;
+    const bool queue = c->knobs.recon_mode != 0;
+    // mode 2: the first rounds as launches (every tile is busy), the rest of
+    // the propagation in one work-queue launch (no round barrier per step)
+    const int kq = c->knobs.recon_mode == 2 ? c->knobs.recon_queue_after : 0;
     if (!use_graph) {
         if ((e = enqueue_front(c, P, sp, s, true))) return e;
         if (queue) {
             int aborted = 0;
-            if ((e = recon_queue(c, P.run, rimgs, n, RT_U8, 8, s)) ||
+            if (kq > 0 && (e = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, kq, s))) return e;
+            if ((e = recon_queue(c, P.run, rimgs, n, RT_U8, 8, s, kq)) ||
                 (e = recon_queue_aborted(c, P.run, s, &aborted)))
                 return e;
-            rounds = 1;
+            rounds = kq + 1;
             if (aborted) {
                 int more = 0;
                 if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
@@ -579,7 +583,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     }
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
-                                c->knobs.objects_path, c->knobs.recon_mode, c->knobs.recon_level_mode,
+                                c->knobs.objects_path, c->knobs.recon_mode, kq, c->knobs.recon_level_mode,
                                 c->knobs.recon_level_frac,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
@@ -611,7 +615,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
             c,
             [&](hipStream_t cs) {
                 int e2 = enqueue_front(c, P, sp, cs, false);
-                if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, RT_U8, 8, cs)
+                if (!e2 && kq > 0) e2 = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, kq, cs);
+                if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, RT_U8, 8, cs, kq)
                                     : recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, budget, cs);
                 return e2;
             },
@@ -629,7 +634,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     if (queue) {
         int aborted = 0;
         if ((e = recon_queue_aborted(c, P.run, s, &aborted))) return e;
-        rounds = 1;
+        rounds = kq + 1;
         if (aborted) {
             int more = 0;
             if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
@@ -1103,8 +1108,11 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
         CHECK(value >= 1 && value <= 1024, "rt_set_knob: recon_max_sweeps must be 1..1024");
         c->knobs.recon_max_sweeps = value;
     } else if (n == "recon_mode") {
-        CHECK(value == 0 || value == 1, "rt_set_knob: recon_mode must be 0 or 1");
+        CHECK(value >= 0 && value <= 2, "rt_set_knob: recon_mode must be 0, 1 or 2");
         c->knobs.recon_mode = value;
+    } else if (n == "recon_queue_after") {
+        CHECK(value >= 1 && value <= 64, "rt_set_knob: recon_queue_after must be 1..64");
+        c->knobs.recon_queue_after = value;
     } else if (n == "objects_path") {
         CHECK(value >= 0 && value <= 2, "rt_set_knob: objects_path must be 0..2");
         c->knobs.objects_path = value;
@@ -1138,6 +1146,8 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.objects_path;
     else if (n == "recon_mode")
         *value = c->knobs.recon_mode;
+    else if (n == "recon_queue_after")
+        *value = c->knobs.recon_queue_after;
     else if (n == "graph")
         *value = c->knobs.graph;
     else if (n == "graph_rounds")

@@ -224,6 +224,33 @@ __global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
     }
 }
 
+// Seeding from the worklist a round left behind (count on the device): the
+// first kernel empties the ring and the in-queue flags, the second puts the
+// listed tiles under tickets 0 .. count-1.
+__global__ void k_queue_clear(QueueArgs q) {
+    const int cap = 2 * q.total;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
+        q.ring[i] = RING_EMPTY;
+        if (i < q.total) q.inq[i] = 0u;
+    }
+}
+
+__global__ void k_queue_seed(QueueArgs q, const int32_t *list, const int32_t *count) {
+    const int nl = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+        const int tile = list[i];
+        q.ring[i] = ((unsigned long long)i << 32) | (unsigned)tile;
+        q.inq[tile] = 1u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        q.ctl[0] = 0u;
+        q.ctl[1] = (unsigned)nl;
+        q.ctl[2] = (unsigned)nl;
+        q.ctl[3] = 0u;
+        q.ctl[4] = 0u;
+    }
+}
+
 __global__ void k_queue_init(QueueArgs q) {
     const int cap = 2 * q.total;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
@@ -670,7 +697,7 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
 }
 
 int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
-                hipStream_t s) {
+                hipStream_t s, int from_round) {
     if (run.total <= 0) return RT_OK;
     QueueArgs q;
     q.imgs = imgs_dev;
@@ -683,7 +710,16 @@ int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, i
     q.spin_limit = 200000;   // 2 ms at the 100 MHz wall clock
     q.visits = c->prof_on ? c->prof_visits : nullptr;
     const int gi = (int)std::min<int64_t>((2 * (int64_t)run.total + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_queue_init, dim3(gi), dim3(256), 0, s, q);
+    if (from_round <= 0) {
+        hipLaunchKernelGGL(k_queue_init, dim3(gi), dim3(256), 0, s, q);
+    } else {
+        // the list that round from_round - 1 wrote, counted by counter from_round % 3
+        hipLaunchKernelGGL(k_queue_clear, dim3(gi), dim3(256), 0, s, q);
+        RT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_queue_seed, dim3(gi), dim3(256), 0, s, q,
+                           (const int32_t *)(run.lists + (from_round & 1) * (size_t)run.total),
+                           (const int32_t *)(run.cnt + (from_round % 3)));
+    }
     RT_HIP(hipGetLastError());
     hipEvent_t ev_end = nullptr;
     if (c->prof_on) {
@@ -760,12 +796,14 @@ int recon_rounds(rt_ctx_impl *c, const ReconImg *imgs_dev, int n, int dtype, int
     const size_t mark = c->arena.off;
     ReconRun run;
     int e = recon_prepare(c, total, run);
-    if (!e && c->knobs.recon_mode == 1) {
+    if (!e && c->knobs.recon_mode != 0) {
         int aborted = 0;
-        e = recon_queue(c, run, imgs_dev, n, dtype, conn, s);
+        const int kq = c->knobs.recon_mode == 2 ? c->knobs.recon_queue_after : 0;
+        if (kq > 0) e = recon_launch(c, run, imgs_dev, n, dtype, conn, 0, kq, s);
+        if (!e) e = recon_queue(c, run, imgs_dev, n, dtype, conn, s, kq);
         if (!e) e = recon_queue_aborted(c, run, s, &aborted);
         if (!e && aborted) e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
-        else if (rounds_out) *rounds_out = 1;
+        else if (rounds_out) *rounds_out = kq + 1;
     } else if (!e) {
         e = recon_finish(c, run, imgs_dev, n, dtype, conn, 0, s, rounds_out);
     }

@@ -57,7 +57,8 @@ struct Knobs {
     int recon_round_batch = 8;   // propagation rounds launched between host checks
     int recon_max_sweeps = 64;   // in-tile sweeps before a tile re-queues itself
     int objects_path = 0;        // per-object class routing (ObjLists::path)
-    int recon_mode = 0;          // 0: rounds with host checks; 1: one work-queue launch
+    int recon_mode = 0;          // 0: rounds with host checks; 1: one work-queue launch; 2: rounds, then the queue
+    int recon_queue_after = 2;   // recon_mode 2: rounds launched before the work queue takes over
     int graph = 0;               // replay segmentation batches from captured HIP graphs
     int graph_rounds = 24;       // reconstruction rounds inside the first graph
 };
@@ -206,8 +207,10 @@ int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run);
 int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
                  int k1, hipStream_t s);
 // Enqueues the work-queue propagation (one persistent launch; capturable).
+// from_round > 0: seed the queue with the worklist round from_round - 1 left
+// (rounds 0 .. from_round - 1 already enqueued on s); else with every tile
 int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
-                hipStream_t s);
+                hipStream_t s, int from_round = 0);
 // After recon_queue: whether a wave gave up waiting (synchronises `s`); the
 // caller then finishes with recon_finish from round 0.
 int recon_queue_aborted(rt_ctx_impl *c, const ReconRun &run, hipStream_t s, int *aborted);

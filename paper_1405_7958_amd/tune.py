@@ -33,7 +33,8 @@ SPACE = {
     "recon_round_batch": [4, 8, 16, 32],
     "recon_max_sweeps": [16, 32, 64, 128],
     "objects_path": [0, 1, 2],
-    "recon_mode": [0, 1],
+    "recon_mode": [0, 1, 2],
+    "recon_queue_after": [2, 1, 3, 4],
 }
 
 

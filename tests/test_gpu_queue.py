@@ -1,6 +1,7 @@
-"""The work-queue reconstruction (recon_mode 1) against the oracle: single
-reconstructions (u8 / int32, 4 / 8 connectivity, domains, a spiral whose
-path crosses every tile), whole tiles, and graph replays of a batch."""
+"""The work-queue reconstruction against the oracle, alone (recon_mode 1) and
+after a round of launches (recon_mode 2): single reconstructions (u8 /
+int32, 4 / 8 connectivity, domains, a spiral whose path crosses every tile),
+whole tiles, and graph replays of a batch."""
 import numpy as np
 import pytest
 
@@ -18,10 +19,11 @@ def rt():
     return rtseg
 
 
-@pytest.fixture(scope="module")
-def qctx(rt):
+@pytest.fixture(scope="module", params=[1, 2])
+def qctx(rt, request):
     c = rt.Context(0)
-    rt.rt_set_knob("recon_mode", 1, ctx=c)
+    rt.rt_set_knob("recon_mode", request.param, ctx=c)
+    rt.rt_set_knob("recon_queue_after", 1, ctx=c)
     yield c
     c.close()
 
@@ -63,11 +65,12 @@ def test_queue_segment_tiles(rt, oracle, qctx, levels):
     rt.rt_set_knob("recon_levels", 3, ctx=qctx)
 
 
-def test_queue_batch_graph_replays(rt, oracle):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_queue_batch_graph_replays(rt, oracle, mode):
     import torch
     d = dev()
     c = rt.Context(0)
-    rt.rt_set_knob("recon_mode", 1, ctx=c)
+    rt.rt_set_knob("recon_mode", mode, ctx=c)
     specs = [synth.spec_uneven(i) for i in (0, 2)]
     specs = [synth.TileSpec(w=min(s.w, 1024), h=min(s.h, 1024), seed=s.seed, n_nuclei=s.n_nuclei // 4, amin=4,
                             amax=14, cluster_frac=0.2, cluster_min=2, cluster_max=4, jitter=20) for s in specs]
