@@ -202,11 +202,15 @@ __global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
         }
         item = __shfl(item, 0, 64);
         if (item < 0) break;
-        __threadfence();   // acquire: the pusher's tile writes are visible
         if (lane == 0) {
             atomicExch(q.inq + item, 0u);
             if (q.visits) atomicAdd(q.visits, 1ull);
         }
+        // acquire after leaving the queue: a neighbour that changed this
+        // tile's input and found it still queued (so did not queue it again)
+        // released its writes before that test, which precedes the exchange
+        // above; fencing before the exchange could keep stale lines cached
+        __threadfence();
         const ReconImg a = q.imgs[recon_img_of(q.imgs, q.n, item)];
         recon_tile<T, CONN, true>(a, item, q.max_sweeps, Ts, [&](int nb, bool valid) {
             if (valid && atomicExch(q.inq + nb, 1u) == 0u) {
