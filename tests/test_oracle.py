@@ -299,6 +299,58 @@ def test_seeds_are_regional_maxima_of_hmaxima(oracle):
             assert (I["seeds"][cl == c] > 0).any()
 
 
+def test_rmax_identity_and_hmaxima_bound():
+    """For integer g on a domain, the regional maxima are exactly where
+    g - rho_g(g - 1) = 1 (the reconstruction lowers every other plateau by one),
+    and every regional maximum of the h-maxima transform rho_g(g - h) contains a
+    regional maximum of g, so no component holds more seeds than maxima of g.
+    The per-object kernels count maxima with the first identity and skip the
+    h-maxima step when a component has a single one."""
+    r = np.random.Generator(np.random.PCG64(77))
+    for t in range(60):
+        h, w = int(r.integers(3, 13)), int(r.integers(3, 13))
+        dom = r.random((h, w)) < 0.8
+        g = r.integers(0, 6, (h, w)).astype(np.int64)
+        if t % 3 == 0:
+            g = ndi.uniform_filter(g * 4, 3).astype(np.int64)       # broader plateaus
+        g = np.where(dom, g, 0)
+        rm = B.regional_maxima(g, dom, 8)
+        low = B.recon_iterate(np.where(dom, g - 1, 0), g, dom, 8)
+        assert np.array_equal(rm, dom & (g - low == 1))
+        cl, n = ndi.label(dom, structure=np.ones((3, 3)))
+        for hh in (1, 2, 3):
+            hm = B.recon_iterate(np.where(dom, g - hh, 0), g, dom, 8)
+            rmh = B.regional_maxima(hm, dom, 8)
+            lab_g, _ = B.scipy_ccl(rm, 8)
+            lab_h, _ = B.scipy_ccl(rmh, 8)
+            for c in range(1, n + 1):
+                comp = cl == c
+                # each maximum of the transform holds a maximum of g
+                for m in np.unique(lab_h[comp & (lab_h > 0)]):
+                    assert (rm & (lab_h == m)).any()
+                assert len(np.unique(lab_h[comp & (lab_h > 0)])) <= len(np.unique(lab_g[comp & (lab_g > 0)]))
+
+
+def test_single_maximum_component_is_one_object(oracle):
+    """A foreground component whose distance map has one regional maximum comes
+    out of the watershed as one object covering the whole component."""
+    seen = 0
+    for fg in _blob_cases(80, 23):
+        lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
+        dq = I["dq"]
+        rm = B.regional_maxima(dq, fg, 8)
+        cl, n = B.scipy_ccl(fg, 8)
+        rml, _ = B.scipy_ccl(rm, 8)
+        for c in range(1, n + 1):
+            comp = cl == c
+            if len(np.unique(rml[comp & (rml > 0)])) != 1:
+                continue
+            seen += 1
+            assert (mask[comp] == 1).all()
+            assert len(np.unique(lab[comp])) == 1
+    assert seen > 20
+
+
 def test_lambda_is_widest_path(oracle):
     for fg in _blob_cases(40, 19):
         lab, mask, I = oracle.watershed(fg, None, 3, intermediates=True)
