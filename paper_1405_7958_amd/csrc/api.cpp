@@ -272,6 +272,7 @@ struct Plan {
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
     bool any_maps = false;   // some tile asks for its foreground / seed maps
+    int rdt = RECON_U8_PLAIN;   // reconstruction kernel: plain uint8 unless an image reaches 2 GiB
     ReconRun run;
 };
 
@@ -481,6 +482,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         cl[i] = A;
 
         rec[i] = ReconImg{t.w, t.h, pw, hq, R, nullptr, (t.w + 61) / 62, (t.h + 61) / 62, q.rec0};
+        if ((int64_t)t.w * t.h + 8 >= (int64_t(1) << 31)) P.rdt = RT_U8;
 
         CclArgs B{};
         B.pred = CclPred::TophatBg;
@@ -564,17 +566,17 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         if ((e = enqueue_front(c, P, sp, s, true))) return e;
         if (queue) {
             int aborted = 0;
-            if (kq > 0 && (e = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, kq, s))) return e;
-            if ((e = recon_queue(c, P.run, rimgs, n, RT_U8, 8, s, kq)) ||
+            if (kq > 0 && (e = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, kq, s))) return e;
+            if ((e = recon_queue(c, P.run, rimgs, n, P.rdt, 8, s, kq)) ||
                 (e = recon_queue_aborted(c, P.run, s, &aborted)))
                 return e;
             rounds = kq + 1;
             if (aborted) {
                 int more = 0;
-                if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
+                if ((e = recon_finish(c, P.run, rimgs, n, P.rdt, 8, 0, s, &more))) return e;
                 rounds += more;
             }
-        } else if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &rounds))) {
+        } else if ((e = recon_finish(c, P.run, rimgs, n, P.rdt, 8, 0, s, &rounds))) {
             return e;
         }
         c->prof_launches[2] += rounds;
@@ -615,9 +617,9 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
             c,
             [&](hipStream_t cs) {
                 int e2 = enqueue_front(c, P, sp, cs, false);
-                if (!e2 && kq > 0) e2 = recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, kq, cs);
-                if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, RT_U8, 8, cs, kq)
-                                    : recon_launch(c, P.run, rimgs, n, RT_U8, 8, 0, budget, cs);
+                if (!e2 && kq > 0) e2 = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, kq, cs);
+                if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, P.rdt, 8, cs, kq)
+                                    : recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, budget, cs);
                 return e2;
             },
             &g->a);
@@ -637,10 +639,10 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         rounds = kq + 1;
         if (aborted) {
             int more = 0;
-            if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, 0, s, &more))) return e;
+            if ((e = recon_finish(c, P.run, rimgs, n, P.rdt, 8, 0, s, &more))) return e;
             rounds += more;
         }
-    } else if ((e = recon_finish(c, P.run, rimgs, n, RT_U8, 8, budget, s, &rounds))) {
+    } else if ((e = recon_finish(c, P.run, rimgs, n, P.rdt, 8, budget, s, &rounds))) {
         return e;
     }
     c->last_rounds = rounds;
@@ -773,7 +775,9 @@ int rt_morph_recon(rt_ctx *c, int dtype, const void *marker, const void *mask, v
                     o_args)) ||
         (e = sg.flush(s)))
         return e;
-    return recon_rounds(c, at<ReconImg>(c, o_args), 1, dtype, conn, (int)ntiles, s);
+    // the plain uint8 kernel addresses the images with 32-bit offsets
+    const bool plain = dtype == RT_U8 && !domain && (int64_t)(h - 1) * pitch + w + 8 < (int64_t(1) << 31);
+    return recon_rounds(c, at<ReconImg>(c, o_args), 1, plain ? RECON_U8_PLAIN : dtype, conn, (int)ntiles, s);
 }
 
 int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t h, int64_t pitch, int bg_conn,

@@ -110,9 +110,237 @@ __device__ __forceinline__ int shl0(int v) {  // lane i <- lane i+1 (lane 63: do
 template <typename T, int CONN, bool QUEUE, typename Push>
 __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*Ts)[65], Push push);
 
-template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
-    __shared__ int Ts[64][65];
+// Plain uint8 images (no domain), the reconstruction of ReconToNuclei.
+//
+// Every value is >= 0 here, so a pixel outside the image carries the value 0
+// and every non-member (outside the image, or on the ring) carries the mask
+// 0: for it max(r, min(m, 0)) = r, so it never changes, and the zeros it
+// feeds to its neighbours' scan steps never raise a member, whose value is
+// >= 0.  Scan steps then need no membership test.  Both images are staged
+// through LDS in row order: each lane loads 17 aligned dwords per image (the
+// 64-byte rows of a block start at any byte), each clamped to a dword that
+// holds at least one byte of its row; an aligned dword never crosses a page,
+// so no load leaves the pages of the row's bytes.  Bytes outside the image
+// are masked when the registers are built.  The sweep tests convergence by
+// the wave's sum of values: values only rise, so a sweep changed something
+// iff the sum grew.
+constexpr int SP = 68;                   // staging row pitch in bytes (17 dwords)
+constexpr int TP = 66;                   // transpose row pitch in uint16 (33 dwords)
+constexpr int PLAIN_LDS = 2 * 64 * SP;   // two staged images; >= 64 * TP * 2
+
+extern "C" __device__ int __ockl_wfred_add_i32(int);
+
+// bytes b of a dword whose index 4k + b lies in [lo, hi]
+__device__ __forceinline__ uint32_t byte_span(int k, int lo, int hi) {
+    const int a = min(max(lo - 4 * k, 0), 4), b = min(max(hi + 1 - 4 * k, 0), 4);
+    return (uint32_t)(((1ull << (8 * b)) - 1ull) & ~((1ull << (8 * a)) - 1ull));
+}
+
+template <int CONN, bool QUEUE, typename Push>
+__device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, uint8_t *lds, Push push) {
+    const int lane = threadIdx.x;
+    const int tile = gtile - a.unit0;
+    const int tx = tile % a.ntx, ty = tile / a.ntx;
+    // block coordinate (i, j) is image pixel (x0-1+i, y0-1+j)
+    const int x0 = tx * RIN, y0 = ty * RIN;
+    uint8_t *rr = static_cast<uint8_t *>(a.r);
+    const uintptr_t bR = (uintptr_t)rr, bM = (uintptr_t)a.mask;
+    uint8_t *sR = lds, *sM = lds + 64 * SP;
+    uint16_t *Tw = reinterpret_cast<uint16_t *>(lds);
+    // last interior column / row inside the image (block coordinates)
+    const int limw = min(RIN, a.w - x0), limh = min(RIN, a.h - y0);
+
+    // byte offsets from the dword-aligned image bases (the host keeps the
+    // images below 2 GiB for this path)
+    const uintptr_t bR4 = bR & ~(uintptr_t)3, bM4 = bM & ~(uintptr_t)3;
+    const int aR = (int)(bR & 3), aM = (int)(bM & 3);
+    const int pitch = (int)a.pitch;
+    {
+        typedef const __attribute__((address_space(1))) uint32_t *gw;
+        typedef const __attribute__((address_space(1))) uint8_t *gb;
+        const gb gR = (gb)bR4, gM = (gb)bM4;
+        // the lane index, opaque to the optimiser so that the addresses below
+        // are recomputed per tile rather than held in registers across tiles
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        // dwords 0..15 of rows 4k .. 4k+3 (16 lanes per row), then dword 16
+        // of row `lane`
+        const int lr = ln >> 4, ld = ln & 15;
+        uint32_t vr[17], vm[17];
+#pragma unroll
+        for (int k = 0; k < 17; ++k) {
+            const int row = k < 16 ? 4 * k + lr : ln, d = k < 16 ? ld : 16;
+            const int yo = min(max(y0 - 1 + row, 0), a.h - 1) * pitch;
+            const int sr = aR + yo, sm = aM + yo;   // the row's first byte
+            const int orr = min(max(((sr + x0 - 1) & ~3) + 4 * d, sr & ~3), (sr + a.w - 1) & ~3);
+            const int om = min(max(((sm + x0 - 1) & ~3) + 4 * d, sm & ~3), (sm + a.w - 1) & ~3);
+            vr[k] = *(gw)(gR + (uint32_t)orr);
+            vm[k] = *(gw)(gM + (uint32_t)om);
+            // addresses are computed next to their loads
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        uint32_t *dR = reinterpret_cast<uint32_t *>(sR + lr * SP + 4 * ld);
+        uint32_t *dM = reinterpret_cast<uint32_t *>(sM + lr * SP + 4 * ld);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            dR[k * SP] = vr[k];   // (4k + lr) * SP bytes = k * SP dwords further
+            dM[k * SP] = vm[k];
+        }
+        reinterpret_cast<uint32_t *>(sR + ln * SP)[16] = vr[16];
+        reinterpret_cast<uint32_t *>(sM + ln * SP)[16] = vm[16];
+    }
+    __syncthreads();
+
+    const int gx = x0 - 1 + lane;
+    const bool col_ok = gx >= 0 && gx < a.w;
+    const bool col_m = lane >= 1 && lane <= limw;
+    const bool row_m = lane >= 1 && lane <= limh;
+    const bool edge = x0 == 0 || y0 == 0 || x0 + RIN >= a.w || y0 + RIN >= a.h;
+    const uint32_t colmask = col_m ? ~0u : 0u, rowmask = row_m ? ~0u : 0u;
+    int r[64];
+    uint32_t mc[16], mr[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        uint32_t p = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = 4 * k + b;
+            const int yo = min(max(y0 - 1 + j, 0), a.h - 1) * pitch;
+            const int oR = (aR + yo + x0 - 1) & 3, oM = (aM + yo + x0 - 1) & 3;
+            r[j] = sR[j * SP + oR + lane];
+            p |= (uint32_t)sM[j * SP + oM + lane] << (8 * b);
+        }
+        mc[k] = p & byte_span(k, 1, limh) & colmask;
+        // at most eight LDS reads in flight: the counter holds no more anyway
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (edge) {
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            const int gy = y0 - 1 + j;
+            r[j] = (col_ok && gy >= 0 && gy < a.h) ? r[j] : 0;
+        }
+    }
+    // lane = row: the mask's row, and the original values of columns 1 and 62
+    int oL, oR;
+    {
+        const int yo = min(max(y0 - 1 + lane, 0), a.h - 1) * pitch;
+        const int o = (aM + yo + x0 - 1) & 3, orr = (aR + yo + x0 - 1) & 3;
+        const uint32_t *srow = reinterpret_cast<const uint32_t *>(sM + lane * SP);
+        uint32_t dw[17];
+#pragma unroll
+        for (int d = 0; d < 17; ++d) dw[d] = srow[d];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            mr[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], o) & byte_span(k, 1, limw) & rowmask;
+        oL = (int)((uint32_t)sR[lane * SP + orr + 1] & rowmask);
+        oR = (int)((uint32_t)sR[lane * SP + orr + RIN] & (limw >= RIN ? rowmask : 0u));
+    }
+    const int oT = r[1], oB = r[62];
+    int tot0 = 0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) tot0 += r[j];
+    int prev = __ockl_wfred_add_i32(tot0);
+    __syncthreads();   // the staging area becomes the transpose buffer
+
+    bool any_change = false;
+    bool converged = false;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        // down and up, lane = column
+        {
+            int pc = r[0];
+#pragma unroll
+            for (int j = 1; j < 64; ++j) {
+                const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
+                pc = max(r[j], min(m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u)));
+                r[j] = pc;
+            }
+#pragma unroll
+            for (int j = 62; j >= 0; --j) {
+                const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
+                pc = max(r[j], min(m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u)));
+                r[j] = pc;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 64; ++j) Tw[j * TP + lane] = (uint16_t)r[j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 64; ++i) r[i] = Tw[lane * TP + i];
+        __syncthreads();
+        // right and left, lane = row; the left scan also sums the final values
+        int acc;
+        {
+            int pc = r[0];
+#pragma unroll
+            for (int i = 1; i < 64; ++i) {
+                const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
+                pc = max(r[i], min(m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u)));
+                r[i] = pc;
+            }
+            acc = pc;
+#pragma unroll
+            for (int i = 62; i >= 0; --i) {
+                const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
+                pc = max(r[i], min(m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u)));
+                r[i] = pc;
+                acc += pc;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 64; ++i) Tw[lane * TP + i] = (uint16_t)r[i];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 64; ++j) r[j] = Tw[j * TP + lane];
+        __syncthreads();
+        const int tot = __ockl_wfred_add_i32(acc);
+        if (tot == prev) {
+            converged = true;
+            break;
+        }
+        prev = tot;
+        any_change = true;
+    }
+    if (!any_change) return;
+
+    // write back the interior members (own column)
+    if (col_m) {
+#pragma unroll
+        for (int j = 1; j < 63; ++j)
+            if (j <= limh) rr[(int64_t)(y0 - 1 + j) * a.pitch + gx] = (uint8_t)r[j];
+    }
+    // which interior edges changed?  (Tw keeps the row-major copy)
+    const bool cT = col_m && r[1] != oT, cB = col_m && r[62] != oB;
+    const bool cL = row_m && (int)Tw[lane * TP + 1] != oL, cR = row_m && (int)Tw[lane * TP + RIN] != oR;
+    const uint64_t mT = __ballot(cT), mB = __ballot(cB), mL = __ballot(cL), mR = __ballot(cR);
+    if constexpr (QUEUE) __threadfence();   // release the tile's writes before announcing them
+    int nb[9];
+    int nn = 0;
+    auto add = [&](int dx, int dy) {
+        int nx = tx + dx, ny = ty + dy;
+        if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = a.unit0 + ny * a.ntx + nx;
+    };
+    if (mT) add(0, -1);
+    if (mB) add(0, 1);
+    if (mL) add(-1, 0);
+    if (mR) add(1, 0);
+    if (CONN == 8) {
+        if ((mT >> 1) & 1ull) add(-1, -1);
+        if ((mT >> 62) & 1ull) add(1, -1);
+        if ((mB >> 1) & 1ull) add(-1, 1);
+        if ((mB >> 62) & 1ull) add(1, 1);
+    }
+    if (!converged) nb[nn++] = gtile;
+    int mine = -1;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (k == lane && k < nn) mine = nb[k];
+    push(mine, lane < nn);
+}
+
+template <typename T, int CONN, bool PLAIN>
+__global__ __launch_bounds__(64, PLAIN ? 3 : 1) void k_recon_round(RoundArgs ra) {
+    __shared__ __align__(16) uint8_t lds[PLAIN ? PLAIN_LDS : 64 * 65 * 4];
     const int lane = threadIdx.x;
     int32_t *cnt_in = ra.cnt + (ra.k % 3);
     int32_t *cnt_out = ra.cnt + ((ra.k + 1) % 3);
@@ -125,7 +353,7 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
         const int gtile = ra.first ? slot : ra.list_in[slot];
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
         // every lane calls push; one counter update per wave for its new entries
-        recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, Ts, [&](int item, bool valid) {
+        auto push = [&](int item, bool valid) {
             const bool fresh = valid && atomicExch(ra.stamp + item, ra.epoch) != ra.epoch;
             const uint64_t m = __ballot(fresh);
             if (!m) return;
@@ -133,7 +361,11 @@ __global__ __launch_bounds__(64) void k_recon_round(RoundArgs ra) {
             if (lane == 0) base = atomicAdd(cnt_out, __popcll(m));
             base = __shfl(base, 0, 64);
             if (fresh) ra.list_out[base + __popcll(m & ((1ull << lane) - 1))] = item;
-        });
+        };
+        if constexpr (PLAIN)
+            recon_tile_plain<CONN, false>(a, gtile, ra.max_sweeps, lds, push);
+        else
+            recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, reinterpret_cast<int (*)[65]>(lds), push);
         __syncthreads();
     }
 }
@@ -159,9 +391,9 @@ struct QueueArgs {
 
 constexpr unsigned long long RING_EMPTY = ~0ull;
 
-template <typename T, int CONN>
-__global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
-    __shared__ int Ts[64][65];
+template <typename T, int CONN, bool PLAIN>
+__global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_queue(QueueArgs q) {
+    __shared__ __align__(16) uint8_t lds[PLAIN ? PLAIN_LDS : 64 * 65 * 4];
     const int lane = threadIdx.x;
     const unsigned cap = 2u * (unsigned)q.total;
     unsigned int *head = q.ctl, *tail = q.ctl + 1, *pending = q.ctl + 2, *abortf = q.ctl + 3, *done = q.ctl + 4;
@@ -212,14 +444,18 @@ __global__ __launch_bounds__(64) void k_recon_queue(QueueArgs q) {
         // above; fencing before the exchange could keep stale lines cached
         __threadfence();
         const ReconImg a = q.imgs[recon_img_of(q.imgs, q.n, item)];
-        recon_tile<T, CONN, true>(a, item, q.max_sweeps, Ts, [&](int nb, bool valid) {
+        auto push = [&](int nb, bool valid) {
             if (valid && atomicExch(q.inq + nb, 1u) == 0u) {
                 atomicAdd(pending, 1u);
                 const unsigned t = atomicAdd(tail, 1u);
                 __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-        });
+        };
+        if constexpr (PLAIN)
+            recon_tile_plain<CONN, true>(a, item, q.max_sweeps, lds, push);
+        else
+            recon_tile<T, CONN, true>(a, item, q.max_sweeps, reinterpret_cast<int (*)[65]>(lds), push);
         __syncthreads();
         if (lane == 0) {
             atomicAdd(done, 1u);
@@ -620,9 +856,9 @@ int launch_batch_end(const BatchAux *aux, int n, hipStream_t s) {
     return hip_fail(hipGetLastError(), "k_batch_end");
 }
 
-template <typename T, int CONN>
+template <typename T, int CONN, bool PLAIN = false>
 static void launch_round(const RoundArgs &ra, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_recon_round<T, CONN>), dim3(grid), dim3(64), 0, s, ra);
+    hipLaunchKernelGGL((k_recon_round<T, CONN, PLAIN>), dim3(grid), dim3(64), 0, s, ra);
 }
 
 int64_t recon_tiles(int w, int h) { return (int64_t)((w + RIN - 1) / RIN) * ((h + RIN - 1) / RIN); }
@@ -687,7 +923,12 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
             ev_end = c->round_events[c->round_used + 1];
             c->round_used += 2;
         }
-        if (dtype == RT_U8) {
+        if (dtype == RECON_U8_PLAIN) {
+            // three waves per SIMD fit the plain kernel's registers
+            const int g = std::min(run.total, c->n_cu * 12);
+            if (conn == 8) launch_round<uint8_t, 8, true>(ra, g, s);
+            else launch_round<uint8_t, 4, true>(ra, g, s);
+        } else if (dtype == RT_U8) {
             if (conn == 8) launch_round<uint8_t, 8>(ra, grid, s);
             else launch_round<uint8_t, 4>(ra, grid, s);
         } else {
@@ -738,12 +979,15 @@ int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, i
     }
     // every wave resident: 2 waves per SIMD fit the kernel's registers
     const int grid = std::min(run.total, c->n_cu * 8);
-    if (dtype == RT_U8) {
-        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<uint8_t, 8>), dim3(grid), dim3(64), 0, s, q);
-        else hipLaunchKernelGGL((k_recon_queue<uint8_t, 4>), dim3(grid), dim3(64), 0, s, q);
+    if (dtype == RECON_U8_PLAIN) {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<uint8_t, 8, true>), dim3(grid), dim3(64), 0, s, q);
+        else hipLaunchKernelGGL((k_recon_queue<uint8_t, 4, true>), dim3(grid), dim3(64), 0, s, q);
+    } else if (dtype == RT_U8) {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<uint8_t, 8, false>), dim3(grid), dim3(64), 0, s, q);
+        else hipLaunchKernelGGL((k_recon_queue<uint8_t, 4, false>), dim3(grid), dim3(64), 0, s, q);
     } else {
-        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<int32_t, 8>), dim3(grid), dim3(64), 0, s, q);
-        else hipLaunchKernelGGL((k_recon_queue<int32_t, 4>), dim3(grid), dim3(64), 0, s, q);
+        if (conn == 8) hipLaunchKernelGGL((k_recon_queue<int32_t, 8, false>), dim3(grid), dim3(64), 0, s, q);
+        else hipLaunchKernelGGL((k_recon_queue<int32_t, 4, false>), dim3(grid), dim3(64), 0, s, q);
     }
     RT_HIP(hipGetLastError());
     if (ev_end) RT_HIP(hipEventRecord(ev_end, s));

@@ -182,6 +182,9 @@ struct ReconImg {
     int ntx, nty;                  // reconstruction tiles per row / column
     int unit0;                     // first tile of this image in the batch
 };
+// dtype of the reconstruction calls for uint8 images with no domain (the
+// fast round kernel); the API dtypes RT_U8 / RT_I32 select the general one
+constexpr int RECON_U8_PLAIN = 101;
 int64_t recon_tiles(int w, int h);   // number of 62 x 62 reconstruction tiles of a w x h image
 int recon_init(int dtype, const void *marker, const void *mask, void *out, int w, int h, int64_t pitch,
                hipStream_t s);
