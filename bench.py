@@ -53,10 +53,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TILE_VISIT_BYTES = 62 * 62 * 3
+ROUND_KERNEL = "k_recon_round<unsigned char, 8, true>"   # the plain uint8 round kernel
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def tune_cache(args):
+    return None if args.tune_cache.lower() == "none" else args.tune_cache
 
 
 def batch64(rtseg, synth, torch, args):
@@ -69,8 +74,9 @@ def batch64(rtseg, synth, torch, args):
     with ThreadPoolExecutor(8) as ex:
         rgbs = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
     ctx = rtseg.Context(0)
-    res = tune.autotune(rgbs, ctx=ctx, reps=3, cache=None)
-    log(f"autotuned knobs {res['knobs']} ({res['ms']:.2f} ms/batch, {res['seconds']} s)")
+    res = tune.autotune(rgbs, ctx=ctx, reps=3, cache=tune_cache(args))
+    log(f"{'cached' if res.get('cached') else 'autotuned'} knobs {res['knobs']} ({res['ms']:.2f} ms/batch, "
+        f"{res['seconds']} s)")
     params = rtseg.default_params()
     for _ in range(2):
         rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
@@ -87,7 +93,7 @@ def batch64(rtseg, synth, torch, args):
     log(f"batch64: {ms:.2f} ms/batch, {64 / (ms * 1e-3):.1f} tiles/s, {px / (ms * 1e-3) / 1e6:.0f} Mpx/s")
     out = {"tiles": 64, "megapixels": round(px / 1e6, 2), "steps": steps, "ms_per_batch": round(ms, 3),
            "tiles_per_s": round(64 / (ms * 1e-3), 2), "mpx_per_s": round(px / (ms * 1e-3) / 1e6, 1),
-           "objects": objs, "knobs": res["knobs"],
+           "objects": objs, "knobs": res["knobs"], "knobs_source": "tune cache" if res.get("cached") else "autotuned",
            "pipeline_floor_frac": round(8 * px / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
     ctx.close()
     return out
@@ -179,6 +185,8 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default knobs for the 4096x4096 tile")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1405_7958_amd", "tune_cache.json"),
+                    help="autotuner cache (knob sets by device and tile sizes); 'none' tunes afresh")
     ap.add_argument("--knobs", default="", metavar="K=V,...",
                     help="knobs for the 4096x4096 tile instead of autotuning (e.g. the set a tuned run reported)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1405_7958_amd", "weights", "unet_surrogate.rtunet"))
@@ -220,7 +228,9 @@ def main():
     params = rtseg.default_params()
 
     knobs = None
+    knobs_source = "defaults"
     if args.knobs:
+        knobs_source = "--knobs"
         knobs = {}
         for kv in args.knobs.split(","):
             k, v = kv.split("=")
@@ -229,25 +239,32 @@ def main():
         log(f"knobs for the 4096x4096 tile: {knobs}")
     elif not args.no_tune:
         from paper_1405_7958_amd import tune
-        res = tune.autotune([rgb], ctx=ctx, reps=3, cache=None, allow_graph=False)
+        res = tune.autotune([rgb], ctx=ctx, reps=3, cache=tune_cache(args), allow_graph=False)
         knobs = res["knobs"]
-        log(f"autotuned knobs for the 4096x4096 tile: {knobs} ({res['ms']:.3f} ms, {res['seconds']} s)")
+        knobs_source = "tune cache" if res.get("cached") else "autotuned"
+        log(f"{knobs_source} knobs for the 4096x4096 tile: {knobs} ({res['ms']:.3f} ms, {res['seconds']} s)")
     for i in range(args.warmup):
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    # the timed steps run without instrumentation ...
+    # the timed steps record only the round kernel's timing (two HIP events
+    # around each run of round launches on the call's stream, and the number
+    # of tiles each launch processes) ...
+    rtseg.rt_profile_enable(2, ctx)
+    rtseg.rt_profile_recon_rounds(ctx)  # discard
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
+    rtseg.rt_profile_enable(False, ctx)
     n_obj = int(n.item())
     ms_step = (t1 - t0) * 1e3 / args.steps
     tiles_s = args.steps / (t1 - t0)
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/tile, {tiles_s:.1f} tiles/s, {n_obj} objects")
-    # ... then the same steps again with the library's HIP events at every
-    # stage boundary and around every reconstruction round launch
+    # ... then the same steps again with HIP events at every stage boundary
     rtseg.rt_profile_enable(True, ctx)
     rtseg.rt_profile_read(ctx)          # discard
     rtseg.rt_profile_recon_rounds(ctx)  # discard
@@ -259,7 +276,7 @@ def main():
     t3 = time.perf_counter()
     rtseg.rt_profile_enable(False, ctx)
     calls, stages = rtseg.rt_profile_read(ctx)
-    r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
+    rtseg.rt_profile_recon_rounds(ctx)  # the timed steps' figures are kept
     ms_prof = (t3 - t2) * 1e3 / args.steps
     log(f"instrumented steps: {ms_prof:.3f} ms/tile")
 
@@ -285,14 +302,15 @@ def main():
             used = knobs or {k: rtseg.rt_get_knob(k, ctx=ctx) for k in rtseg.KNOBS}
             same = all(int(used.get(k, -1)) == int(v) for k, v in tj.get("knobs", {}).items()
                        if k in ("recon_levels", "recon_level_mode", "recon_level_frac", "recon_round_batch"))
+            same = same and tj.get("kernel") == ROUND_KERNEL   # counters of this kernel's code
             traffic = tj.get("bytes_per_launch") if same and tj.get("knobs") else None
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "kernel": "k_recon_round<unsigned char, 8>",
+            "kernel": ROUND_KERNEL,
             "alg_bytes_per_launch": round(bytes_launch), "us_per_launch": round(ms_launch * 1e3, 2),
-            "launches_per_tile": round(r_launches / max(1, calls), 2),
+            "launches_per_tile": round(r_launches / max(1, args.steps), 2),
             "tile_visits_per_launch": round(r_visits / max(1, r_launches), 1)}
 
     batch = None
@@ -332,7 +350,7 @@ def main():
                                "8000 nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20, seed 0",
                    "tile": [h, w], "objects": n_obj, "foreground_px": fg,
                    "pipeline_floor_frac": round(8 * N * tiles_s / (HBM_PEAK_GBS * 1e9), 5),
-                   "knobs": knobs, "ms_per_step_instrumented": round(ms_prof, 4), "stages": per_stage},
+                   "knobs": knobs, "knobs_source": knobs_source, "ms_per_step_instrumented": round(ms_prof, 4), "stages": per_stage},
         "roofline": roof,
         "batch64": batch,
         "surrogate": sur,

@@ -246,8 +246,11 @@ int rt_set_knob(rt_ctx *ctx, const char *name, int value);
 int rt_get_knob(rt_ctx *ctx, const char *name, int *value);
 
 /*
- * Stage timing, for benchmarks.  While enabled, rt_segment_tile records HIP
- * events on its own stream at the boundaries of its stages:
+ * Stage timing, for benchmarks.  rt_profile_enable(ctx, 1) turns on stage
+ * and round timing, (ctx, 2) round timing only (rt_profile_recon_rounds; two
+ * events per run of round launches, no stage events), (ctx, 0) neither.
+ * While stage timing is on, rt_segment_tile records HIP events on its own
+ * stream at the boundaries of its stages:
  *   0 deconv       colour deconvolution (table, histogram, pixels)
  *   1 level_bound  frame connectivity of the upper level sets (CCL, 8 levels)
  *   2 recon        reconstruction rounds (one launch per round)
@@ -266,11 +269,14 @@ int rt_profile_enable(rt_ctx *ctx, int enable);
 int rt_profile_read(rt_ctx *ctx, double *ms, int64_t *launches, int max_stages);
 const char *rt_profile_stage_name(int stage);
 /*
- * Per-launch timing of the reconstruction round kernel, recorded while stage
- * timing is enabled: a pair of HIP events around every round launch on the
- * call's stream.  Returns the summed kernel milliseconds, the number of round
- * launches and the number of 62 x 62 tile visits (tiles processed, over all
- * rounds) since the last read, synchronises the events and clears the record.
+ * Timing of the reconstruction round kernel, recorded while profiling is
+ * enabled (mode 1 or 2): a pair of HIP events on the call's stream around
+ * each run of consecutive round launches (the launches between two host
+ * checks of the worklist, or the one work-queue launch), so the time between
+ * launches of a run counts as kernel time.  Returns the summed milliseconds,
+ * the number of round launches and the number of 62 x 62 tile visits (tiles
+ * processed, over all rounds) since the last read, synchronises the events
+ * and clears the record.
  */
 int rt_profile_recon_rounds(rt_ctx *ctx, double *kernel_ms, int64_t *launches, int64_t *tile_visits);
 

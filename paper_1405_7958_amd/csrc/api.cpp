@@ -184,7 +184,7 @@ const char *kStageNames[RT_PROF_STAGES] = {"deconv", "level_bound", "recon", "fi
 // Boundary event `k` (0..RT_PROF_STAGES) of the current profiled call, or
 // nullptr when profiling is off.
 hipEvent_t prof_event(rt_ctx *c, int k) {
-    if (!c->prof_on) return nullptr;
+    if (!c->prof_stages) return nullptr;
     size_t idx = c->prof_used + (size_t)k;
     while (c->prof_events.size() <= idx) {
         hipEvent_t ev;
@@ -195,7 +195,7 @@ hipEvent_t prof_event(rt_ctx *c, int k) {
 }
 
 int prof_mark(rt_ctx *c, int k, hipStream_t s) {
-    if (!c->prof_on) return RT_OK;
+    if (!c->prof_stages) return RT_OK;
     hipEvent_t ev = prof_event(c, k);
     if (!ev) {
         set_error("profiling: hipEventCreate failed");
@@ -1173,6 +1173,7 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
 
 int rt_profile_enable(rt_ctx *c, int enable) {
     CHECK(c, "rt_profile_enable: ctx is NULL");
+    CHECK(enable >= 0 && enable <= 2, "rt_profile_enable: mode %d (0, 1 or 2)", enable);
     int e = set_dev(c);
     if (e) return e;
     if (enable && !c->prof_visits) {
@@ -1180,6 +1181,7 @@ int rt_profile_enable(rt_ctx *c, int enable) {
         RT_HIP(hipMemset(c->prof_visits, 0, sizeof(unsigned long long)));
     }
     c->prof_on = enable != 0;
+    c->prof_stages = enable == 1;
     return RT_OK;
 }
 
@@ -1195,7 +1197,7 @@ int rt_profile_recon_rounds(rt_ctx *c, double *kernel_ms, int64_t *launches, int
         ms += t;
     }
     *kernel_ms = ms;
-    *launches = (int64_t)(c->round_used / 2);
+    *launches = c->round_launches;
     unsigned long long v = 0;
     if (c->prof_visits) {
         RT_HIP(hipMemcpy(&v, c->prof_visits, sizeof v, hipMemcpyDeviceToHost));
@@ -1203,6 +1205,7 @@ int rt_profile_recon_rounds(rt_ctx *c, double *kernel_ms, int64_t *launches, int
     }
     *tile_visits = (int64_t)v;
     c->round_used = 0;
+    c->round_launches = 0;
     return RT_OK;
 }
 

@@ -347,8 +347,7 @@ __global__ __launch_bounds__(64, PLAIN ? 3 : 1) void k_recon_round(RoundArgs ra)
     int32_t *cnt_clr = ra.cnt + ((ra.k + 2) % 3);
     if (blockIdx.x == 0 && lane == 0) *cnt_clr = 0;
     const int n_in = ra.first ? ra.total : *cnt_in;
-    if (ra.visits && lane == 0 && (int)blockIdx.x < n_in)
-        atomicAdd(ra.visits, (unsigned long long)((n_in - 1 - (int)blockIdx.x) / (int)gridDim.x + 1));
+    if (ra.visits && lane == 0 && blockIdx.x == 0) atomicAdd(ra.visits, (unsigned long long)n_in);
     for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
         const int gtile = ra.first ? slot : ra.list_in[slot];
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
@@ -905,24 +904,26 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
         if (e) return e;
     }
     ra.visits = c->prof_on ? c->prof_visits : nullptr;
+    hipEvent_t ev_end = nullptr;
+    if (c->prof_on && k1 > k0) {
+        // timing of the round kernel: one pair of events around these
+        // consecutive launches (the gaps between them count as kernel time)
+        while (c->round_events.size() < c->round_used + 2) {
+            hipEvent_t ev;
+            RT_HIP(hipEventCreate(&ev));
+            c->round_events.push_back(ev);
+        }
+        RT_HIP(hipEventRecord(c->round_events[c->round_used], s));
+        ev_end = c->round_events[c->round_used + 1];
+        c->round_used += 2;
+        c->round_launches += k1 - k0;
+    }
     for (int k = k0; k < k1; ++k) {
         ra.k = k;
         ra.first = k == 0;
         ra.list_in = run.lists + (k & 1) * (size_t)run.total;
         ra.list_out = run.lists + ((k + 1) & 1) * (size_t)run.total;
         ra.epoch = (uint32_t)k + 1;
-        hipEvent_t ev_end = nullptr;
-        if (c->prof_on) {
-            // per-launch timing of the round kernel: a pair of events around it
-            while (c->round_events.size() < c->round_used + 2) {
-                hipEvent_t ev;
-                RT_HIP(hipEventCreate(&ev));
-                c->round_events.push_back(ev);
-            }
-            RT_HIP(hipEventRecord(c->round_events[c->round_used], s));
-            ev_end = c->round_events[c->round_used + 1];
-            c->round_used += 2;
-        }
         if (dtype == RECON_U8_PLAIN) {
             // three waves per SIMD fit the plain kernel's registers
             const int g = std::min(run.total, c->n_cu * 12);
@@ -936,8 +937,8 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
             else launch_round<int32_t, 4>(ra, grid, s);
         }
         RT_HIP(hipGetLastError());
-        if (ev_end) RT_HIP(hipEventRecord(ev_end, s));
     }
+    if (ev_end) RT_HIP(hipEventRecord(ev_end, s));
     return RT_OK;
 }
 
@@ -976,6 +977,7 @@ int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, i
         RT_HIP(hipEventRecord(c->round_events[c->round_used], s));
         ev_end = c->round_events[c->round_used + 1];
         c->round_used += 2;
+        c->round_launches += 1;
     }
     // every wave resident: 2 waves per SIMD fit the kernel's registers
     const int grid = std::min(run.total, c->n_cu * 8);

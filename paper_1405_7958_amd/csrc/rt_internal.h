@@ -96,13 +96,15 @@ struct rt_ctx_impl {
     int64_t graph_replays = 0, graph_captures = 0;
     int last_rounds = 0;
     // stage timing
-    bool prof_on = false;
+    bool prof_on = false;                  // round timing (modes 1 and 2)
+    bool prof_stages = false;              // stage boundary events (mode 1)
     std::vector<hipEvent_t> prof_events;   // (RT_PROF_STAGES + 1) per profiled call
     size_t prof_used = 0;                  // events in use
     int64_t prof_launches[RT_PROF_STAGES] = {};
     int prof_calls = 0;
-    std::vector<hipEvent_t> round_events;  // begin/end pairs around reconstruction round launches
+    std::vector<hipEvent_t> round_events;  // begin/end pairs around each run of consecutive round launches
     size_t round_used = 0;
+    int64_t round_launches = 0;            // round launches inside those pairs
     unsigned long long *prof_visits = nullptr;   // device: tiles processed by the round kernel
 };
 

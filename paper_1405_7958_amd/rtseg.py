@@ -333,8 +333,12 @@ def rt_get_knob(name, ctx=None):
 
 
 def rt_profile_enable(enable=True, ctx=None):
+    """True / 1: stage and round timing; 2: round timing only; False / 0: off."""
     ctx = ctx or default_context()
-    _check(lib().rt_profile_enable(ctx.h, 1 if enable else 0))
+    mode = 1 if enable is True else int(enable)
+    if mode not in (0, 1, 2):
+        raise ValueError("rt_profile_enable: 0, 1 or 2")
+    _check(lib().rt_profile_enable(ctx.h, mode))
 
 
 def rt_profile_read(ctx=None):
@@ -351,7 +355,7 @@ def rt_profile_read(ctx=None):
 
 def rt_profile_recon_rounds(ctx=None):
     """Returns (kernel_ms, launches, tile_visits) of the reconstruction round
-    kernel since the last read (recorded while stage timing is on)."""
+    kernel since the last read (recorded in profiling modes 1 and 2)."""
     ctx = ctx or default_context()
     ms = C.c_double()
     ln = C.c_int64()

@@ -86,7 +86,7 @@ def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEF
             hit = None
         if hit:
             apply(hit["knobs"], ctx)
-            return hit
+            return dict(hit, cached=True)
     outs = None
 
     def run():

@@ -182,6 +182,37 @@ def test_graph_single_tile_and_profile_off(rt, oracle):
     ctx.close()
 
 
+def test_profile_modes(rt):
+    """Mode 2 times the round kernel only, mode 1 also the stages; the tile
+    visits of the round kernel cover every tile of the first round."""
+    d = dev()
+    rgb = to_dev(synth.make_tile(synth.spec_small(3))[0], d)
+    h, w = rgb.shape[:2]
+    tiles = ((w + 61) // 62) * ((h + 61) // 62)
+    ctx = rt.Context(0)
+    rt.rt_set_knob("graph", 0, ctx=ctx)
+    with pytest.raises(ValueError):
+        rt.rt_profile_enable(3, ctx)
+    assert rt.lib().rt_profile_enable(ctx.h, 3) == rt.RT_EINVAL
+    for mode in (2, 1):
+        say("profile mode", mode)
+        rt.rt_profile_enable(mode, ctx)
+        rt.rt_profile_read(ctx)
+        rt.rt_profile_recon_rounds(ctx)
+        for _ in range(2):
+            rt.rt_segment_tile(rgb, ctx=ctx)
+        calls, stages = rt.rt_profile_read(ctx)
+        ms, launches, visits = rt.rt_profile_recon_rounds(ctx)
+        rt.rt_profile_enable(False, ctx)
+        assert launches >= 2 and ms > 0.0
+        assert visits >= 2 * tiles
+        if mode == 2:
+            assert calls == 0
+        else:
+            assert calls == 2 and stages["recon"][1] >= launches // 2
+    ctx.close()
+
+
 def test_autotune_keeps_results(rt, tmp_path):
     from paper_1405_7958_amd import tune
     d = dev()

@@ -126,6 +126,32 @@ def test_recon_spiral(rt, oracle):
         assert_equal(to_np(got), oracle.recon(J, s, None, conn).astype(np.uint8), f"spiral conn={conn}")
 
 
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("h,w,pad,offs", [(70, 129, 5, (1, 3, 2)), (130, 67, 0, (2, 0, 3)),
+                                          (63, 63, 1, (3, 1, 1)), (125, 187, 3, (0, 2, 1))])
+def test_recon_u8_strided_misaligned(rt, oracle, conn, h, w, pad, offs):
+    """uint8 images at odd byte offsets with a pitch above the width, each
+    image ending at the last byte of its buffer: the plain kernel stages rows
+    through aligned dword loads clamped to the bytes of each row."""
+    import torch
+    d = dev()
+    say("recon strided", conn, h, w, pad, offs)
+    J, I, _ = _recon_case(h * 13 + w + pad, h, w, np.uint8, False)
+    pitch = w + pad
+
+    def view(img, off):
+        buf = torch.zeros(off + (h - 1) * pitch + w, dtype=torch.uint8, device=d)
+        v = torch.as_strided(buf, (h, w), (pitch, 1), off)
+        v.copy_(torch.from_numpy(np.ascontiguousarray(img)).to(d))
+        return v
+
+    tJ, tI = view(J, offs[0]), view(I, offs[1])
+    out = view(np.zeros_like(I), offs[2])
+    # the binding needs marker, mask and output to share the pitch only
+    rt.rt_morph_recon(tJ, tI, None, conn, out=out)
+    assert_equal(to_np(out), oracle.recon(J, I, None, conn).astype(np.uint8), f"strided {h}x{w}+{pad} {offs}")
+
+
 def test_recon_in_place(rt, oracle):
     d = dev()
     say("recon in place")
