@@ -349,7 +349,16 @@ __global__ __launch_bounds__(64, PLAIN ? 3 : 1) void k_recon_round(RoundArgs ra)
     const int n_in = ra.first ? ra.total : *cnt_in;
     if (ra.visits && lane == 0 && blockIdx.x == 0) atomicAdd(ra.visits, (unsigned long long)n_in);
     for (int slot = blockIdx.x; slot < n_in; slot += gridDim.x) {
-        const int gtile = ra.first ? slot : ra.list_in[slot];
+        // the first round visits every tile: consecutive workgroups go to the
+        // eight XCDs in turn, so slot s takes a tile of the s % 8-th eighth of
+        // the tile range, and tiles that share halo rows share an L2
+        int gtile;
+        if (ra.first) {
+            const int q = ra.total >> 3, rem = ra.total & 7, x = slot & 7;
+            gtile = x * q + min(x, rem) + (slot >> 3);
+        } else {
+            gtile = ra.list_in[slot];
+        }
         const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
         // every lane calls push; one counter update per wave for its new entries
         auto push = [&](int item, bool valid) {
