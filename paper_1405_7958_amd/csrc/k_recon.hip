@@ -736,31 +736,6 @@ int recon_init(int dtype, const void *marker, const void *mask, void *out, int w
     return hip_fail(hipGetLastError(), "k_recon_init");
 }
 
-// Level choice for the connectivity lower bound: the bound helps most around
-// the density at which the upper level set {v >= l} stops percolating (about
-// 0.41 for 8-connected sites), so the n levels are the smallest values whose
-// upper-set density drops to n targets spread over [0.33, 0.75].
-__device__ void select_levels(const uint32_t *hist, int n_levels, int32_t *levels) {
-    double total = 0;
-    for (int v = 0; v < 256; ++v) total += hist[v];
-    double above = total;  // pixels with value >= v
-    int k = 0;
-    for (int v = 0; v < 256 && k < n_levels; ++v) {
-        for (;;) {
-            if (k >= n_levels) break;
-            const double q = n_levels == 1 ? 0.5 : 0.75 - 0.42 * k / (n_levels - 1);
-            if (above > q * total) break;
-            levels[k++] = v > 0 ? v : 1;
-        }
-        above -= hist[v];
-    }
-    while (k < n_levels) levels[k++] = 255;
-}
-
-// Per-image set-up and tear-down of a batch (one block per image):
-// begin zeroes the Hq histogram and the kept-object counter (block n zeroes
-// the shared counters); levels picks the threshold levels; end copies each
-// image's kept-object count to the caller's counter.
 __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, int n_ctr) {
     const int i = blockIdx.x;
     if (i == n) {
@@ -772,6 +747,11 @@ __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, i
     if (threadIdx.x == 0) *a.kept = 0;
 }
 
+// Level choice for the connectivity lower bound: the bound helps most around
+// the density at which the upper level set {v >= l} stops percolating (about
+// 0.41 for 8-connected sites), so the n levels are the smallest values whose
+// upper-set density drops to n targets spread over [0.33, 0.75].
+//
 // Band selection: v0 = the highest value with at least frac of the pixels at
 // or above it, and the levels v0 - n + 2 .. v0 + 1 (n = 1: v0 alone).  The
 // reconstruction of the frame marker under Hq is the largest value at which
@@ -782,34 +762,65 @@ __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, i
 // above that value make the bound exact on the plateau and on the thin
 // clusters that stay joined to the frame one step higher, which otherwise
 // take the longest propagation.
-__device__ void select_levels_band(const uint32_t *hist, int n_levels, int frac_permille, int32_t *levels) {
-    double total = 0;
-    for (int v = 0; v < 256; ++v) total += hist[v];
-    const double need = total * frac_permille / 1000.0;
-    double above = total;   // pixels with value >= v
-    int v0 = 0;
-    for (int v = 0; v < 256; ++v) {
-        if (above >= need) v0 = v;
-        above -= hist[v];
-    }
-    const int top = n_levels == 1 ? v0 : min(v0 + 1, 255);
-    for (int k = 0; k < n_levels; ++k) levels[k] = max(1, top - (n_levels - 1 - k));
-}
-
-__global__ void k_batch_levels(const BatchAux *aux, int n_levels, int mode, int frac_permille) {
-    __shared__ uint32_t H[256];
+//
+// Threshold levels of the connectivity bound from the Hq histogram, one wave
+// per image: lane t owns bins 4t .. 4t+3 and the counts of pixels at or above
+// each bin come from a suffix sum over the lanes.  Mode 1 (band): v0 is the
+// highest value whose upper set holds at least frac_permille / 1000 of the
+// pixels, and the levels are v0 - n + 2 .. v0 + 1.  Mode 0 (quantiles): level
+// k is the lowest value whose upper set holds at most q_k of the pixels, q_k
+// from 0.75 down to 0.33.
+__global__ __launch_bounds__(64) void k_batch_levels(const BatchAux *aux, int n_levels, int mode, int frac_permille) {
     const BatchAux a = aux[blockIdx.x];
-    for (int v = threadIdx.x; v < 256; v += blockDim.x) {
-        uint32_t s = 0;
-        for (int c = 0; c < HIST_COPIES; ++c) s += a.hist[c * 256 + v];
-        H[v] = s;
+    const int t = threadIdx.x;
+    // the histogram copies sit in the arena (256-byte aligned): 16-byte loads
+    const uint4 *hv = reinterpret_cast<const uint4 *>(a.hist);
+    uint32_t h[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < HIST_COPIES; ++c) {
+        const uint4 q = hv[c * 64 + t];
+        h[0] += q.x;
+        h[1] += q.y;
+        h[2] += q.z;
+        h[3] += q.w;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (mode == 1)
-            select_levels_band(H, n_levels, frac_permille, a.levels);
-        else
-            select_levels(H, n_levels, a.levels);
+    const uint32_t mine = h[0] + h[1] + h[2] + h[3];
+    // inclusive suffix sum over the lanes: lane t gets the pixels of bins >= 4t
+    uint32_t suf = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_down(suf, d, 64);
+        if (t + d < 64) suf += o;
+    }
+    const uint32_t total = __shfl(suf, 0, 64);
+    uint32_t above[4];   // pixels with value >= 4t + j
+    above[0] = suf;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) above[j] = above[j - 1] - h[j - 1];
+    if (mode == 1) {
+        // v0: the highest value whose upper set holds at least frac of the pixels (0 if none)
+        const double need = (double)total * frac_permille / 1000.0;
+        int v0 = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((double)above[j] >= need) v0 = 4 * t + j;
+        for (int d = 32; d > 0; d >>= 1) v0 = max(v0, __shfl_xor(v0, d, 64));
+        if (t == 0) {
+            const int top = n_levels == 1 ? v0 : min(v0 + 1, 255);
+            for (int k = 0; k < n_levels; ++k) a.levels[k] = max(1, top - (n_levels - 1 - k));
+        }
+    } else {
+        // level k: the lowest value whose upper set holds at most q_k of the
+        // pixels, q_k from 0.75 down to 0.33 (255 if none)
+        for (int k = 0; k < n_levels; ++k) {
+            const double q = n_levels == 1 ? 0.5 : 0.75 - 0.42 * k / (n_levels - 1);
+            int v = 256;
+#pragma unroll
+            for (int j = 3; j >= 0; --j)
+                if ((double)above[j] <= q * (double)total) v = 4 * t + j;
+            for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+            if (t == 0) a.levels[k] = v == 256 ? 255 : max(v, 1);
+        }
     }
 }
 
