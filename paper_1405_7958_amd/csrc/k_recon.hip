@@ -875,6 +875,13 @@ int launch_batch_end(const BatchAux *aux, int n, hipStream_t s) {
     return hip_fail(hipGetLastError(), "k_batch_end");
 }
 
+// Start of a reconstruction: no tile stamped, the three list counters zero
+// (one launch for both).
+__global__ void k_recon_reset(uint32_t *stamp, int total, int32_t *cnt) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) stamp[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 3) cnt[threadIdx.x] = 0;
+}
+
 template <typename T, int CONN, bool PLAIN = false>
 static void launch_round(const RoundArgs &ra, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_recon_round<T, CONN, PLAIN>), dim3(grid), dim3(64), 0, s, ra);
@@ -919,9 +926,9 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
     const int grid = std::min(run.total, c->n_cu * 8);
     if (run.total <= 0) return RT_OK;
     if (k0 == 0) {
-        int e = launch_fill_i32((int32_t *)c->stamps, 0, (size_t)run.total, s);
-        if (!e) e = launch_fill_i32(run.cnt, 0, 3, s);
-        if (e) return e;
+        hipLaunchKernelGGL(k_recon_reset, dim3(std::min((run.total + 255) / 256, 1024)), dim3(256), 0, s, c->stamps,
+                           run.total, run.cnt);
+        RT_HIP(hipGetLastError());
     }
     ra.visits = c->prof_on ? c->prof_visits : nullptr;
     hipEvent_t ev_end = nullptr;
