@@ -60,6 +60,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 0
+    return f"{model}, {n} cores available"
+
+
 def tune_cache(args):
     return None if args.tune_cache.lower() == "none" else args.tune_cache
 
@@ -330,7 +348,8 @@ def main():
         c1 = time.perf_counter()
         cpu = {"value": round(1.0 / (c1 - c0), 5), "unit": "tiles/s", "cores": 1, "kind": "oracle",
                "sample": "one full 4096x4096 tile of the same workload (deconvolution + segmentation), "
-                         f"single thread, {c1 - c0:.2f} s"}
+                         f"single thread, {c1 - c0:.2f} s",
+               "host": host_cpu()}
         log(f"oracle: {c1 - c0:.2f} s/tile")
 
     line = {
