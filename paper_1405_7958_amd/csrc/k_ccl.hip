@@ -373,9 +373,12 @@ __device__ void build_rows(const CclArgs &A, const Tile &t, int level, uint64_t 
     __syncthreads();
 }
 
-// Tile forest over runs: after the call, P[slot(y*64+s)] = local root (tile
-// index of a run start) for every run start s of row y.  Lane = row.
-template <typename PT>
+// Tile forest over runs.  Lane = row.  With FLAT, after the call
+// P[slot(y*64+s)] = local root (tile index of a run start) for every run
+// start s of row y; without it the forest is final but not flattened (a root
+// is still its own entry, and lroot walks to it), which is all the local
+// phase needs: it looks up the roots of border runs only.
+template <typename PT, bool FLAT = true>
 __device__ void run_forest(const uint64_t *rows, PT *P, int conn) {
     const int y = lane_id();
     const uint64_t m = rows[y];
@@ -404,16 +407,29 @@ __device__ void run_forest(const uint64_t *rows, PT *P, int conn) {
         }
     }
     __syncthreads();
-    for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        const int li = y * CT + __builtin_ctzll(st);
-        P[slot(li)] = (PT)lfind(P, li);
+    if constexpr (FLAT) {
+        for (uint64_t st = run_starts(m); st; st &= st - 1) {
+            const int li = y * CT + __builtin_ctzll(st);
+            P[slot(li)] = (PT)lfind(P, li);
+        }
+        __syncthreads();
     }
-    __syncthreads();
+}
+
+// Root of run start x in a final forest, read-only; roots may carry tags.
+template <typename PT>
+__device__ __forceinline__ int lroot(const PT *P, int x) {
+    int p = p_load(P, slot(x)) & LIDX;
+    while (p != x) {
+        x = p;
+        p = p_load(P, slot(x)) & LIDX;
+    }
+    return x;
 }
 
 template <typename PT>
 __device__ __forceinline__ int root_of(const uint64_t *rows, const PT *P, int x, int y) {
-    return P[slot(y * CT + run_start_of(rows[y], x))] & LIDX;
+    return lroot(P, y * CT + run_start_of(rows[y], x));
 }
 
 // Tags the roots of components that reach the tile border.  Only those can
@@ -421,17 +437,17 @@ __device__ __forceinline__ int root_of(const uint64_t *rows, const PT *P, int x,
 // the tile border too.  Lane = row.
 template <typename PT>
 __device__ void mark_touch(const Tile &t, const uint64_t *rows, PT *P) {
-    const int y = lane_id();
-    const uint64_t m = rows[y];
-    if (y < t.th && m) {
-        if (y == 0 || y == t.th - 1) {
-            for (uint64_t st = run_starts(m); st; st &= st - 1)
-                p_or(P, slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), TOUCH_BIT);
-        } else {
-            if (m & 1ull) p_or(P, slot(root_of(rows, P, 0, y)), TOUCH_BIT);
-            if ((m >> (t.tw - 1)) & 1ull) p_or(P, slot(root_of(rows, P, t.tw - 1, y)), TOUCH_BIT);
-        }
+    const int lane = lane_id();
+    // left and right columns (lane = row)
+    if (lane < t.th) {
+        const uint64_t m = rows[lane];
+        if (m & 1ull) p_or(P, slot(root_of(rows, P, 0, lane)), TOUCH_BIT);
+        if ((m >> (t.tw - 1)) & 1ull) p_or(P, slot(root_of(rows, P, t.tw - 1, lane)), TOUCH_BIT);
     }
+    // top and bottom rows (lane = column): every run, at its start
+    const int yb = t.th - 1;
+    if ((run_starts(rows[0]) >> lane) & 1ull) p_or(P, slot(lroot(P, lane)), TOUCH_BIT);
+    if (yb > 0 && ((run_starts(rows[yb]) >> lane) & 1ull)) p_or(P, slot(lroot(P, yb * CT + lane)), TOUCH_BIT);
     __syncthreads();
 }
 
@@ -457,22 +473,25 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
     uint64_t *rows = ccl_smem;
     uint16_t *P = (uint16_t *)(ccl_smem + CT);
     build_rows<PR>(A, t, wave_level<PR>(A, wave), rows);
-    run_forest(rows, P, A.conn);
+    // the level sets hold many small components (short chains to walk), the
+    // other sets few large ones, where one flattening pass beats long walks
+    run_forest<uint16_t, PR != CclPred::Level>(rows, P, A.conn);
     mark_touch(t, rows, P);
     const int y = lane;
     const uint64_t m = rows[y];
     const bool tile_on_frame = t.x0 == 0 || t.y0 == 0 || t.x0 + t.tw == A.w || t.y0 + t.th == A.h;
     if (A.frame_virtual && tile_on_frame) {
-        if (y < t.th && m) {
-            if (t.y0 + y == 0 || t.y0 + y == A.h - 1) {
-                for (uint64_t st = run_starts(m); st; st &= st - 1)
-                    p_or(P, slot(P[slot(y * CT + __builtin_ctzll(st))] & LIDX), FRAME_BIT);
-            } else {
-                if (t.x0 == 0 && (m & 1ull)) p_or(P, slot(root_of(rows, P, 0, y)), FRAME_BIT);
-                if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
-                    p_or(P, slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
-            }
+        // frame columns (lane = row)
+        if (y < t.th) {
+            if (t.x0 == 0 && (m & 1ull)) p_or(P, slot(root_of(rows, P, 0, y)), FRAME_BIT);
+            if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
+                p_or(P, slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
         }
+        // frame rows (lane = column): every run, at its start
+        const int yb = t.th - 1;
+        if (t.y0 == 0 && ((run_starts(rows[0]) >> lane) & 1ull)) p_or(P, slot(lroot(P, lane)), FRAME_BIT);
+        if (t.y0 + t.th == A.h && ((run_starts(rows[yb]) >> lane) & 1ull))
+            p_or(P, slot(lroot(P, yb * CT + lane)), FRAME_BIT);
         __syncthreads();
     }
     if (!live) return;
