@@ -46,7 +46,7 @@ extern "C" {
 #define RT_EINVAL (-1)       /* bad argument: null pointer, w/h <= 0, pitch < w, too many pixels, bad conn/dtype, min > max */
 #define RT_ENOMEM (-2)       /* scratch allocation failed */
 #define RT_EDEVICE (-3)      /* HIP runtime error */
-#define RT_EUNSUPPORTED (-4) /* valid request this build does not implement */
+#define RT_EUNSUPPORTED (-4) /* valid request the library does not implement */
 
 #define RT_U8 1
 #define RT_I32 2
