@@ -495,15 +495,15 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
         __syncthreads();
     }
     if (!live) return;
-    // roots (lane = row)
-    for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        const int s = __builtin_ctzll(st);
-        const int li = y * CT + s;
-        const int pv = P[slot(li)];
-        if ((pv & LIDX) != li) continue;
-        const int id = gid(A, t, s, y);
-        if (pv & TOUCH_BIT) ids[id] = (pv & FRAME_BIT) ? 0 : id;
-        if constexpr (OU == CclOut::Labels) {
+    if constexpr (OU == CclOut::Labels) {
+        // roots (lane = row): publish the touching ones, reset the statistics of all
+        for (uint64_t st = run_starts(m); st; st &= st - 1) {
+            const int s = __builtin_ctzll(st);
+            const int li = y * CT + s;
+            const int pv = P[slot(li)];
+            if ((pv & LIDX) != li) continue;
+            const int id = gid(A, t, s, y);
+            if (pv & TOUCH_BIT) ids[id] = (pv & FRAME_BIT) ? 0 : id;
             if (A.st_area) {
                 A.st_area[id] = 0;
                 A.st_x0[id] = 0x7fffffff;
@@ -512,6 +512,21 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
                 A.st_y1[id] = -1;
             }
         }
+    } else {
+        // only the touching roots matter, and each is the root of a border
+        // run: publish them from the border runs (the same value may be
+        // written more than once)
+        auto publish = [&](int r) {
+            const int id = gid(A, t, r & (CT - 1), r >> 6);
+            ids[id] = (p_load(P, slot(r)) & FRAME_BIT) ? 0 : id;
+        };
+        if (y < t.th) {
+            if (m & 1ull) publish(root_of(rows, P, 0, y));
+            if ((m >> (t.tw - 1)) & 1ull) publish(root_of(rows, P, t.tw - 1, y));
+        }
+        const int yb = t.th - 1;
+        if ((run_starts(rows[0]) >> lane) & 1ull) publish(lroot(P, lane));
+        if (yb > 0 && ((run_starts(rows[yb]) >> lane) & 1ull)) publish(lroot(P, yb * CT + lane));
     }
     // edge pixels that are not roots: left / right columns (lane = row)
     if (m & 1ull) {
