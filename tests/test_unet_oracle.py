@@ -183,3 +183,54 @@ def test_adam_first_step_closed_form():
     # first bias-corrected step: m_hat = g, v_hat = g^2 -> update lr * g / (|g| + eps)
     exp = np.array([1.0, -2.0, 3.0]) - 0.01 * G["a"] / (np.abs(G["a"]) + 1e-8)
     np.testing.assert_allclose(P["a"], exp, rtol=1e-14)
+
+
+def test_adam_constant_gradient_every_step():
+    # with g constant, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    # bias-corrected step is lr * g / (|g| + eps) at every t: pins both
+    # corrections (a missing or wrong power of beta shows from t = 2 on)
+    g = np.array([0.5, -4.0, 1e-3, 7.0])
+    P = {"a": np.zeros(4)}
+    M = {"a": np.zeros(4)}
+    V = {"a": np.zeros(4)}
+    step = 0.01 * g / (np.abs(g) + 1e-8)
+    for t in range(1, 51):
+        before = P["a"].copy()
+        U.adam_step(P, {"a": g}, M, V, t, lr=0.01)
+        np.testing.assert_allclose(before - P["a"], step, rtol=1e-9, atol=1e-15)
+
+
+def test_adam_two_steps_by_hand():
+    # g1 = 1, g2 = -3, p0 = 0.5, lr = 0.1, betas (0.9, 0.999), eps 1e-8, worked
+    # out by hand in 40-digit decimal arithmetic:
+    #   t=1: m = 0.1, v = 0.001, m^ = 1, v^ = 1, p = 0.5 - 0.1 / (1 + 1e-8)
+    #   t=2: m = 0.09 - 0.3 = -0.21, v = 0.000999 + 0.009 = 0.009999,
+    #        m^ = -0.21 / 0.19, v^ = 0.009999 / 0.001999,
+    #        p = p1 - 0.1 * m^ / (sqrt(v^) + 1e-8)
+    P = {"a": np.array([0.5])}
+    M = {"a": np.zeros(1)}
+    V = {"a": np.zeros(1)}
+    U.adam_step(P, {"a": np.array([1.0])}, M, V, 1, lr=0.1)
+    assert abs(P["a"][0] - 0.40000000099999999) < 1e-15
+    U.adam_step(P, {"a": np.array([-3.0])}, M, V, 2, lr=0.1)
+    assert abs(M["a"][0] - (-0.21)) < 1e-15 and abs(V["a"][0] - 0.009999) < 1e-16
+    assert abs(P["a"][0] - 0.44941898410874449) < 1e-14
+
+
+def test_adam_scale_and_sign_symmetry():
+    # with eps negligible the update depends on the gradient history only
+    # through m / sqrt(v): scaling every gradient by c > 0 leaves it unchanged,
+    # flipping every sign flips it
+    r = np.random.Generator(np.random.PCG64(11))
+    gs = [r.standard_normal(6) for _ in range(5)]
+
+    def run(scale):
+        P = {"a": np.zeros(6)}
+        M = {"a": np.zeros(6)}
+        V = {"a": np.zeros(6)}
+        for t, g in enumerate(gs, 1):
+            U.adam_step(P, {"a": g * scale}, M, V, t, lr=0.01, eps=0.0)
+        return P["a"]
+
+    np.testing.assert_allclose(run(1.0), run(37.0), rtol=1e-12)
+    np.testing.assert_allclose(run(1.0), -run(-1.0), rtol=1e-12)
