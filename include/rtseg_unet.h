@@ -68,6 +68,16 @@ int rt_unet_grad_step(rt_unet *net, const uint8_t *rgb, const uint8_t *fg_tgt, c
                       int32_t h, int32_t w, float w_seed, float *loss_dev, void *stream);
 int rt_unet_train_step(rt_unet *net, const uint8_t *rgb, const uint8_t *fg_tgt, const uint8_t *seed_tgt, int32_t b,
                        int32_t h, int32_t w, float lr, float w_seed, float *loss_dev, void *stream);
+/*
+ * One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected with the step number t, which this call increments) on the FP32
+ * master weights from the accumulated gradient, which it then clears, and a
+ * repack of the bf16 operand copies: gradient accumulation over several
+ * rt_unet_grad_step calls followed by one update.  Asynchronous on `stream`.
+ * rt_unet_get_step returns t (0 after create or set_params).
+ */
+int rt_unet_adam_step(rt_unet *net, float lr, void *stream);
+int rt_unet_get_step(rt_unet *net, int64_t *step);
 
 /*
  * Tile inference: 512 x 512 windows at stride 480 (the last window flush with
@@ -84,6 +94,13 @@ int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t
 /* Parameter file: 8 magic bytes "RTUNET01", int64 count, count float32. */
 int rt_unet_save(rt_unet *net, const char *path);
 int rt_unet_load(rt_unet *net, const char *path);
+/* Training checkpoint, for resuming: 8 magic bytes "RTUNETC1", int64 count,
+ * int64 step t, then count float32 each of the master weights, the gradient
+ * accumulator, Adam's first and second moments.  Loading restores all of it
+ * (and repacks the bf16 operand copies).  Both synchronise the device.
+ * Errors: RT_EINVAL for a file that is not a checkpoint of this network. */
+int rt_unet_save_checkpoint(rt_unet *net, const char *path);
+int rt_unet_load_checkpoint(rt_unet *net, const char *path);
 
 /*
  * Segmentation stage with the surrogate: fg = [p_fg >= 0.5], seeds =

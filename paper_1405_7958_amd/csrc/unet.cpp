@@ -462,14 +462,33 @@ int rt_unet_grad_step(rt_unet *net, const uint8_t *rgb, const uint8_t *fg_tgt, c
     return RT_OK;
 }
 
+int rt_unet_adam_step(rt_unet *net, float lr, void *stream) {
+    if (!net || !std::isfinite(lr)) {
+        set_error("rt_unet_adam_step: bad arguments");
+        return RT_EINVAL;
+    }
+    RT_HIP(hipSetDevice(net->device));
+    hipStream_t s = (hipStream_t)stream;
+    net->step++;
+    int e = nn_adam(net->P, net->G, net->M, net->V, net->np, lr, 0.9f, 0.999f, 1e-8f, net->step, s);
+    if (e) return e;
+    return pack_all(net, s);
+}
+
 int rt_unet_train_step(rt_unet *net, const uint8_t *rgb, const uint8_t *fg_tgt, const uint8_t *seed_tgt, int32_t b,
                        int32_t h, int32_t w, float lr, float w_seed, float *loss_dev, void *stream) {
     int e = rt_unet_grad_step(net, rgb, fg_tgt, seed_tgt, b, h, w, w_seed, loss_dev, stream);
     if (e) return e;
-    hipStream_t s = (hipStream_t)stream;
-    net->step++;
-    if ((e = nn_adam(net->P, net->G, net->M, net->V, net->np, lr, 0.9f, 0.999f, 1e-8f, net->step, s))) return e;
-    return pack_all(net, s);
+    return rt_unet_adam_step(net, lr, stream);
+}
+
+int rt_unet_get_step(rt_unet *net, int64_t *step) {
+    if (!net || !step) {
+        set_error("rt_unet_get_step: null argument");
+        return RT_EINVAL;
+    }
+    *step = net->step;
+    return RT_OK;
 }
 
 int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h, float *fg_prob,
@@ -603,6 +622,70 @@ int rt_unet_load(rt_unet *net, const char *path) {
         return RT_EINVAL;
     }
     return rt_unet_set_params(net, h.data(), net->np);
+}
+
+// Training checkpoint: 8 magic bytes "RTUNETC1", int64 count, int64 step,
+// then count float32 each of the master weights, the gradient accumulator and
+// the two Adam moments.
+int rt_unet_save_checkpoint(rt_unet *net, const char *path) {
+    if (!net || !path) {
+        set_error("rt_unet_save_checkpoint: null argument");
+        return RT_EINVAL;
+    }
+    RT_HIP(hipSetDevice(net->device));
+    RT_HIP(hipDeviceSynchronize());
+    const int64_t n = net->np, step = net->step;
+    std::vector<float> h((size_t)n * 4);
+    const float *src[4] = {net->P, net->G, net->M, net->V};
+    for (int k = 0; k < 4; ++k)
+        RT_HIP(hipMemcpy(h.data() + (size_t)k * n, src[k], sizeof(float) * n, hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error("rt_unet_save_checkpoint: cannot open %s", path);
+        return RT_EINVAL;
+    }
+    const char magic[8] = {'R', 'T', 'U', 'N', 'E', 'T', 'C', '1'};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&n, sizeof n, 1, f) == 1 &&
+              std::fwrite(&step, sizeof step, 1, f) == 1 && std::fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) {
+        set_error("rt_unet_save_checkpoint: write to %s failed", path);
+        return RT_EDEVICE;
+    }
+    return RT_OK;
+}
+
+int rt_unet_load_checkpoint(rt_unet *net, const char *path) {
+    if (!net || !path) {
+        set_error("rt_unet_load_checkpoint: null argument");
+        return RT_EINVAL;
+    }
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error("rt_unet_load_checkpoint: cannot open %s", path);
+        return RT_EINVAL;
+    }
+    char magic[8];
+    int64_t n = 0, step = 0;
+    std::vector<float> h((size_t)net->np * 4);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && !std::memcmp(magic, "RTUNETC1", 8) &&
+              std::fread(&n, sizeof n, 1, f) == 1 && n == net->np && std::fread(&step, sizeof step, 1, f) == 1 &&
+              step >= 0 && std::fread(h.data(), sizeof(float), h.size(), f) == h.size();
+    std::fclose(f);
+    if (!ok) {
+        set_error("rt_unet_load_checkpoint: %s is not a checkpoint of this network", path);
+        return RT_EINVAL;
+    }
+    RT_HIP(hipSetDevice(net->device));
+    RT_HIP(hipDeviceSynchronize());
+    float *dst[4] = {net->P, net->G, net->M, net->V};
+    for (int k = 0; k < 4; ++k)
+        RT_HIP(hipMemcpy(dst[k], h.data() + (size_t)k * n, sizeof(float) * n, hipMemcpyHostToDevice));
+    net->step = (int)step;
+    int e = pack_all(net, nullptr);
+    if (e) return e;
+    RT_HIP(hipDeviceSynchronize());
+    return RT_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -86,6 +86,10 @@ def lib():
         L.rt_unet_forward.argtypes = [vp, vp, i64, i32, i32, vp, vp, i64, vp]
         L.rt_unet_save.argtypes = [vp, C.c_char_p]
         L.rt_unet_load.argtypes = [vp, C.c_char_p]
+        L.rt_unet_adam_step.argtypes = [vp, f32, vp]
+        L.rt_unet_get_step.argtypes = [vp, C.POINTER(i64)]
+        L.rt_unet_save_checkpoint.argtypes = [vp, C.c_char_p]
+        L.rt_unet_load_checkpoint.argtypes = [vp, C.c_char_p]
         L.rt_segment_tile_surrogate.argtypes = [vp, vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), f32, vp, vp,
                                                 i64, vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), vp]
         L.rt_nn_conv3_fwd.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, vp, vp, i32, i32, vp, vp, vp]
@@ -433,6 +437,22 @@ class UNet:
                                         _ptr(loss), _stream()))
         return loss
 
+    def adam_step(self, lr=1e-3):
+        """One Adam update from the accumulated gradient (then cleared)."""
+        _check(lib().rt_unet_adam_step(self.h, float(lr), _stream()))
+
+    @property
+    def step(self):
+        t = C.c_int64(0)
+        _check(lib().rt_unet_get_step(self.h, C.byref(t)))
+        return int(t.value)
+
+    def save_checkpoint(self, path):
+        _check(lib().rt_unet_save_checkpoint(self.h, os.fsencode(path)))
+
+    def load_checkpoint(self, path):
+        _check(lib().rt_unet_load_checkpoint(self.h, os.fsencode(path)))
+
     def forward(self, rgb):
         """(H, W, 3) uint8 tile -> (p_fg, p_seed) float32 maps."""
         _img(rgb, torch.uint8, "rgb", 3)
@@ -474,15 +494,17 @@ def _u16(t, name):
     return t
 
 
-def nn_conv3_fwd(x0, wf, bias, co, relu=False, x1=None, ctx=None):
-    """x0 (n, h, w, c0) [and x1 (n, h, w, c1)] bf16 -> y float32 (n, h, w, co)."""
+def nn_conv3_fwd(x0, wf, bias, co, relu=False, x1=None, want_bf16=False, ctx=None):
+    """x0 (n, h, w, c0) [and x1 (n, h, w, c1)] bf16 -> y float32 (n, h, w, co)
+    [and, with want_bf16, the same output rounded to bf16 by the kernel]."""
     ctx = ctx or default_context()
     n, h, w, c0 = x0.shape
     c1 = x1.shape[3] if x1 is not None else 0
     y = torch.empty((n, h, w, co), dtype=torch.float32, device=x0.device)
+    yb = torch.empty((n, h, w, co), dtype=torch.int16, device=x0.device) if want_bf16 else None
     _check(lib().rt_nn_conv3_fwd(ctx.h, _ptr(_u16(x0, "x0")), c0, _ptr(x1), c1, n, h, w, _ptr(_u16(wf, "wf")),
-                                 _ptr(bias), co, 1 if relu else 0, _ptr(y), None, _stream()))
-    return y
+                                 _ptr(bias), co, 1 if relu else 0, _ptr(y), _ptr(yb), _stream()))
+    return (y, yb) if want_bf16 else y
 
 
 def nn_conv3_dgrad(g, wt, ci, c0=None, ctx=None):
@@ -508,13 +530,14 @@ def nn_conv3_wgrad(x0, g, x1=None, ctx=None):
     return dw, db
 
 
-def nn_up2_fwd(x, uf, bias, co, ctx=None):
+def nn_up2_fwd(x, uf, bias, co, want_bf16=False, ctx=None):
     ctx = ctx or default_context()
     n, h, w, ci = x.shape
     y = torch.empty((n, 2 * h, 2 * w, co), dtype=torch.float32, device=x.device)
+    yb = torch.empty((n, 2 * h, 2 * w, co), dtype=torch.int16, device=x.device) if want_bf16 else None
     _check(lib().rt_nn_up2_fwd(ctx.h, _ptr(_u16(x, "x")), ci, n, h, w, _ptr(_u16(uf, "uf")), _ptr(bias), co, _ptr(y),
-                               None, _stream()))
-    return y
+                               _ptr(yb), _stream()))
+    return (y, yb) if want_bf16 else y
 
 
 def nn_up2_bwd(x, g, ut, ctx=None):
@@ -583,6 +606,7 @@ EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_de
            "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds",
            "rt_profile_stage_name", "rt_unet_param_count", "rt_unet_create", "rt_unet_destroy", "rt_unet_get_params",
            "rt_unet_set_params", "rt_unet_get_grads", "rt_unet_grad_step", "rt_unet_train_step", "rt_unet_forward",
-           "rt_unet_save", "rt_unet_load", "rt_segment_tile_surrogate", "rt_nn_conv3_fwd", "rt_nn_conv3_dgrad",
+           "rt_unet_save", "rt_unet_load", "rt_unet_adam_step", "rt_unet_get_step", "rt_unet_save_checkpoint",
+           "rt_unet_load_checkpoint", "rt_segment_tile_surrogate", "rt_nn_conv3_fwd", "rt_nn_conv3_dgrad",
            "rt_nn_conv3_wgrad", "rt_nn_up2_fwd", "rt_nn_up2_bwd", "rt_nn_pool2", "rt_nn_head_loss", "rt_nn_pack",
            "rt_nn_prep_input")
