@@ -15,6 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "rt_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "features_oracle.c")]
 
 DQ_MAX = 65535
 
@@ -29,19 +30,42 @@ DEFAULTS = dict(scale=85.0, t_fg=16, min_area=20, max_area=1000, h_seed=3)
 
 def build(force: bool = False) -> str:
     """Compiles the oracle with gcc (plain -O2, no FP contraction)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", _SO, _SRC, "-lm"])
+    newest = max(os.path.getmtime(p) for p in _SRCS + [os.path.join(_HERE, "rt_oracle.h")])
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", _SO, *_SRCS, "-lm"])
     return _SO
 
 
+def build_native(outdir: str) -> str:
+    """Compiles the same source for timing on this host: -O3 -march=native,
+    still without FP contraction (so the arithmetic is unchanged).  Built
+    where it runs, never shipped: -march=native is only valid on this CPU."""
+    so = os.path.join(outdir, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fPIC", "-shared", "-o", so, *_SRCS,
+                           "-lm"])
+    return so
+
+
 _lib = None
+_so_override = None
+
+
+def use_library(path: str) -> None:
+    """Makes later calls load `path` (a build of rt_oracle.c) instead of the default build."""
+    global _lib, _so_override
+    _lib = None
+    _so_override = path
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_SO)
+        if _so_override:
+            so = _so_override
+        else:
+            build()
+            so = _SO
+        L = C.CDLL(so)
         u8p = C.POINTER(C.c_uint8)
         i32p = C.POINTER(C.c_int32)
         i64p = C.POINTER(C.c_int64)
@@ -59,6 +83,9 @@ def lib():
         L.or_watershed.argtypes = [u8p, u8p, C.c_int, C.c_int, C.c_int, i32p, u8p, i32p, i32p, i32p, i32p]
         L.or_segment_from_hq.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          u8p, i32p, u8p, u8p, u8p, u8p]
+        L.or_sobel_mag.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.or_sobel_mag.restype = C.c_int64
+        L.or_features.argtypes = [i32p, u8p, C.c_int, C.c_int, C.c_int, i32p, f64p, i64p]
         _lib = L
     return _lib
 
@@ -201,3 +228,47 @@ def segment_rgb(rgb, stain=STAIN_HE, scale=85.0, **kw):
     hq = deconv(rgb, stain, scale)
     mask, lab, n = segment_from_hq(hq, **kw)
     return hq, mask, lab, n
+
+
+# feature computation (rt_oracle.h): names in output order
+FEATURE_NAMES = (
+    "area", "perimeter", "centroid_x", "centroid_y", "bbox_w", "bbox_h", "extent", "equiv_diameter",
+    "circularity", "major_axis", "minor_axis", "eccentricity", "orientation",
+    "int_mean", "int_std", "int_min", "int_max", "int_median", "int_p25", "int_p75", "int_skewness",
+    "int_kurtosis", "int_entropy", "int_energy", "int_range",
+    "grad_mean", "grad_std", "grad_max", "grad_entropy", "grad_energy", "edge_fraction",
+    "glcm_asm", "glcm_contrast", "glcm_correlation", "glcm_variance", "glcm_homogeneity",
+    "glcm_sum_average", "glcm_sum_variance", "glcm_sum_entropy", "glcm_entropy", "glcm_diff_variance",
+    "glcm_diff_entropy", "glcm_imc1", "glcm_imc2", "glcm_max_prob", "glcm_cluster_shade",
+    "glcm_cluster_prominence")
+NFEAT = len(FEATURE_NAMES)
+NCOUNT = 537
+GLCM_LEVELS = 16
+GRAD_BINS = 16
+GRAD_BIN_WIDTH = 32
+EDGE_THRESHOLD = 128
+
+
+def sobel_mag(hq, x, y):
+    q = _u8(hq)
+    h, w = q.shape
+    return int(lib().or_sobel_mag(_p(q, C.c_uint8), w, h, int(x), int(y)))
+
+
+def features(labels, hq, want_counts=False):
+    """Per-nucleus features.  Returns (labels [n] int32, feats [n, NFEAT]
+    float64) and, with want_counts, the counts [n, NCOUNT] int64."""
+    lab = _i32(labels)
+    q = _u8(hq)
+    h, w = lab.shape
+    # the number of nuclei is at most the number of distinct positive labels
+    cap = max(1, int(np.unique(lab[lab > 0]).size))
+    lo = np.empty(cap, np.int32)
+    fo = np.empty((cap, NFEAT), np.float64)
+    co = np.empty((cap, NCOUNT), np.int64) if want_counts else None
+    n = lib().or_features(_p(lab, C.c_int32), _p(q, C.c_uint8), w, h, cap, _p(lo, C.c_int32), _p(fo, C.c_double),
+                          _p(co, C.c_int64))
+    n = min(n, cap)
+    if want_counts:
+        return lo[:n], fo[:n], co[:n]
+    return lo[:n], fo[:n]

@@ -108,6 +108,93 @@ int or_segment_from_hq(const uint8_t *hq, int w, int h, int t_fg, int min_area, 
                        int h_seed, uint8_t *mask_out, int32_t *labels_out,
                        uint8_t *recon_out, uint8_t *f0_out, uint8_t *f_out, uint8_t *a_out);
 
+/* ------------------------------------------------------------------------
+ * Feature computation (Sec. 5.1: shape and texture features per segmented
+ * nucleus from per-nucleus histograms and co-occurrence matrices; Fig. 1:
+ * 60-100 shape and texture features per object).  The paper lists no
+ * feature; the set below is the reading, each from its textbook definition.
+ *
+ * Input: labels (int32, 0 = background, a nucleus = all pixels sharing one
+ * positive label, label values <= w*h; labels as produced by the segmentation
+ * are 1 + the row-major index of the nucleus' first pixel) and Hq (uint8).
+ * Nuclei are reported in order of their first pixel in row-major order (for
+ * such labels: increasing label).
+ *
+ * Per-nucleus counts (exact integers):
+ *   area, bounding box, coordinate sums (x, y, x^2, y^2, xy);
+ *   perimeter = number of pixel sides (4-neighbours) of the nucleus that face
+ *     a pixel of another label or the outside of the tile;
+ *   hist[v] = pixels with Hq = v;
+ *   gradient magnitude g = floor(sqrt(gx^2 + gy^2)) of the 3x3 Sobel operator
+ *     on Hq, pixels outside the tile replicating the nearest edge pixel;
+ *     ghist[b] = pixels with min(g / OR_GRAD_BIN_WIDTH, OR_GRAD_BINS - 1) = b;
+ *     sum g, sum g^2, max g;
+ *   co-occurrence matrix C of Hq quantised to OR_GLCM_LEVELS levels
+ *     (q = Hq / (256 / levels)) over the offsets (1,0), (1,1), (0,1), (-1,1)
+ *     (0, 45, 90, 135 degrees, distance 1), pooled: every pair of pixels of
+ *     the same nucleus at one of these offsets adds 1 to C[q1][q2] and 1 to
+ *     C[q2][q1].
+ * Features (FP64), in this order:
+ *   shape: area; perimeter; centroid x, y; bbox width, height; extent =
+ *     area / bbox area; equivalent diameter sqrt(4 area / pi); circularity
+ *     4 pi area / perimeter^2; major and minor axis 4 sqrt(l1), 4 sqrt(l2) and
+ *     eccentricity sqrt(1 - l2 / l1) with l1 >= l2 the eigenvalues of the
+ *     second central moments (mu20, mu11; mu11, mu02) of the pixel set, each
+ *     pixel a unit square (1/12 added to mu20 and mu02), mu20 =
+ *     (A sum x^2 - (sum x)^2) / A^2 etc.; orientation 0.5 atan2(2 mu11,
+ *     mu20 - mu02) (radians, y down);
+ *   intensity of Hq: mean; standard deviation (population); min; max; median,
+ *     25th and 75th percentile = the sorted values at 0-based ranks
+ *     floor((A-1)/2), floor((A-1)/4), floor(3(A-1)/4); skewness m3 / m2^1.5
+ *     and kurtosis m4 / m2^2 (central moments, 0 when m2 = 0); entropy
+ *     -sum p log2 p and energy sum p^2 of the histogram; range max - min;
+ *   gradient: mean g; standard deviation sqrt(A sum g^2 - (sum g)^2) / A;
+ *     max g; entropy and energy of ghist; edge fraction = share of pixels with
+ *     g >= OR_EDGE_THRESHOLD;
+ *   Haralick texture of p = C / sum C (all 0 when sum C = 0), px its
+ *     marginal (equal for rows and columns: C is symmetric), mu = sum i px(i),
+ *     var = sum (i - mu)^2 px(i), p_{x+y}(k) and p_{x-y}(k) the sums of p over
+ *     i + j = k and |i - j| = k: angular second moment sum p^2; contrast
+ *     sum (i-j)^2 p; correlation sum (i-mu)(j-mu) p / var (1 when var = 0);
+ *     variance var; homogeneity sum p / (1 + (i-j)^2); sum average
+ *     sum k p_{x+y}; sum variance sum (k - sum average)^2 p_{x+y}; sum entropy;
+ *     entropy -sum p log2 p; difference variance (about the mean of
+ *     p_{x-y}); difference entropy; information measures of correlation
+ *     IMC1 = (HXY - HXY1) / HX (0 when HX = 0) and IMC2 =
+ *     sqrt(1 - exp(-2 max(HXY2 - HXY, 0))) with HX = -sum px log2 px,
+ *     HXY1 = -sum p log2(px(i) px(j)), HXY2 = -sum px(i)px(j) log2(px(i)px(j));
+ *     maximum probability; cluster shade sum (i + j - 2 mu)^3 p and cluster
+ *     prominence sum (i + j - 2 mu)^4 p.
+ * ------------------------------------------------------------------------ */
+#define OR_GLCM_LEVELS 16
+#define OR_GRAD_BINS 16
+#define OR_GRAD_BIN_WIDTH 32
+#define OR_EDGE_THRESHOLD 128
+enum {
+    OF_AREA, OF_PERIMETER, OF_CENTROID_X, OF_CENTROID_Y, OF_BBOX_W, OF_BBOX_H, OF_EXTENT, OF_EQUIV_DIAMETER,
+    OF_CIRCULARITY, OF_MAJOR_AXIS, OF_MINOR_AXIS, OF_ECCENTRICITY, OF_ORIENTATION,
+    OF_INT_MEAN, OF_INT_STD, OF_INT_MIN, OF_INT_MAX, OF_INT_MEDIAN, OF_INT_P25, OF_INT_P75, OF_INT_SKEWNESS,
+    OF_INT_KURTOSIS, OF_INT_ENTROPY, OF_INT_ENERGY, OF_INT_RANGE,
+    OF_GRAD_MEAN, OF_GRAD_STD, OF_GRAD_MAX, OF_GRAD_ENTROPY, OF_GRAD_ENERGY, OF_EDGE_FRACTION,
+    OF_GLCM_ASM, OF_GLCM_CONTRAST, OF_GLCM_CORRELATION, OF_GLCM_VARIANCE, OF_GLCM_HOMOGENEITY,
+    OF_GLCM_SUM_AVERAGE, OF_GLCM_SUM_VARIANCE, OF_GLCM_SUM_ENTROPY, OF_GLCM_ENTROPY, OF_GLCM_DIFF_VARIANCE,
+    OF_GLCM_DIFF_ENTROPY, OF_GLCM_IMC1, OF_GLCM_IMC2, OF_GLCM_MAX_PROB, OF_GLCM_CLUSTER_SHADE,
+    OF_GLCM_CLUSTER_PROMINENCE,
+    OR_NFEAT
+};
+/* counts per nucleus: area, perimeter, x0, y0, x1, y1, hist[256], C[16][16]
+   (row-major), ghist[16], sum g, sum g^2, max g */
+#define OR_NCOUNT 537
+
+/* Gradient magnitude of the feature stage at (x, y). */
+int64_t or_sobel_mag(const uint8_t *hq, int w, int h, int x, int y);
+
+/* Features of every nucleus (see above): labels_out[k], feats_out[k*OR_NFEAT +
+ * i] for the first min(n, max_nuclei) nuclei; counts_out (nullable) receives
+ * OR_NCOUNT counts per nucleus.  Returns the number of nuclei n. */
+int or_features(const int32_t *labels, const uint8_t *hq, int w, int h, int max_nuclei, int32_t *labels_out,
+                double *feats_out, int64_t *counts_out);
+
 #ifdef __cplusplus
 }
 #endif
