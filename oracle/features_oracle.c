@@ -21,7 +21,8 @@ typedef struct {
     int32_t label;
     int64_t area, perim;
     int32_t x0, y0, x1, y1;
-    int64_t sx, sy, sxx, syy, sxy;      /* coordinate sums (tile coordinates) */
+    int32_t xr, yr;                     /* the first pixel (row-major) */
+    int64_t sx, sy, sxx, syy, sxy;      /* sums of coordinates relative to the first pixel */
     int64_t hist[256];                  /* Hq histogram */
     int64_t ghist[OR_GRAD_BINS];        /* Sobel magnitude histogram */
     int64_t gsum, gsum2, gmax;
@@ -75,8 +76,8 @@ static void features_of(const nuc_acc *n, double *f) {
     /* ---- shape */
     f[OF_AREA] = A;
     f[OF_PERIMETER] = (double)n->perim;
-    f[OF_CENTROID_X] = (double)n->sx / A;
-    f[OF_CENTROID_Y] = (double)n->sy / A;
+    f[OF_CENTROID_X] = n->xr + (double)n->sx / A;
+    f[OF_CENTROID_Y] = n->yr + (double)n->sy / A;
     const double bw = n->x1 - n->x0 + 1, bh = n->y1 - n->y0 + 1;
     f[OF_BBOX_W] = bw;
     f[OF_BBOX_H] = bh;
@@ -85,12 +86,14 @@ static void features_of(const nuc_acc *n, double *f) {
     f[OF_CIRCULARITY] = 4.0 * PI * A / ((double)n->perim * (double)n->perim);
     /* second central moments of the pixel set, each pixel a unit square
        (variance 1/12 along each axis added) */
-    const int64_t c20 = n->area * n->sxx - n->sx * n->sx;
-    const int64_t c02 = n->area * n->syy - n->sy * n->sy;
-    const int64_t c11 = n->area * n->sxy - n->sx * n->sy;
-    const double m20 = (double)c20 / (A * A) + 1.0 / 12.0;
-    const double m02 = (double)c02 / (A * A) + 1.0 / 12.0;
-    const double m11 = (double)c11 / (A * A);
+    /* A^2 mu = A sum x^2 - (sum x)^2, exact in 128-bit integers */
+    const __int128 c20 = (__int128)n->area * n->sxx - (__int128)n->sx * n->sx;
+    const __int128 c02 = (__int128)n->area * n->syy - (__int128)n->sy * n->sy;
+    const __int128 c11 = (__int128)n->area * n->sxy - (__int128)n->sx * n->sy;
+    const double AA = (double)(n->area * n->area);
+    const double m20 = (double)c20 / AA + 1.0 / 12.0;
+    const double m02 = (double)c02 / AA + 1.0 / 12.0;
+    const double m11 = (double)c11 / AA;
     const double tr = m20 + m02;
     const double disc = sqrt((m20 - m02) * (m20 - m02) + 4.0 * m11 * m11);
     const double l1 = (tr + disc) / 2.0, l2 = (tr - disc) / 2.0;
@@ -133,7 +136,7 @@ static void features_of(const nuc_acc *n, double *f) {
     f[OF_INT_RANGE] = vmax - vmin;
     /* ---- gradient magnitude over the nucleus */
     f[OF_GRAD_MEAN] = (double)n->gsum / A;
-    f[OF_GRAD_STD] = sqrt((double)(n->area * n->gsum2 - n->gsum * n->gsum)) / A;
+    f[OF_GRAD_STD] = sqrt((double)((__int128)n->area * n->gsum2 - (__int128)n->gsum * n->gsum)) / A;
     f[OF_GRAD_MAX] = (double)n->gmax;
     double gent = 0.0, gen = 0.0;
     int64_t edge = 0;
@@ -247,8 +250,8 @@ int or_features(const int32_t *labels, const uint8_t *hq, int w, int h, int max_
                 }
                 memset(&acc[n], 0, sizeof(nuc_acc));
                 acc[n].label = L;
-                acc[n].x0 = acc[n].x1 = x;
-                acc[n].y0 = acc[n].y1 = y;
+                acc[n].x0 = acc[n].x1 = acc[n].xr = x;
+                acc[n].y0 = acc[n].y1 = acc[n].yr = y;
                 idx[L] = n++;
             }
             nuc_acc *a = &acc[idx[L]];
@@ -256,11 +259,12 @@ int or_features(const int32_t *labels, const uint8_t *hq, int w, int h, int max_
             if (x < a->x0) a->x0 = x;
             if (x > a->x1) a->x1 = x;
             if (y > a->y1) a->y1 = y;
-            a->sx += x;
-            a->sy += y;
-            a->sxx += (int64_t)x * x;
-            a->syy += (int64_t)y * y;
-            a->sxy += (int64_t)x * y;
+            const int64_t dx = x - a->xr, dy = y - a->yr;
+            a->sx += dx;
+            a->sy += dy;
+            a->sxx += dx * dx;
+            a->syy += dy * dy;
+            a->sxy += dx * dy;
             /* perimeter: 4-neighbour sides facing another label or the outside */
             static const int PX4[4] = {1, -1, 0, 0}, PY4[4] = {0, 0, 1, -1};
             for (int k = 0; k < 4; ++k) {

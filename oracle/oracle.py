@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "rt_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "features_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "features_oracle.c"), os.path.join(_HERE, "morph_oracle.c")]
 
 DQ_MAX = 65535
 
@@ -83,6 +83,11 @@ def lib():
         L.or_watershed.argtypes = [u8p, u8p, C.c_int, C.c_int, C.c_int, i32p, u8p, i32p, i32p, i32p, i32p]
         L.or_segment_from_hq.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          u8p, i32p, u8p, u8p, u8p, u8p]
+        L.or_erode.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
+        L.or_dilate.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
+        L.or_open.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
+        L.or_recon_to_nuclei.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, u8p, u8p]
+        L.or_rbc_detect.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, u8p]
         L.or_sobel_mag.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_sobel_mag.restype = C.c_int64
         L.or_features.argtypes = [i32p, u8p, C.c_int, C.c_int, C.c_int, i32p, f64p, i64p]
@@ -272,3 +277,47 @@ def features(labels, hq, want_counts=False):
     if want_counts:
         return lo[:n], fo[:n], co[:n]
     return lo[:n], fo[:n]
+
+
+# pre-processing operations (rt_oracle.h)
+MARKER_FRAME = 0
+MARKER_OPEN = 1
+
+
+def _morph(fn, img, radius):
+    a = _u8(img)
+    h, w = a.shape
+    out = np.empty((h, w), np.uint8)
+    fn(_p(a, C.c_uint8), w, h, int(radius), _p(out, C.c_uint8))
+    return out
+
+
+def erode(img, radius):
+    return _morph(lib().or_erode, img, radius)
+
+
+def dilate(img, radius):
+    return _morph(lib().or_dilate, img, radius)
+
+
+def open_(img, radius):
+    return _morph(lib().or_open, img, radius)
+
+
+def recon_to_nuclei(hq, marker=MARKER_FRAME, radius=0, t_fg=16):
+    """Returns (R, F0)."""
+    q = _u8(hq)
+    h, w = q.shape
+    r = np.empty((h, w), np.uint8)
+    f0 = np.empty((h, w), np.uint8)
+    lib().or_recon_to_nuclei(_p(q, C.c_uint8), w, h, int(marker), int(radius), int(t_fg), _p(r, C.c_uint8),
+                             _p(f0, C.c_uint8))
+    return r, f0
+
+
+def rbc_detect(rgb, t_strong=200, t_weak=150):
+    a = _u8(rgb)
+    h, w = a.shape[:2]
+    out = np.empty((h, w), np.uint8)
+    lib().or_rbc_detect(_p(a, C.c_uint8), w, h, int(t_strong), int(t_weak), _p(out, C.c_uint8))
+    return out

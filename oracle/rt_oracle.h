@@ -141,7 +141,9 @@ int or_segment_from_hq(const uint8_t *hq, int w, int h, int t_fg, int min_area, 
  *     eccentricity sqrt(1 - l2 / l1) with l1 >= l2 the eigenvalues of the
  *     second central moments (mu20, mu11; mu11, mu02) of the pixel set, each
  *     pixel a unit square (1/12 added to mu20 and mu02), mu20 =
- *     (A sum x^2 - (sum x)^2) / A^2 etc.; orientation 0.5 atan2(2 mu11,
+ *     (A sum x^2 - (sum x)^2) / A^2 etc. (coordinates relative to the
+ *     nucleus' first pixel; numerators exact in 128-bit integers, so
+ *     w, h <= 32768); orientation 0.5 atan2(2 mu11,
  *     mu20 - mu02) (radians, y down);
  *   intensity of Hq: mean; standard deviation (population); min; max; median,
  *     25th and 75th percentile = the sorted values at 0-based ranks
@@ -194,6 +196,37 @@ int64_t or_sobel_mag(const uint8_t *hq, int w, int h, int x, int y);
  * OR_NCOUNT counts per nucleus.  Returns the number of nuclei n. */
 int or_features(const int32_t *labels, const uint8_t *hq, int w, int h, int max_nuclei, int32_t *labels_out,
                 double *feats_out, int64_t *counts_out);
+
+/* ------------------------------------------------------------------------
+ * Pre-processing operations the paper lists beside the segmentation (Sec.
+ * 5.1: Morphological Open, RBC detection, and the ReconToNuclei marker).
+ * The paper defines none of them; the readings:
+ *
+ * Erosion / dilation (grey, uint8) with the flat disk B_r = {(dx, dy) :
+ * dx^2 + dy^2 <= r^2}: out(p) = min (max) of in(p + d) over d in B_r with
+ * p + d inside the tile (pixels outside the tile are ignored, i.e. padded
+ * with 255 for erosion and 0 for dilation).  Opening = dilation of the
+ * erosion, both with B_r.
+ *
+ * ReconToNuclei with a choice of marker: R = recon8(J under Hq) with
+ * J = Hq on the 1-px tile frame and 0 inside (OR_MARKER_FRAME, the plain
+ * pipeline's marker) or J = erosion of Hq by B_r (OR_MARKER_OPEN: opening
+ * by reconstruction, so T is a top-hat by reconstruction);
+ * F0 = [Hq - R >= t_fg].
+ *
+ * RBC detection: redness(p) = 2 R - G - B of the RGB pixel; the red blood
+ * cell mask is every pixel of an 8-connected region of {redness >= t_weak}
+ * that holds a pixel with redness >= t_strong (hysteresis thresholding, as a
+ * binary reconstruction).
+ * ------------------------------------------------------------------------ */
+#define OR_MARKER_FRAME 0
+#define OR_MARKER_OPEN 1
+void or_erode(const uint8_t *in, int w, int h, int radius, uint8_t *out);
+void or_dilate(const uint8_t *in, int w, int h, int radius, uint8_t *out);
+void or_open(const uint8_t *in, int w, int h, int radius, uint8_t *out);
+void or_recon_to_nuclei(const uint8_t *hq, int w, int h, int marker_mode, int radius, int t_fg, uint8_t *recon_out,
+                        uint8_t *f0_out);
+void or_rbc_detect(const uint8_t *rgb, int w, int h, int t_strong, int t_weak, uint8_t *mask_out);
 
 #ifdef __cplusplus
 }
