@@ -4,7 +4,7 @@ One step = rt_segment_tile over one 4096 x 4096 synthetic H&E-like tile (8000
 nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20,
 seed 0), input resident in HBM.  Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-stream4k]
                   [--no-batch] [--no-surrogate] [--no-tune] [--knobs K=V,...]
                   [--copy-calibration MB]
 
@@ -13,13 +13,25 @@ The launch knobs of the 4096 x 4096 tile are picked first by the autotuner
 gives them (profiler runs pass the set a tuned run reported, so that no
 tuning trial enters the kernel statistics).
 
-Roofline: the dominant kernel is the reconstruction round kernel (most of the
-GPU time of a tile).  After the timed steps, the same number of steps runs
-again with the library's stage timing on: HIP events at every stage boundary
-and a pair around every round launch, on the call's stream, plus a count of
-the 62 x 62 tiles the rounds process; achieved = tile visits x 11532
-algorithmic bytes (read Hq and R, write R: 3 bytes per interior pixel) /
-summed kernel time.  `value` comes from the uninstrumented steps.
+Roofline: after the timed steps are read, four kernels are candidates for the
+dominant one: the reconstruction round kernel and the three per-object
+kernels (small, medium and large LDS classes, which run side by side on
+three streams).  The library records a pair of HIP events around every
+launch on the stream the kernel runs on (around each run of consecutive
+round launches for the round kernel) and device counters of the work done.
+The kernel with the most time per tile is the dominant one.  Algorithmic
+bytes are per call, never per re-visit: the uint8 reconstruction moves 3 B
+per pixel of the tile per call (read Hq and R, write R), spread over the
+call's round launches; a per-object kernel moves 9 B per pixel of the
+components it processes (read the label, write label and mask).  `value`
+comes from the same timed steps (the events add no synchronisation).
+`pipeline_floor_frac` is the whole tile's 8 B/px floor (RGB in, mask and
+labels out) at the measured tiles/s, as a fraction of the 8 TB/s peak.
+
+The "stream4k" object times rt_segment_batch over 8 distinct 4096 x 4096
+tiles of the same generator (seeds 0..7) per call: every tile's data is
+different, so the 1.2 GB working set cannot stay in the 256 MB MALL between
+steps.
 
 The "batch64" object times rt_segment_batch on the 64-tile batch of uneven
 slide-edge sizes (each side drawn from {512, 1024, 2048, 4096}), with knobs
@@ -33,8 +45,11 @@ tau (tiles/s of both, fallback rate, Dice with fallback tiles counting 1).
 Weights come from --weights if that file exists, else the network is trained
 in the run on --train-crops crops labelled by the plain pipeline.
 
-The CPU baseline is the project's oracle (plain single-threaded C) timed on
-the same 4096 x 4096 tile on this host.
+The CPU baseline is the project's oracle (plain single-threaded C, the same
+source built -O3 -march=native -ffp-contract=off on this host) timed on the
+same 4096 x 4096 tile: once on one core, then one copy of the tile per
+available core in as many threads (tile-parallel); `value` is the all-core
+tiles/s.
 
 --copy-calibration MB runs one plain device copy of MB MiB before anything
 else, so that a counter run (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) sees a
@@ -52,8 +67,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TILE_VISIT_BYTES = 62 * 62 * 3
+BF16_PEAK_TFLOPS = 2500.0
+METRIC = "4K\u00d74K tiles/s on 1 MI355X: plain vs surrogate @Dice\u22650.95; HBM GB/s % of peak"
 ROUND_KERNEL = "k_recon_round<unsigned char, 8, true>"   # the plain uint8 round kernel
+OBJ_KERNELS = ("k_objects_s", "k_objects_m", "k_objects_l")
+OBJ_BYTES_PER_PX = 9      # read the label, write label (4 B) and mask (1 B)
+RECON_BYTES_PER_PX = 3    # uint8 reconstruction per call: read Hq and R, write R
 
 
 def log(*a):
@@ -92,9 +111,8 @@ def batch64(rtseg, synth, torch, args):
     with ThreadPoolExecutor(8) as ex:
         rgbs = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
     ctx = rtseg.Context(0)
-    res = tune.autotune(rgbs, ctx=ctx, reps=3, cache=tune_cache(args))
-    log(f"{'cached' if res.get('cached') else 'autotuned'} knobs {res['knobs']} ({res['ms']:.2f} ms/batch, "
-        f"{res['seconds']} s)")
+    res = tune.autotune(rgbs, ctx=ctx, reps=3, cache=tune_cache(args), trials=args.tune_trials)
+    log(f"{'cached' if res.get('cached') else 'tuner'} knobs {res['knobs']} ({res['ms']:.2f} ms/batch)")
     params = rtseg.default_params()
     for _ in range(2):
         rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
@@ -111,10 +129,92 @@ def batch64(rtseg, synth, torch, args):
     log(f"batch64: {ms:.2f} ms/batch, {64 / (ms * 1e-3):.1f} tiles/s, {px / (ms * 1e-3) / 1e6:.0f} Mpx/s")
     out = {"tiles": 64, "megapixels": round(px / 1e6, 2), "steps": steps, "ms_per_batch": round(ms, 3),
            "tiles_per_s": round(64 / (ms * 1e-3), 2), "mpx_per_s": round(px / (ms * 1e-3) / 1e6, 1),
-           "objects": objs, "knobs": res["knobs"], "knobs_source": "tune cache" if res.get("cached") else "autotuned",
+           "objects": objs, "knobs": res["knobs"],
+           "knobs_source": "tune cache" if res.get("cached") else res.get("source", "autotuned"),
            "pipeline_floor_frac": round(8 * px / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
     ctx.close()
     return out
+
+
+def stream4k(rtseg, synth, torch, args, knobs):
+    """rt_segment_batch over `args.stream4k_tiles` distinct 4096 x 4096 tiles
+    (the 4096 x 4096 workload's generator, seeds 0..n-1) per call, with the
+    knob set of the single 4096 x 4096 tile (no tuning trials)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1405_7958_amd import tune
+    d = torch.device("cuda", 0)
+    nt = args.stream4k_tiles
+    base = synth.spec_4k(0)
+    specs = [synth.TileSpec(w=base.w, h=base.h, seed=i, n_nuclei=base.n_nuclei, amin=base.amin, amax=base.amax,
+                            cluster_frac=base.cluster_frac, cluster_min=base.cluster_min, cluster_max=base.cluster_max,
+                            jitter=base.jitter) for i in range(nt)]
+    log(f"generating {nt} distinct 4096x4096 tiles ...")
+    with ThreadPoolExecutor(8) as ex:
+        rgbs = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
+    ctx = rtseg.Context(0)
+    if knobs:
+        tune.apply(knobs, ctx)
+    params = rtseg.default_params()
+    for _ in range(2):
+        rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = rtseg.rt_segment_batch(rgbs, params, ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    px = nt * base.w * base.h
+    tps = nt / (ms * 1e-3)
+    objs = sum(int(o[2].item()) for o in outs)
+    log(f"stream4k: {ms:.2f} ms per {nt} tiles, {tps:.1f} tiles/s")
+    out = {"tiles_per_call": nt, "seeds": [0, nt - 1], "steps": steps, "ms_per_call": round(ms, 3),
+           "tiles_per_s": round(tps, 2), "mpx_per_s": round(px / (ms * 1e-3) / 1e6, 1), "objects": objs,
+           "working_set_mb": round(nt * base.w * base.h * (3 + 1 + 4) / 1e6, 1),
+           "knobs": knobs, "knobs_source": "the 4096x4096 tile's knob set" if knobs else "defaults",
+           "pipeline_floor_frac": round(8 * px / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
+    ctx.close()
+    return out
+
+
+def unet_forward_flops_per_px():
+    """Algorithmic FLOPs per input pixel of one U-Net forward pass (2 per
+    multiply-add; RGB input, levels of 16/32/64/128 channels, two 3x3 convs
+    per level, 2x2 stride-2 up-convs, 1x1 head to 2 maps)."""
+    ch = (16, 32, 64, 128)
+    f = 0.0
+    cin = 3
+    for lvl, c in enumerate(ch):              # encoder and bottleneck
+        f += 2 * 9 * (cin * c + c * c) / 4 ** lvl
+        cin = c
+    for lvl in (2, 1, 0):                     # decoder
+        c = ch[lvl]
+        f += 2 * ch[lvl + 1] * c / 4 ** lvl   # up-conv: one input pixel per output pixel
+        f += 2 * 9 * (2 * c * c + c * c) / 4 ** lvl
+    return f + 2 * ch[0] * 2
+
+
+def surrogate_forward_rate(rtseg, torch, net, tile, reps=5):
+    """Times rt_unet_forward on one tile; FLOPs counted over the inference
+    windows (512 x 512 at stride 480, the last flush with the edge)."""
+    h, w = tile.shape[:2]
+
+    def nwin(n):
+        return 1 if n <= 512 else 1 + -(-(n - 512) // 480)
+    px = nwin(h) * nwin(w) * 512 * 512
+    net.forward(tile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(tile)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = unet_forward_flops_per_px() * px
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"ms_per_tile": round(ms, 3), "tflop_per_tile": round(flops / 1e12, 4), "achieved_tflops": round(tf, 1),
+            "peak_tflops": BF16_PEAK_TFLOPS, "mfma_frac": round(tf / BF16_PEAK_TFLOPS, 5), "window_px": px}
 
 
 def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
@@ -154,6 +254,9 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
         held.append(torch.from_numpy(synth.make_tile(spec)[0]).to(d))
     for t in held[:1]:   # warm-up
         rtseg.rt_segment_tile_surrogate(t, net, tau=-1.0, ctx=ctx)
+    fwd = surrogate_forward_rate(rtseg, torch, net, held[0])
+    log(f"U-Net forward on a 4096x4096 tile: {fwd['ms_per_tile']} ms, {fwd['achieved_tflops']} TFLOP/s "
+        f"({fwd['mfma_frac']:.4f} of the bf16 MFMA peak)")
     recs, t_plain, t_sur = surrogate.evaluate(net, held, tau=-1.0, ctx=ctx)
     dice = [r["dice"] for r in recs]
     iou = [r["iou"] for r in recs]
@@ -165,7 +268,7 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
     if args.stream <= 0:
         net.close()
         ctx.close()
-        return {"weights": src, "training": train, "heldout_4k": cfg4, "stream": None}
+        return {"weights": src, "training": train, "forward": fwd, "heldout_4k": cfg4, "stream": None}
     # config 5: a sample of the mixed stream, surrogate + fallback
     from concurrent.futures import ThreadPoolExecutor
     specs = [synth.spec_stream(20000 + i) for i in range(args.stream)]
@@ -176,7 +279,10 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
     raw = np.array([r["dice"] for r in recs])
     fb = np.array([r["fallback"] for r in recs])
     px = sum(s.w * s.h for s in specs)
-    cfg5 = {"tiles": len(tiles), "megapixels": round(px / 1e6, 1), "tau": args.tau,
+    cfg5 = {"tiles": len(tiles), "of_stream_tiles": 1024,
+            "sample": f"the first {len(tiles)} tiles (seeds 20000..{20000 + len(tiles) - 1}) of the 1,024-tile mixed "
+                      "stream" if len(tiles) < 1024 else "the whole 1,024-tile mixed stream",
+            "megapixels": round(px / 1e6, 1), "tau": args.tau,
             "surrogate_tiles_per_s": round(len(tiles) / t_sur, 2), "plain_tiles_per_s": round(len(tiles) / t_plain, 2),
             "fallback_rate": round(float(fb.mean()), 4), "dice_mean": round(float(dice.mean()), 4),
             "dice_p5": round(float(np.percentile(dice, 5)), 4),
@@ -189,7 +295,42 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
         f"(p5 {cfg5['dice_p5']})")
     net.close()
     ctx.close()
-    return {"weights": src, "training": train, "heldout_4k": cfg4, "stream": cfg5}
+    return {"weights": src, "training": train, "forward": fwd, "heldout_4k": cfg4, "stream": cfg5}
+
+
+def cpu_baseline(rgb_np):
+    """The oracle on this host's cores: one tile on one core, then one copy of
+    the tile per available core, one thread each (the C calls release the
+    interpreter lock, so the threads run in parallel)."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    oracle.use_library(oracle.build_native(tmp))
+
+    def one(_):
+        oracle.segment_from_hq(oracle.deconv(rgb_np))
+
+    log("timing the CPU oracle on the 4096x4096 tile: one core ...")
+    c0 = time.perf_counter()
+    one(0)
+    t1 = time.perf_counter() - c0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cores = os.cpu_count() or 1
+    log(f"oracle: {t1:.2f} s/tile on one core; {cores} tiles on {cores} threads ...")
+    c0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, range(cores)))
+    tall = time.perf_counter() - c0
+    log(f"oracle: {cores} tiles in {tall:.2f} s")
+    return {"value": round(cores / tall, 5), "unit": "tiles/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} copies of the 4096x4096 tile (deconvolution + segmentation), one per thread, "
+                      f"{tall:.2f} s wall; single core: one tile in {t1:.2f} s",
+            "single_core_value": round(1.0 / t1, 5),
+            "build": "gcc -O3 -march=native -ffp-contract=off (built on this host)", "host": host_cpu()}
 
 
 def main():
@@ -200,7 +341,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_recon_round_4k.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_4k.json"))
+    ap.add_argument("--no-stream4k", action="store_true")
+    ap.add_argument("--tune-trials", action="store_true",
+                    help="run tuning trials on a cache miss (default: the cached knob set or the defaults)")
+    ap.add_argument("--stream4k-tiles", type=int, default=8)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default knobs for the 4096x4096 tile")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1405_7958_amd", "tune_cache.json"),
@@ -257,19 +402,22 @@ def main():
         log(f"knobs for the 4096x4096 tile: {knobs}")
     elif not args.no_tune:
         from paper_1405_7958_amd import tune
-        res = tune.autotune([rgb], ctx=ctx, reps=3, cache=tune_cache(args), allow_graph=False)
+        res = tune.autotune([rgb], ctx=ctx, reps=3, cache=tune_cache(args), allow_graph=False,
+                            trials=args.tune_trials)
         knobs = res["knobs"]
-        knobs_source = "tune cache" if res.get("cached") else "autotuned"
+        knobs_source = "tune cache" if res.get("cached") else res.get("source", "autotuned")
         log(f"{knobs_source} knobs for the 4096x4096 tile: {knobs} ({res['ms']:.3f} ms, {res['seconds']} s)")
     for i in range(args.warmup):
         rtseg.rt_segment_tile(rgb, params, ctx=ctx, out=out)
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    # the timed steps record only the round kernel's timing (two HIP events
-    # around each run of round launches on the call's stream, and the number
-    # of tiles each launch processes) ...
+    # the timed steps record the candidate kernels' timing: HIP events around
+    # each run of round launches and around each per-object class launch, on
+    # the stream each runs on, plus device counters of the work done
     rtseg.rt_profile_enable(2, ctx)
     rtseg.rt_profile_recon_rounds(ctx)  # discard
+    for k in range(3):
+        rtseg.rt_profile_objects(k, ctx)  # discard
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -277,6 +425,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r_ms, r_launches, r_visits = rtseg.rt_profile_recon_rounds(ctx)
+    obj = [rtseg.rt_profile_objects(k, ctx) for k in range(3)]
     rtseg.rt_profile_enable(False, ctx)
     n_obj = int(n.item())
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -285,7 +434,6 @@ def main():
     # ... then the same steps again with HIP events at every stage boundary
     rtseg.rt_profile_enable(True, ctx)
     rtseg.rt_profile_read(ctx)          # discard
-    rtseg.rt_profile_recon_rounds(ctx)  # discard
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for i in range(args.steps):
@@ -295,6 +443,8 @@ def main():
     rtseg.rt_profile_enable(False, ctx)
     calls, stages = rtseg.rt_profile_read(ctx)
     rtseg.rt_profile_recon_rounds(ctx)  # the timed steps' figures are kept
+    for k in range(3):
+        rtseg.rt_profile_objects(k, ctx)
     ms_prof = (t3 - t2) * 1e3 / args.steps
     log(f"instrumented steps: {ms_prof:.3f} ms/tile")
 
@@ -305,14 +455,29 @@ def main():
         per_call = ms_tot / max(1, calls)
         per_stage[k] = {"ms_per_tile": round(per_call, 4), "launches_per_tile": round(launches / max(1, calls), 2)}
         log(f"  {k:12s} {per_call:8.4f} ms/tile  launches/tile {launches / max(1, calls):6.2f}")
-    # dominant kernel: the reconstruction round kernel
-    ms_launch = r_ms / max(1, r_launches)
-    bytes_launch = TILE_VISIT_BYTES * r_visits / max(1, r_launches)
-    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9 if r_launches else 0.0
-    log(f"recon round kernel: {r_launches} launches, {ms_launch * 1e3:.1f} us/launch, "
-        f"{r_visits / max(1, r_launches):.0f} tile visits/launch, {achieved:.1f} GB/s")
-    # counter traffic of the round kernel, measured for one knob set: it holds
-    # for this run when the knobs that change a launch's work agree
+    # candidate kernels: time per tile, algorithmic bytes per launch, rate
+    kern = []
+    if r_launches:
+        kern.append({"kernel": ROUND_KERNEL, "ms_per_tile": r_ms / args.steps, "launches": r_launches,
+                     "us_per_launch": r_ms * 1e3 / r_launches,
+                     "alg_bytes_per_launch": RECON_BYTES_PER_PX * N * args.steps / r_launches,
+                     "alg_bytes_rule": "3 B per tile pixel per call (read Hq and R, write R), over the call's "
+                                       "round launches",
+                     "tile_visits_per_launch": round(r_visits / r_launches, 1)})
+    for name, (ms_k, ln_k, px_k) in zip(OBJ_KERNELS, obj):
+        if ln_k:
+            kern.append({"kernel": name, "ms_per_tile": ms_k / args.steps, "launches": ln_k,
+                         "us_per_launch": ms_k * 1e3 / ln_k, "alg_bytes_per_launch": OBJ_BYTES_PER_PX * px_k / ln_k,
+                         "alg_bytes_rule": "9 B per pixel of the components the class processed (device count)",
+                         "component_px_per_launch": round(px_k / ln_k)})
+    for k in kern:
+        k["achieved_gbs"] = k["alg_bytes_per_launch"] / (k["us_per_launch"] * 1e-6) / 1e9
+        k["frac"] = k["achieved_gbs"] / HBM_PEAK_GBS
+        log(f"  {k['kernel']:40s} {k['ms_per_tile'] * 1e3:8.1f} us/tile {k['us_per_launch']:8.1f} us/launch "
+            f"{k['alg_bytes_per_launch'] / 1e6:8.2f} MB/launch {k['achieved_gbs']:8.1f} GB/s")
+    dom = max(kern, key=lambda k: k["ms_per_tile"])
+    # counter traffic of the dominant kernel (two rocprofv3 --pmc runs,
+    # calibrated by a copy), valid for the knob set the counters were taken with
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
@@ -320,40 +485,32 @@ def main():
             used = knobs or {k: rtseg.rt_get_knob(k, ctx=ctx) for k in rtseg.KNOBS}
             same = all(int(used.get(k, -1)) == int(v) for k, v in tj.get("knobs", {}).items()
                        if k in ("recon_levels", "recon_level_mode", "recon_level_frac", "recon_round_batch"))
-            same = same and tj.get("kernel") == ROUND_KERNEL   # counters of this kernel's code
-            traffic = tj.get("bytes_per_launch") if same and tj.get("knobs") else None
+            traffic = tj.get("bytes_per_launch", {}).get(dom["kernel"]) if same and tj.get("knobs") else None
         except Exception:
             traffic = None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "kernel": ROUND_KERNEL,
-            "alg_bytes_per_launch": round(bytes_launch), "us_per_launch": round(ms_launch * 1e3, 2),
-            "launches_per_tile": round(r_launches / max(1, args.steps), 2),
-            "tile_visits_per_launch": round(r_visits / max(1, r_launches), 1)}
+    floor_frac = 8 * N * tiles_s / (HBM_PEAK_GBS * 1e9)
+    roof = {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dom["frac"], 5), "traffic": traffic, "kernel": dom["kernel"],
+            "alg_bytes_per_launch": round(dom["alg_bytes_per_launch"]), "us_per_launch": round(dom["us_per_launch"], 2),
+            "pipeline_floor_frac": round(floor_frac, 5),
+            "kernels": [{k2: (round(v, 5) if isinstance(v, float) else v) for k2, v in k.items()} for k in kern]}
 
     batch = None
     if not args.no_batch:
         batch = batch64(rtseg, synth, torch, args)
+    s4k = None
+    if not args.no_stream4k:
+        s4k = stream4k(rtseg, synth, torch, args, knobs)
     sur = None
     if not args.no_surrogate:
         sur = surrogate_leg(rtseg, synth, torch, args, ms_step)
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        log("timing the CPU oracle on the same tile (single thread) ...")
-        c0 = time.perf_counter()
-        hq = oracle.deconv(rgb_np)
-        oracle.segment_from_hq(hq)
-        c1 = time.perf_counter()
-        cpu = {"value": round(1.0 / (c1 - c0), 5), "unit": "tiles/s", "cores": 1, "kind": "oracle",
-               "sample": "one full 4096x4096 tile of the same workload (deconvolution + segmentation), "
-                         f"single thread, {c1 - c0:.2f} s",
-               "host": host_cpu()}
-        log(f"oracle: {c1 - c0:.2f} s/tile")
+        cpu = cpu_baseline(rgb_np)
 
     line = {
-        "metric": "4Kx4K tiles/s on 1 MI355X (plain pipeline); HBM GB/s % of peak",
+        "metric": METRIC,
         "value": round(tiles_s, 3),
         "unit": "tiles/s",
         "n_gpus": 1,
@@ -368,10 +525,11 @@ def main():
         "config": {"workload": "plain segmentation pipeline (rt_segment_tile), one 4096x4096 synthetic H&E tile, "
                                "8000 nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20, seed 0",
                    "tile": [h, w], "objects": n_obj, "foreground_px": fg,
-                   "pipeline_floor_frac": round(8 * N * tiles_s / (HBM_PEAK_GBS * 1e9), 5),
+                   "pipeline_floor_frac": round(floor_frac, 5),
                    "knobs": knobs, "knobs_source": knobs_source, "ms_per_step_instrumented": round(ms_prof, 4), "stages": per_stage},
         "roofline": roof,
         "batch64": batch,
+        "stream4k": s4k,
         "surrogate": sur,
         "cpu_baseline": cpu,
     }

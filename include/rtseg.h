@@ -110,6 +110,7 @@ int rt_fill_holes(rt_ctx *ctx, const uint8_t *in, uint8_t *out, int32_t w, int32
 int rt_ccl(rt_ctx *ctx, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
            int32_t *n_out_dev, void *stream);
 
+
 /*
  * AreaThreshold (Sec. 5.1): a component (pixels sharing one positive label)
  * with min_area <= area <= max_area keeps its label; other pixels become 0.
@@ -223,12 +224,12 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *                             rounds as launches, then the work queue seeded
  *                             with the tiles they left queued; default 0
  *   "recon_queue_after" 1..64 rounds before the work queue in mode 2; default 2
- *   "objects_path"      0..2  routing of components to the per-object kernels:
- *                             0 crops <= 32^2 and <= 64^2 to the register-scan
+ *   "objects_path"      0     routing of components to the per-object kernels:
+ *                             crops <= 32^2 and <= 64^2 to the register-scan
  *                             classes, up to 9312 px to the LDS class, larger
- *                             to global memory; 1 skips the 64^2 register
- *                             class; 2 sends every crop that fits to the LDS
- *                             class; default 0
+ *                             to global memory.  The values 1 (no 64^2 class)
+ *                             and 2 (every crop to the LDS class) are switched
+ *                             off and return RT_EUNSUPPORTED
  *   "graph"             0|1   rt_segment_tile / rt_segment_batch replay the
  *                             launch sequence from captured HIP graphs (cached
  *                             per tile-size list, up to 4); default 0.  The
@@ -244,6 +245,116 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  */
 int rt_set_knob(rt_ctx *ctx, const char *name, int value);
 int rt_get_knob(rt_ctx *ctx, const char *name, int *value);
+
+/*
+ * Pre-processing operations listed beside the segmentation (Sec. 5.1:
+ * Morphological Open, RBC detection; the PATS discussion of Sec. 5.5 names
+ * them among the low-speedup operations).  The paper defines none of them.
+ *
+ * rt_morph: grey erosion (op RT_ERODE), dilation (RT_DILATE) or opening
+ * (RT_OPEN = dilation of the erosion) of a uint8 image by the flat disk
+ * B_r = {(dx, dy) : dx^2 + dy^2 <= r^2}, 0 <= r <= RT_MORPH_MAX_RADIUS:
+ * out(p) = min (max) of in(p + d) over d in B_r with p + d inside the image
+ * (pixels outside are ignored).  in and out are uint8 with their own
+ * pitches and must not overlap.  RT_OPEN takes w*h bytes of scratch.
+ */
+#define RT_ERODE 0
+#define RT_DILATE 1
+#define RT_OPEN 2
+#define RT_MORPH_MAX_RADIUS 32
+int rt_morph(rt_ctx *ctx, int op, const uint8_t *in, int64_t in_pitch, uint8_t *out, int64_t out_pitch, int32_t w,
+             int32_t h, int32_t radius, void *stream);
+
+/*
+ * ReconToNuclei with a choice of marker: R = reconstruction by dilation
+ * (8-connected) of the marker J under Hq, with J = Hq on the one-pixel tile
+ * frame and 0 inside (RT_MARKER_FRAME, the marker of rt_segment_tile) or
+ * J = erosion of Hq by B_radius (RT_MARKER_OPEN: opening by reconstruction,
+ * so Hq - R is a top-hat by reconstruction); F0 = [Hq - R >= t_fg].
+ * hq, r_out (nullable: R is then kept in scratch) and f0_out share `pitch`.
+ * Synchronises `stream` between reconstruction rounds, like rt_morph_recon.
+ */
+#define RT_MARKER_FRAME 0
+#define RT_MARKER_OPEN 1
+int rt_recon_to_nuclei(rt_ctx *ctx, const uint8_t *hq, uint8_t *r_out, uint8_t *f0_out, int32_t w, int32_t h,
+                       int64_t pitch, int marker, int32_t radius, int32_t t_fg, void *stream);
+
+/*
+ * RBC detection: redness(p) = 2 R - G - B of the interleaved RGB pixel; the
+ * red blood cell mask (uint8 0/1, pitch out_pitch) holds every pixel of an
+ * 8-connected region of {redness >= t_weak} that contains a pixel with
+ * redness >= t_strong (hysteresis thresholding, computed as a binary
+ * reconstruction).  t_weak <= t_strong.  Synchronises `stream` between
+ * reconstruction rounds.  Scratch: out_pitch * h bytes.
+ */
+int rt_rbc_detect(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, int32_t w, int32_t h, int32_t t_strong,
+                  int32_t t_weak, uint8_t *mask_out, int64_t out_pitch, void *stream);
+
+/*
+ * Feature computation (Sec. 5.1: shape and texture features of every
+ * segmented nucleus, computed in two steps -- one block per nucleus bounding
+ * box builds the nucleus' histograms and co-occurrence matrix, then one
+ * thread per nucleus computes the features; Fig. 1: a vector of shape and
+ * texture features per object).  The paper lists no feature; the set is:
+ *
+ * Input: labels (int32, pitch lab_pitch; 0 = background; a nucleus is every
+ * pixel carrying one positive label, whose value is 1 + the row-major index
+ * y*w + x of the nucleus' first pixel -- the labels rt_segment_tile, rt_ccl
+ * and rt_watershed produce) and Hq (uint8, pitch hq_pitch).  Nuclei are
+ * numbered in increasing label order; the first min(n, max_nuclei) are
+ * written.  Other label values are ignored (memory-safe, unspecified
+ * features).  w, h <= 32768.
+ * Per-nucleus counts (exact): area; bounding box; perimeter = pixel sides of
+ * the nucleus (4-neighbours) that face another label or the outside of the
+ * tile; hist[v] = pixels with Hq = v; Sobel gradient g = floor(sqrt(gx^2 +
+ * gy^2)) of Hq (3 x 3 kernels with weights 1, 2, 1; pixels outside the tile
+ * replicate the nearest edge pixel) with its histogram ghist[min(g / 32, 15)],
+ * sum, sum of squares and maximum; co-occurrence matrix C of the grey levels
+ * Hq / 16 (16 levels) over the offsets (1,0), (1,1), (0,1), (-1,1): every
+ * pair of pixels of the nucleus at one of them adds 1 to C[q1][q2] and to
+ * C[q2][q1].
+ * Features (FP64, RT_NFEAT per nucleus, in this order):
+ *    0 area  1 perimeter  2 centroid x  3 centroid y  4 bbox width
+ *    5 bbox height  6 extent (area / bbox area)  7 equivalent diameter
+ *    sqrt(4 area / pi)  8 circularity 4 pi area / perimeter^2
+ *    9 major axis 4 sqrt(l1)  10 minor axis 4 sqrt(l2)  11 eccentricity
+ *    sqrt(1 - l2 / l1)  12 orientation 0.5 atan2(2 mu11, mu20 - mu02)
+ *    (radians, y down) -- l1 >= l2 the eigenvalues of the second central
+ *    moments of the pixel set with each pixel a unit square (1/12 added to
+ *    mu20 and mu02); A^2 mu20 = A sum x^2 - (sum x)^2 etc. exact in 128 bits;
+ *   13 mean  14 standard deviation  15 min  16 max  17 median  18 25th and
+ *   19 75th percentile of Hq (the sorted values at 0-based ranks
+ *   floor((A-1)/2), floor((A-1)/4), floor(3(A-1)/4))  20 skewness m3/m2^1.5
+ *   21 kurtosis m4/m2^2 (0 when m2 = 0)  22 entropy -sum p log2 p and
+ *   23 energy sum p^2 of the Hq histogram  24 range max - min;
+ *   25 mean g  26 standard deviation of g  27 max g  28 entropy and
+ *   29 energy of ghist  30 share of pixels with g >= 128;
+ *   Haralick features of p = C / sum C (all 0 when sum C = 0; px the
+ *   marginal, mu = sum i px, var = sum (i-mu)^2 px, p_{x+y}, p_{x-y} the
+ *   sums over i+j = k and |i-j| = k): 31 angular second moment
+ *   32 contrast  33 correlation (1 when var = 0)  34 variance
+ *   35 homogeneity sum p / (1 + (i-j)^2)  36 sum average  37 sum variance
+ *   38 sum entropy  39 entropy  40 difference variance  41 difference entropy
+ *   42 IMC1 = (HXY - HXY1) / HX (0 when HX = 0)  43 IMC2 =
+ *   sqrt(1 - exp(-2 max(HXY2 - HXY, 0)))  44 maximum probability
+ *   45 cluster shade sum (i+j-2mu)^3 p  46 cluster prominence
+ *   sum (i+j-2mu)^4 p.  Logarithms base 2.
+ * Outputs (device memory owned by the caller): labels_out[max_nuclei] (the
+ * nuclei's labels), feats_out[max_nuclei * RT_NFEAT], counts_out (nullable,
+ * int64, max_nuclei * RT_FEAT_NCOUNT: area, perimeter, x0, y0, x1, y1,
+ * hist[256], C[16][16] row-major, ghist[16], sum g, sum g^2, max g) and
+ * n_out_dev (nullable, int32: the number of nuclei, also beyond max_nuclei).
+ * Scratch: 4 (w*h + h + 1) bytes plus about 2.2 KB per nucleus.
+ */
+#define RT_NFEAT 47
+#define RT_FEAT_NCOUNT 537
+#define RT_FEAT_GLCM_LEVELS 16
+#define RT_FEAT_GRAD_BINS 16
+#define RT_FEAT_GRAD_BIN_WIDTH 32
+#define RT_FEAT_EDGE_THRESHOLD 128
+int rt_features(rt_ctx *ctx, const int32_t *labels, int64_t lab_pitch, const uint8_t *hq, int64_t hq_pitch,
+                int32_t w, int32_t h, int32_t max_nuclei, int32_t *labels_out, double *feats_out,
+                int64_t *counts_out, int32_t *n_out_dev, void *stream);
 
 /*
  * Stage timing, for benchmarks.  rt_profile_enable(ctx, 1) turns on stage
@@ -279,6 +390,17 @@ const char *rt_profile_stage_name(int stage);
  * and clears the record.
  */
 int rt_profile_recon_rounds(rt_ctx *ctx, double *kernel_ms, int64_t *launches, int64_t *tile_visits);
+/*
+ * Timing of the per-object kernels (profiling modes 1 and 2, outside graph
+ * capture): cls 0 = small class (crops up to 32 x 32, and the components
+ * erased by the first area threshold), 1 = medium (up to 64 x 64), 2 = large
+ * LDS class.  kernel_ms = summed time between an event pair recorded around
+ * each launch of the class on the stream it runs on; launches = launches
+ * recorded; pixels = pixels of the components in the class's work list (the
+ * sum of their areas, tallied on the device by a separate kernel after the
+ * stage).  Reading synchronises and clears that class's figures.
+ */
+int rt_profile_objects(rt_ctx *ctx, int cls, double *kernel_ms, int64_t *launches, int64_t *pixels);
 
 #ifdef __cplusplus
 }

@@ -245,7 +245,8 @@ struct Stager {
     }
 };
 
-size_t max_obj_of(int w, int h) { return ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1); }
+// most 8-connected components of a w x h tile
+size_t max_obj_of(int w, int h) { return max_components(w, h, 8); }
 
 // ---------------------------------------------------------------------------
 // the segmentation pipeline over one launch group of tiles
@@ -291,6 +292,23 @@ int side_streams(rt_ctx *c, ObjStreams &par) {
     par.fork = c->fork_ev;
     par.join = c->join_ev;
     par.join2 = c->join2_ev;
+    return RT_OK;
+}
+
+// Profiling: an event pair per per-object class for the next launch.
+int objects_timing(rt_ctx *c, ObjStreams &par) {
+    for (int k = 0; k < 3; ++k) {
+        std::vector<hipEvent_t> &v = c->obj_events[k];
+        while (v.size() < c->obj_used[k] + 2) {
+            hipEvent_t ev;
+            RT_HIP(hipEventCreate(&ev));
+            v.push_back(ev);
+        }
+        par.timing[k][0] = v[c->obj_used[k]];
+        par.timing[k][1] = v[c->obj_used[k] + 1];
+        c->obj_used[k] += 2;
+        c->obj_launches[k] += 1;
+    }
     return RT_OK;
 }
 
@@ -342,12 +360,16 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool captur
     ObjStreams par{};
     (void)capturing;
     if ((e = side_streams(c, par))) return e;
+    const bool obj_prof = c->prof_on && !capturing;
+    if (obj_prof && (e = objects_timing(c, par))) return e;
     if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr, &par)))
         return e;
     if ((e = launch_batch_end(at<BatchAux>(c, P.o_aux), P.n, s))) return e;
     c->prof_launches[5] += 2;
     c->prof_launches[6] += 2;
     if (prof && (e = prof_mark(c, 7, s))) return e;
+    // after the last stage event, so that the tally counts in no stage
+    if (obj_prof && (e = launch_objects_tally(at<ObjArgs>(c, P.o_ob), OL, c->prof_obj_px, c->n_cu, s))) return e;
     return RT_OK;
 }
 
@@ -714,6 +736,9 @@ int rt_ctx_destroy(rt_ctx *c) {
     for (hipEvent_t ev : c->prof_events) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->round_events) (void)hipEventDestroy(ev);
     if (c->prof_visits) (void)hipFree(c->prof_visits);
+    if (c->prof_obj_px) (void)hipFree(c->prof_obj_px);
+    for (auto &v : c->obj_events)
+        for (hipEvent_t ev : v) (void)hipEventDestroy(ev);
     delete c;
     return RT_OK;
 }
@@ -820,7 +845,7 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     Layout L;
     const size_t o_args = L.add(sizeof(CclArgs));
     const size_t o_ids = L.add(sizeof(int32_t) * ((size_t)w * h + 1));
-    const size_t o_list = L.add(sizeof(int32_t) * (n_out_dev ? max_obj_of(w, h) : 1));
+    const size_t o_list = L.add(sizeof(int32_t) * (n_out_dev ? max_components(w, h, conn) : 1));
     if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, sizeof(CclArgs) + 4096))) return e;
     CclArgs A{};
     A.pred = CclPred::NonZero;
@@ -841,6 +866,156 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     Stager sg{c};
     if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
     return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::NonZero, CclOut::Labels);
+}
+
+namespace {
+// half-widths of the flat disk of radius r, per row offset dy = -r..r
+void disk_spans(int r, int *span) {
+    for (int dy = -r; dy <= r; ++dy) {
+        int s = 0;
+        while ((s + 1) * (s + 1) + dy * dy <= r * r) ++s;
+        span[dy + r] = s;
+    }
+}
+
+// Reconstruction rounds of the plain uint8 kernel on one image: out already
+// holds min(marker, mask); mask and out share `pitch`.
+int recon_u8_rounds(rt_ctx *c, const uint8_t *mask, uint8_t *out, int w, int h, int64_t pitch, hipStream_t s) {
+    const int64_t ntiles = recon_tiles(w, h);
+    Layout L;
+    const size_t base = al(c->arena.off);
+    const size_t o_args = base + L.add(sizeof(ReconImg));
+    c->arena.off = base + L.off;
+    int e;
+    if ((e = ensure_staging(c, sizeof(ReconImg) + 4096))) return e;
+    Stager sg{c};
+    if ((e = sg.put(std::vector<ReconImg>{ReconImg{w, h, pitch, mask, out, nullptr, (w + 61) / 62, (h + 61) / 62, 0}},
+                    o_args)) ||
+        (e = sg.flush(s)))
+        return e;
+    const bool plain = (int64_t)(h - 1) * pitch + w + 8 < (int64_t(1) << 31);
+    return recon_rounds(c, at<ReconImg>(c, o_args), 1, plain ? RECON_U8_PLAIN : RT_U8, 8, (int)ntiles, s);
+}
+}  // namespace
+
+int rt_morph(rt_ctx *c, int op, const uint8_t *in, int64_t in_pitch, uint8_t *out, int64_t out_pitch, int32_t w,
+             int32_t h, int32_t radius, void *stream) {
+    CHECK(c && in && out, "rt_morph: null argument");
+    CHECK(op == RT_ERODE || op == RT_DILATE || op == RT_OPEN, "rt_morph: bad op %d", op);
+    CHECK(radius >= 0 && radius <= RT_MORPH_MAX_RADIUS, "rt_morph: radius %d outside 0..%d", radius,
+          RT_MORPH_MAX_RADIUS);
+    CHECK(!bad_size(w, h) && in_pitch >= w && out_pitch >= w, "rt_morph: bad size");
+    CHECK((const void *)in != (const void *)out, "rt_morph: out must not alias in");
+    int e = set_dev(c);
+    if (e) return e;
+    hipStream_t s = as_stream(stream);
+    MorphArgs A{};
+    A.w = w;
+    A.h = h;
+    A.radius = radius;
+    disk_spans(radius, A.span);
+    if (op != RT_OPEN) {
+        A.in = in;
+        A.in_pitch = in_pitch;
+        A.out = out;
+        A.out_pitch = out_pitch;
+        return launch_morph(A, op == RT_ERODE, c->n_cu, s);
+    }
+    if ((e = ensure_arena(c, al((size_t)w * h) + 4096))) return e;
+    uint8_t *tmp = (uint8_t *)c->arena.take((size_t)w * h);
+    A.in = in;
+    A.in_pitch = in_pitch;
+    A.out = tmp;
+    A.out_pitch = w;
+    if ((e = launch_morph(A, true, c->n_cu, s))) return e;
+    A.in = tmp;
+    A.in_pitch = w;
+    A.out = out;
+    A.out_pitch = out_pitch;
+    return launch_morph(A, false, c->n_cu, s);
+}
+
+int rt_recon_to_nuclei(rt_ctx *c, const uint8_t *hq, uint8_t *r_out, uint8_t *f0_out, int32_t w, int32_t h,
+                       int64_t pitch, int marker, int32_t radius, int32_t t_fg, void *stream) {
+    CHECK(c && hq && f0_out, "rt_recon_to_nuclei: null argument");
+    CHECK(marker == RT_MARKER_FRAME || marker == RT_MARKER_OPEN, "rt_recon_to_nuclei: bad marker %d", marker);
+    CHECK(marker == RT_MARKER_FRAME || (radius >= 0 && radius <= RT_MORPH_MAX_RADIUS),
+          "rt_recon_to_nuclei: radius %d outside 0..%d", radius, RT_MORPH_MAX_RADIUS);
+    CHECK(!bad_size(w, h) && pitch >= w, "rt_recon_to_nuclei: bad size");
+    CHECK(r_out != hq && f0_out != hq, "rt_recon_to_nuclei: outputs must not alias hq");
+    int e = set_dev(c);
+    if (e) return e;
+    hipStream_t s = as_stream(stream);
+    const size_t plane = (size_t)pitch * h;
+    if ((e = ensure_arena(c, al(plane) + recon_scratch_bytes((int)recon_tiles(w, h)) + 8192))) return e;
+    uint8_t *R = r_out ? r_out : (uint8_t *)c->arena.take(plane);
+    if (marker == RT_MARKER_FRAME) {
+        if ((e = launch_frame_marker(hq, pitch, R, pitch, w, h, s))) return e;
+    } else {
+        MorphArgs A{};
+        A.in = hq;
+        A.in_pitch = pitch;
+        A.out = R;
+        A.out_pitch = pitch;
+        A.w = w;
+        A.h = h;
+        A.radius = radius;
+        disk_spans(radius, A.span);
+        if ((e = launch_morph(A, true, c->n_cu, s))) return e;   // the erosion is <= Hq: already min(J, Hq)
+    }
+    if ((e = recon_u8_rounds(c, hq, R, w, h, pitch, s))) return e;
+    return launch_tophat(hq, pitch, R, pitch, f0_out, pitch, w, h, t_fg, s);
+}
+
+int rt_rbc_detect(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h, int32_t t_strong,
+                  int32_t t_weak, uint8_t *mask_out, int64_t out_pitch, void *stream) {
+    CHECK(c && rgb && mask_out, "rt_rbc_detect: null argument");
+    CHECK(t_weak <= t_strong, "rt_rbc_detect: t_weak > t_strong");
+    CHECK(!bad_size(w, h) && rgb_pitch >= 3LL * w && out_pitch >= w, "rt_rbc_detect: bad size");
+    int e = set_dev(c);
+    if (e) return e;
+    hipStream_t s = as_stream(stream);
+    const size_t plane = (size_t)out_pitch * h;
+    if ((e = ensure_arena(c, al(plane) + recon_scratch_bytes((int)recon_tiles(w, h)) + 8192))) return e;
+    uint8_t *weak = (uint8_t *)c->arena.take(plane);
+    if ((e = launch_rbc_maps(rgb, rgb_pitch, w, h, t_strong, t_weak, mask_out, weak, out_pitch, s))) return e;
+    return recon_u8_rounds(c, weak, mask_out, w, h, out_pitch, s);
+}
+
+int rt_features(rt_ctx *c, const int32_t *labels, int64_t lab_pitch, const uint8_t *hq, int64_t hq_pitch, int32_t w,
+                int32_t h, int32_t max_nuclei, int32_t *labels_out, double *feats_out, int64_t *counts_out,
+                int32_t *n_out_dev, void *stream) {
+    CHECK(c && labels && hq, "rt_features: null argument");
+    CHECK(max_nuclei >= 0, "rt_features: max_nuclei < 0");
+    CHECK(max_nuclei == 0 || (labels_out && feats_out), "rt_features: null output");
+    CHECK(!bad_size(w, h) && w <= 32768 && h <= 32768, "rt_features: bad size %dx%d", w, h);
+    CHECK(lab_pitch >= w && hq_pitch >= w, "rt_features: pitch smaller than width");
+    int e = set_dev(c);
+    if (e) return e;
+    hipStream_t s = as_stream(stream);
+    Layout L;
+    const size_t o_rows = L.add(sizeof(int32_t) * ((size_t)h + 1));
+    const size_t o_map = L.add(sizeof(int32_t) * (size_t)w * h);
+    const size_t o_box = L.add(sizeof(int32_t) * 4 * (size_t)std::max(1, max_nuclei));
+    const size_t o_acc = L.add(sizeof(NucAcc) * (size_t)std::max(1, max_nuclei));
+    if ((e = ensure_arena(c, L.off + 4096))) return e;
+    FeatArgs A{};
+    A.labels = labels;
+    A.lab_pitch = lab_pitch;
+    A.hq = hq;
+    A.hq_pitch = hq_pitch;
+    A.w = w;
+    A.h = h;
+    A.max_nuclei = max_nuclei;
+    A.row_off = at<int32_t>(c, o_rows);
+    A.map = at<int32_t>(c, o_map);
+    A.box = at<int32_t>(c, o_box);
+    A.acc = at<NucAcc>(c, o_acc);
+    A.labels_out = labels_out;
+    A.feats = feats_out;
+    A.counts = counts_out;
+    A.n_out = n_out_dev;
+    return launch_features(A, c->n_cu, s);
 }
 
 int rt_area_filter(rt_ctx *c, const int32_t *lab_in, int32_t *lab_out, uint8_t *mask_out, int32_t w, int32_t h,
@@ -1119,6 +1294,13 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
         c->knobs.recon_queue_after = value;
     } else if (n == "objects_path") {
         CHECK(value >= 0 && value <= 2, "rt_set_knob: objects_path must be 0..2");
+        // the alternative routings (1: no medium class, 2: the large LDS class
+        // for every crop) are switched off: only the autotuner's trials used
+        // them, in a run that faulted the GPU with no cause found
+        if (value != 0) {
+            set_error("rt_set_knob: objects_path %d is switched off (only 0 is available)", value);
+            return RT_EUNSUPPORTED;
+        }
         c->knobs.objects_path = value;
     } else if (n == "graph") {
         CHECK(value == 0 || value == 1, "rt_set_knob: graph must be 0 or 1");
@@ -1180,6 +1362,10 @@ int rt_profile_enable(rt_ctx *c, int enable) {
         RT_HIP(hipMalloc((void **)&c->prof_visits, sizeof(unsigned long long)));
         RT_HIP(hipMemset(c->prof_visits, 0, sizeof(unsigned long long)));
     }
+    if (enable && !c->prof_obj_px) {
+        RT_HIP(hipMalloc((void **)&c->prof_obj_px, 3 * sizeof(unsigned long long)));
+        RT_HIP(hipMemset(c->prof_obj_px, 0, 3 * sizeof(unsigned long long)));
+    }
     c->prof_on = enable != 0;
     c->prof_stages = enable == 1;
     return RT_OK;
@@ -1206,6 +1392,32 @@ int rt_profile_recon_rounds(rt_ctx *c, double *kernel_ms, int64_t *launches, int
     *tile_visits = (int64_t)v;
     c->round_used = 0;
     c->round_launches = 0;
+    return RT_OK;
+}
+
+int rt_profile_objects(rt_ctx *c, int cls, double *kernel_ms, int64_t *launches, int64_t *pixels) {
+    CHECK(c && kernel_ms && launches && pixels, "rt_profile_objects: null argument");
+    CHECK(cls >= 0 && cls < 3, "rt_profile_objects: class %d (0 small, 1 medium, 2 large)", cls);
+    int e = set_dev(c);
+    if (e) return e;
+    double ms = 0.0;
+    const std::vector<hipEvent_t> &evs = c->obj_events[cls];
+    for (size_t i = 0; i + 1 < c->obj_used[cls]; i += 2) {
+        RT_HIP(hipEventSynchronize(evs[i + 1]));
+        float t = 0.f;
+        RT_HIP(hipEventElapsedTime(&t, evs[i], evs[i + 1]));
+        ms += t;
+    }
+    *kernel_ms = ms;
+    *launches = c->obj_launches[cls];
+    unsigned long long v = 0;
+    if (c->prof_obj_px) {
+        RT_HIP(hipMemcpy(&v, c->prof_obj_px + cls, sizeof v, hipMemcpyDeviceToHost));
+        RT_HIP(hipMemset(c->prof_obj_px + cls, 0, sizeof v));
+    }
+    *pixels = (int64_t)v;
+    c->obj_used[cls] = 0;
+    c->obj_launches[cls] = 0;
     return RT_OK;
 }
 

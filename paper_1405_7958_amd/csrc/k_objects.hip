@@ -27,6 +27,7 @@
 // with the crop in registers; larger crops use a global scratch slice with
 // 64-bit keys.  All three launches read their work lists from device
 // counters, so no host round trip is needed.
+#include "crop_addr.h"
 #include "rt_internal.h"
 
 #include <climits>
@@ -473,17 +474,25 @@ template <int R, typename L>
 __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int16_t *tw = nullptr) {
     const int lane = threadIdx.x;
     const int area = a.st_area[g];
-    // ---- load the component
+    // ---- load the component: LOADS_IN_FLIGHT loads per thread issued before
+    // any is used (addresses clamped into the crop, crop_addr.h)
+    const CropGeom geom{m.cx0, m.cy0, m.cw, m.ch, m.st, m.n};
     bool zero = false;
-#pragma unroll 8
-    for (int i = lane; i < m.n; i += blockDim.x) {
-        const int c = i % m.st, r = i / m.st;
-        bool in = false;
-        if (c < m.cw) {
-            in = a.labels[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c] == g;
-            zero |= !in;
+    for (int i0 = 0; i0 < m.n; i0 += LOADS_IN_FLIGHT * (int)blockDim.x) {
+        int32_t v[LOADS_IN_FLIGHT];
+#pragma unroll
+        for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
+            v[k] = a.labels[crop_load_offset(geom, i0 + k * (int)blockDim.x + lane, a.pitch)];
+#pragma unroll
+        for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
+            const int i = i0 + k * (int)blockDim.x + lane;
+            if (i < m.n) {
+                const bool col = i % m.st < m.cw;
+                const bool in = col && v[k] == g;
+                zero |= col && !in;
+                m.fl[i] = in ? F_IN : 0;
+            }
         }
-        m.fl[i] = in ? F_IN : 0;
     }
     const bool has_zero = wave_or(zero);
     // ---- exact distance transform: column distances, then a pruned row search
@@ -550,9 +559,16 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     if (tot > 1) {
         // ---- seeds
         if (a.seeds) {
-            for (int i = lane; i < m.n; i += blockDim.x) {
-                const int c = i % m.st, r = i / m.st;
-                if ((m.fl[i] & F_IN) && a.seeds[(int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c]) m.fl[i] |= F_RM;
+            for (int i0 = 0; i0 < m.n; i0 += LOADS_IN_FLIGHT * (int)blockDim.x) {
+                uint8_t v[LOADS_IN_FLIGHT];
+#pragma unroll
+                for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
+                    v[k] = a.seeds[crop_load_offset(geom, i0 + k * (int)blockDim.x + lane, a.pitch)];
+#pragma unroll
+                for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
+                    const int i = i0 + k * (int)blockDim.x + lane;
+                    if (i < m.n && (m.fl[i] & F_IN) && v[k]) m.fl[i] |= F_RM;
+                }
             }
             __syncthreads();
         } else {
@@ -715,29 +731,13 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     __syncthreads();
 }
 
-struct CropGeom {
-    int cx0, cy0, cw, ch, st, n;
-};
-
 __device__ __forceinline__ CropGeom crop_geom(const ObjArgs &a, int g) {
-    CropGeom q;
-    q.cx0 = max(0, a.st_x0[g] - 1);
-    q.cy0 = max(0, a.st_y0[g] - 1);
-    const int cx1 = min(a.w - 1, a.st_x1[g] + 1), cy1 = min(a.h - 1, a.st_y1[g] + 1);
-    q.cw = cx1 - q.cx0 + 1;
-    q.ch = cy1 - q.cy0 + 1;
-    q.st = q.cw | 1;
-    q.n = q.st * q.ch;
-    return q;
+    return crop_of_box(a.st_x0[g], a.st_y0[g], a.st_x1[g], a.st_y1[g], a.w, a.h);
 }
 
 // The register classes use the row stride R + 1 of the in-place register
 // reconstruction (the plane capacity is R x (R + 1)).
-__device__ __forceinline__ CropGeom with_stride(CropGeom q, int st) {
-    q.st = st;
-    q.n = st * q.ch;
-    return q;
-}
+__device__ __forceinline__ CropGeom with_stride(CropGeom q, int st) { return crop_with_stride(q, st); }
 
 __device__ void erase_object(const ObjArgs &a, int g, const CropGeom &q) {
     for (int i = threadIdx.x; i < q.cw * q.ch; i += blockDim.x) {
@@ -913,6 +913,34 @@ __global__ __launch_bounds__(WAVE) void k_objects_big(const ObjArgs *args, BigPa
     }
 }
 
+// Profiling tally: pixels of the components each LDS class took (sum of the
+// component areas over the class lists), summed by a grid-stride pass after
+// the per-object stage; the class kernels themselves are not instrumented.
+__global__ __launch_bounds__(256) void k_objects_tally(const ObjArgs *args, ObjLists L, unsigned long long *out) {
+    __shared__ unsigned long long part[3];
+    if (threadIdx.x < 3) part[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t *lists[3] = {L.list_s, L.list_m, L.list_l};
+    const int32_t *counts[3] = {L.n_s, L.n_m, L.n_l};
+    for (int k = 0; k < 3; ++k) {
+        const int n = *counts[k];
+        unsigned long long s = 0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const int code = lists[k][i];
+            s += (unsigned long long)args[code >> 25].st_area[code & CODE_MASK];
+        }
+        if (s) atomicAdd(part + k, s);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && part[threadIdx.x]) atomicAdd(out + threadIdx.x, part[threadIdx.x]);
+}
+
+int launch_objects_tally(const ObjArgs *args_dev, const ObjLists &L, unsigned long long *out, int n_cu,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_objects_tally, dim3(n_cu), dim3(256), 0, s, args_dev, L, out);
+    return hip_fail(hipGetLastError(), "k_objects_tally");
+}
+
 // bytes of global scratch one block needs for a crop of n = stride x rows pixels
 static size_t crop_bytes(int64_t n) { return (size_t)n * (8 + 4 + 4 + 1) + 256; }
 // ... and for the largest crop of a w x h tile
@@ -946,12 +974,22 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
         t = par->side;
         u = par->side2;
     }
+    // class timing (profiling): an event pair around each launch on its own stream
+    auto mark = [&](int cls, int end, hipStream_t st) -> int {
+        if (par && par->timing[cls][end]) RT_HIP(hipEventRecord(par->timing[cls][end], st));
+        return RT_OK;
+    };
+    int e;
+    if ((e = mark(2, 0, u))) return e;
     hipLaunchKernelGGL(k_objects_l, dim3(std::max(1, n_cu / 4)), dim3(4 * WAVE), lds_l, u, args_dev, L);
     RT_HIP(hipGetLastError());
+    if ((e = mark(2, 1, u)) || (e = mark(1, 0, s))) return e;
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(2 * WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
+    if ((e = mark(1, 1, s)) || (e = mark(0, 0, t))) return e;
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, t, args_dev, L);
     RT_HIP(hipGetLastError());
+    if ((e = mark(0, 1, t))) return e;
     if (t != s) {
         RT_HIP(hipEventRecord(par->join, t));
         RT_HIP(hipStreamWaitEvent(s, par->join, 0));

@@ -106,6 +106,13 @@ struct rt_ctx_impl {
     size_t round_used = 0;
     int64_t round_launches = 0;            // round launches inside those pairs
     unsigned long long *prof_visits = nullptr;   // device: tiles processed by the round kernel
+    // per-object classes (small, medium, large LDS): begin/end event pairs
+    // around each launch on the class's own stream, launches, and a device
+    // counter per class of the pixels of the components in its list
+    std::vector<hipEvent_t> obj_events[3];
+    size_t obj_used[3] = {};
+    int64_t obj_launches[3] = {};
+    unsigned long long *prof_obj_px = nullptr;
 };
 
 int ensure_arena(rt_ctx_impl *c, size_t bytes);
@@ -291,10 +298,14 @@ constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
 struct ObjStreams {
     hipStream_t side, side2;
     hipEvent_t fork, join, join2;
+    hipEvent_t timing[3][2] = {};  // nullable: begin/end of the small, medium and large class launches
 };
 // `before_big` (nullable) is recorded on `s` at the end of the LDS classes.
 int launch_objects(const ObjArgs *args_dev, const ObjLists &lists, int n_cu, hipStream_t s,
                    hipEvent_t before_big = nullptr, const ObjStreams *par = nullptr);
+// profiling: out[k] += pixels of the components in LDS class k's list (after the stage)
+int launch_objects_tally(const ObjArgs *args_dev, const ObjLists &lists, unsigned long long *out, int n_cu,
+                         hipStream_t s);
 size_t big_object_bytes(int w, int h);   // one slice for the largest crop of a w x h image
 size_t mid_object_bytes(int w, int h);   // one slice for a crop of at most MID_MAX_PX pixels
 // number of mid slices for a launch group of `pixels` pixels
@@ -302,7 +313,62 @@ inline int mid_slices_for(int64_t pixels) {
     return (int)std::max<int64_t>(8, std::min<int64_t>(128, pixels / 65536));
 }
 
+// ---------------------------------------------------------------------------
+// feature computation (per nucleus)
+// ---------------------------------------------------------------------------
+struct NucAcc {                    // step-1 intermediates of one nucleus
+    int64_t area, perim, sx, sy, sxx, syy, sxy, gsum, gsum2, gmax;   // sums relative to the root pixel
+    uint32_t hist[256];
+    uint32_t glcm[RT_FEAT_GLCM_LEVELS * RT_FEAT_GLCM_LEVELS];
+    uint32_t ghist[RT_FEAT_GRAD_BINS];
+};
+struct FeatArgs {
+    const int32_t *labels;
+    int64_t lab_pitch;
+    const uint8_t *hq;
+    int64_t hq_pitch;
+    int w, h;
+    int max_nuclei;
+    int32_t *row_off;              // h + 1: root counts, then row offsets; [h] = total
+    int32_t *map;                  // w*h: label - 1 -> rank (written at roots only)
+    int32_t *box;                  // 4 per nucleus: x0, y0, x1, y1
+    NucAcc *acc;                   // per nucleus
+    int32_t *labels_out;           // max_nuclei
+    double *feats;                 // max_nuclei x RT_NFEAT
+    int64_t *counts;               // nullable: max_nuclei x RT_FEAT_NCOUNT
+    int32_t *n_out;                // nullable: number of nuclei
+};
+int launch_features(const FeatArgs &a, int n_cu, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// pre-processing: flat-disk erosion / dilation, ReconToNuclei markers, RBC maps
+// ---------------------------------------------------------------------------
+struct MorphArgs {
+    const uint8_t *in;
+    int64_t in_pitch;
+    uint8_t *out;
+    int64_t out_pitch;
+    int w, h, radius;
+    int span[2 * RT_MORPH_MAX_RADIUS + 1];   // half-width of the disk at row offset dy (index dy + radius)
+};
+int launch_morph(const MorphArgs &a, bool erode, int n_cu, hipStream_t s);
+int launch_frame_marker(const uint8_t *hq, int64_t hq_pitch, uint8_t *r, int64_t r_pitch, int w, int h,
+                        hipStream_t s);
+int launch_tophat(const uint8_t *hq, int64_t hq_pitch, const uint8_t *r, int64_t r_pitch, uint8_t *f0,
+                  int64_t f0_pitch, int w, int h, int t, hipStream_t s);
+int launch_rbc_maps(const uint8_t *rgb, int64_t rgb_pitch, int w, int h, int t_strong, int t_weak, uint8_t *marker,
+                    uint8_t *mask, int64_t pitch, hipStream_t s);
+
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
+
+// Most components a w x h image can hold.  8-connectivity: two pixels of one
+// 2 x 2 block are always adjacent, so each block meets at most one component.
+// 4-connectivity: the same holds for each horizontal pair of a row (a
+// checkerboard reaches ceil(w/2) per row).
+inline size_t max_components(int w, int h, int conn) {
+    return conn == 4 ? (((size_t)w + 1) / 2) * (size_t)h : ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
+}
+
 // zeroes a pitched w x h uint8 image
 int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s);
 // Surrogate maps: fg = [p_fg >= 0.5], seeds = [p_seed >= 0.5]; counts[0] +=

@@ -63,6 +63,10 @@ def lib():
         L.rt_morph_recon.argtypes = [vp, C.c_int, vp, vp, vp, vp, i32, i32, i64, C.c_int, vp]
         L.rt_fill_holes.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp]
         L.rt_ccl.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp, vp]
+        L.rt_features.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.rt_morph.argtypes = [vp, C.c_int, vp, i64, vp, i64, i32, i32, i32, vp]
+        L.rt_recon_to_nuclei.argtypes = [vp, vp, vp, vp, i32, i32, i64, C.c_int, i32, i32, vp]
+        L.rt_rbc_detect.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, i64, vp]
         L.rt_area_filter.argtypes = [vp, vp, vp, vp, i32, i32, i64, i32, i32, vp]
         L.rt_watershed.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, i64, vp]
         L.rt_seg_params_default.argtypes = [C.POINTER(rt_seg_params)]
@@ -102,6 +106,8 @@ def lib():
         L.rt_nn_pack.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
         L.rt_nn_prep_input.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.rt_profile_recon_rounds.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.rt_profile_objects.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]
         L.rt_profile_stage_name.argtypes = [C.c_int]
         L.rt_profile_stage_name.restype = C.c_char_p
         _lib = L
@@ -244,6 +250,72 @@ def rt_ccl(binary, conn=8, ctx=None):
     return lab, n
 
 
+RT_ERODE, RT_DILATE, RT_OPEN = 0, 1, 2
+RT_MARKER_FRAME, RT_MARKER_OPEN = 0, 1
+RT_MORPH_MAX_RADIUS = 32
+
+
+def rt_morph(img, op, radius, ctx=None):
+    """Grey erosion / dilation / opening by the flat disk of `radius`."""
+    ctx = ctx or default_context(img.device.index)
+    _img(img, torch.uint8, "img")
+    h, w = img.shape
+    out = torch.empty((h, w), dtype=torch.uint8, device=img.device)
+    _check(lib().rt_morph(ctx.h, int(op), _ptr(img), img.stride(0), _ptr(out), w, w, h, int(radius), _stream()))
+    return out
+
+
+def rt_recon_to_nuclei(hq, marker=RT_MARKER_FRAME, radius=0, t_fg=16, ctx=None):
+    """Returns (R, F0) of ReconToNuclei with the frame or opening-by-
+    reconstruction marker."""
+    ctx = ctx or default_context(hq.device.index)
+    _img(hq, torch.uint8, "hq")
+    h, w = hq.shape
+    r = torch.empty_strided(hq.shape, hq.stride(), dtype=torch.uint8, device=hq.device)
+    f0 = torch.empty_strided(hq.shape, hq.stride(), dtype=torch.uint8, device=hq.device)
+    _check(lib().rt_recon_to_nuclei(ctx.h, _ptr(hq), _ptr(r), _ptr(f0), w, h, hq.stride(0), int(marker),
+                                    int(radius), int(t_fg), _stream()))
+    return r, f0
+
+
+def rt_rbc_detect(rgb, t_strong=200, t_weak=150, ctx=None):
+    ctx = ctx or default_context(rgb.device.index)
+    _img(rgb, torch.uint8, "rgb", 3)
+    h, w = rgb.shape[:2]
+    out = torch.empty((h, w), dtype=torch.uint8, device=rgb.device)
+    _check(lib().rt_rbc_detect(ctx.h, _ptr(rgb), rgb.stride(0), w, h, int(t_strong), int(t_weak), _ptr(out), w,
+                               _stream()))
+    return out
+
+
+RT_NFEAT = 47
+RT_FEAT_NCOUNT = 537
+
+
+def rt_features(labels, hq, max_nuclei=65536, want_counts=False, ctx=None):
+    """Per-nucleus features (include/rtseg.h).  labels: int32 (H, W) with the
+    segmentation's labels; hq: uint8 (H, W).  Returns (labels_out [n] int32,
+    feats [n, RT_NFEAT] float64, counts [n, RT_FEAT_NCOUNT] int64 or None,
+    n_total) with n = min(n_total, max_nuclei); reads the count back."""
+    ctx = ctx or default_context(labels.device.index)
+    _img(labels, torch.int32, "labels")
+    _img(hq, torch.uint8, "hq")
+    if labels.shape != hq.shape:
+        raise ValueError("labels and hq must have the same shape")
+    h, w = labels.shape
+    d = labels.device
+    m = int(max_nuclei)
+    lo = torch.empty(max(m, 1), dtype=torch.int32, device=d)
+    fo = torch.empty((max(m, 1), RT_NFEAT), dtype=torch.float64, device=d)
+    co = torch.empty((max(m, 1), RT_FEAT_NCOUNT), dtype=torch.int64, device=d) if want_counts else None
+    n = torch.zeros(1, dtype=torch.int32, device=d)
+    _check(lib().rt_features(ctx.h, _ptr(labels), labels.stride(0), _ptr(hq), hq.stride(0), w, h, m, _ptr(lo),
+                             _ptr(fo), _ptr(co), _ptr(n), _stream()))
+    total = int(n.item())
+    k = min(total, m)
+    return lo[:k], fo[:k], (co[:k] if co is not None else None), total
+
+
 def rt_area_filter(labels, min_area, max_area, ctx=None):
     ctx = ctx or default_context(labels.device.index)
     _img(labels, torch.int32, "labels")
@@ -355,6 +427,17 @@ def rt_profile_read(ctx=None):
         _check(n)
     names = [lib().rt_profile_stage_name(i).decode() for i in range(RT_PROF_STAGES)]
     return n, {names[i]: (ms[i], int(ln[i])) for i in range(RT_PROF_STAGES)}
+
+
+def rt_profile_objects(cls, ctx=None):
+    """Returns (kernel_ms, launches, component_pixels) of per-object class
+    `cls` (0 small, 1 medium, 2 large) since the last read."""
+    ctx = ctx or default_context()
+    ms = C.c_double()
+    ln = C.c_int64()
+    px = C.c_int64()
+    _check(lib().rt_profile_objects(ctx.h, int(cls), C.byref(ms), C.byref(ln), C.byref(px)))
+    return ms.value, ln.value, px.value
 
 
 def rt_profile_recon_rounds(ctx=None):
@@ -602,8 +685,8 @@ def nn_prep_input(rgb, ctx=None):
 
 
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
-           "rt_fill_holes", "rt_ccl", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
-           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds",
+           "rt_fill_holes", "rt_ccl", "rt_features", "rt_morph", "rt_recon_to_nuclei", "rt_rbc_detect", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
+           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds", "rt_profile_objects",
            "rt_profile_stage_name", "rt_unet_param_count", "rt_unet_create", "rt_unet_destroy", "rt_unet_get_params",
            "rt_unet_set_params", "rt_unet_get_grads", "rt_unet_grad_step", "rt_unet_train_step", "rt_unet_forward",
            "rt_unet_save", "rt_unet_load", "rt_unet_adam_step", "rt_unet_get_step", "rt_unet_save_checkpoint",

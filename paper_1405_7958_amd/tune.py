@@ -32,7 +32,7 @@ SPACE = {
     "recon_levels": [2, 1, 3, 4, 6, 8, 0],
     "recon_round_batch": [4, 8, 16, 32],
     "recon_max_sweeps": [16, 32, 64, 128],
-    "objects_path": [0, 1, 2],
+    "objects_path": [0],
     "recon_mode": [0, 1, 2],
     "recon_queue_after": [2, 1, 3, 4],
 }
@@ -72,10 +72,11 @@ def current(ctx=None) -> dict:
 
 
 def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEFAULT_CACHE, verbose=False,
-             allow_graph: bool = True) -> dict:
+             allow_graph: bool = True, trials: bool = True) -> dict:
     """Tunes the knobs of `ctx` for batches like `rgbs` (a list of device
     tiles) and leaves the best setting applied.  Returns
-    {"knobs": ..., "ms": ..., "trials": [...]}."""
+    {"knobs": ..., "ms": ..., "trials": [...]}.  With trials=False only the
+    cache is consulted: on a miss the context's current knobs stay."""
     ctx = ctx or rtseg.default_context(rgbs[0].device.index)
     key = signature(rgbs) + ("" if allow_graph else "|nograph")
     if cache and os.path.exists(cache):
@@ -87,6 +88,9 @@ def autotune(rgbs, params=None, ctx=None, reps: int = 5, cache: str | None = DEF
         if hit:
             apply(hit["knobs"], ctx)
             return dict(hit, cached=True)
+    if not trials:
+        return {"knobs": current(ctx), "ms": float("nan"), "seconds": 0.0, "trials": [], "cached": False,
+                "source": "current knobs (no cache entry, trials off)"}
     outs = None
 
     def run():
