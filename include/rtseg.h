@@ -110,6 +110,26 @@ int rt_fill_holes(rt_ctx *ctx, const uint8_t *in, uint8_t *out, int32_t w, int32
 int rt_ccl(rt_ctx *ctx, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
            int32_t *n_out_dev, void *stream);
 
+/*
+ * rt_ccl without allocation, for callers that cannot allocate memory during a
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, definition and output as rt_ccl.  Its
+ * scratch (an argument record, the union-find array of 4 (w*h + 1) bytes
+ * and, when n_out_dev is given, a component list) lives in one fixed device
+ * array of RT_NOALLOC_SCRATCH_BYTES bytes, which every device the library
+ * runs on holds until the process ends; the array's device address is
+ * looked up when a context is first created on the device.  The call makes
+ * no hipMalloc, hipFree, pinned-memory or other allocating call and no
+ * memset (counters are cleared by a kernel).
+ * Limits: w*h <= RT_NOALLOC_MAX_PIXELS (e.g. 2048 x 2048); larger images
+ * return RT_EINVAL with a message.  Every call on one device shares the
+ * array: calls that overlap on one device (two streams, two host threads,
+ * two contexts) race and must be serialised by the caller.
+ */
+#define RT_NOALLOC_SCRATCH_BYTES (32 << 20)
+#define RT_NOALLOC_MAX_PIXELS (1 << 22)
+int rt_ccl_noalloc(rt_ctx *ctx, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch,
+                   int conn, int32_t *n_out_dev, void *stream);
 
 /*
  * AreaThreshold (Sec. 5.1): a component (pixels sharing one positive label)

@@ -704,6 +704,11 @@ int rt_ctx_create(int device, rt_ctx **out) {
     c->device = device;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    // device address of the fixed scratch array of rt_ccl_noalloc (once per device)
+    if (int e = noalloc_init_device(device)) {
+        delete c;
+        return e;
+    }
     if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void **)&c->lut, 768 * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
@@ -866,6 +871,16 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     Stager sg{c};
     if ((e = sg.put(std::vector<CclArgs>{A}, o_args)) || (e = sg.flush(s))) return e;
     return launch_ccl(at<CclArgs>(c, o_args), 1, ccl_tiles(w, h), c->n_cu, s, CclPred::NonZero, CclOut::Labels);
+}
+
+int rt_ccl_noalloc(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h, int64_t pitch, int conn,
+                   int32_t *n_out_dev, void *stream) {
+    CHECK(c && mask && labels, "rt_ccl_noalloc: null argument");
+    CHECK(conn == 4 || conn == 8, "rt_ccl_noalloc: conn must be 4 or 8");
+    CHECK(!bad_size(w, h) && pitch >= w, "rt_ccl_noalloc: bad size");
+    int e = set_dev(c);
+    if (e) return e;
+    return ccl_noalloc(c->device, c->n_cu, mask, labels, w, h, pitch, conn, n_out_dev, as_stream(stream));
 }
 
 namespace {

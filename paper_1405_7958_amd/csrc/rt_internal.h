@@ -369,6 +369,13 @@ inline size_t max_components(int w, int h, int conn) {
     return conn == 4 ? (((size_t)w + 1) / 2) * (size_t)h : ((size_t)w / 2 + 1) * ((size_t)h / 2 + 1);
 }
 
+// BWLabel on the fixed device array of noalloc.hip (no allocation).  The
+// array's device address is looked up by noalloc_init_device, once per
+// device, with that device current.
+int noalloc_init_device(int device);
+size_t noalloc_ccl_bytes(int w, int h, int conn, bool want_count);
+int ccl_noalloc(int device, int n_cu, const uint8_t *mask, int32_t *labels, int w, int h, int64_t pitch, int conn,
+                int32_t *n_out_dev, hipStream_t s);
 // zeroes a pitched w x h uint8 image
 int launch_zero_u8(uint8_t *p, int64_t pitch, int w, int h, hipStream_t s);
 // Surrogate maps: fg = [p_fg >= 0.5], seeds = [p_seed >= 0.5]; counts[0] +=

@@ -63,6 +63,7 @@ def lib():
         L.rt_morph_recon.argtypes = [vp, C.c_int, vp, vp, vp, vp, i32, i32, i64, C.c_int, vp]
         L.rt_fill_holes.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp]
         L.rt_ccl.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp, vp]
+        L.rt_ccl_noalloc.argtypes = [vp, vp, vp, i32, i32, i64, C.c_int, vp, vp]
         L.rt_features.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
         L.rt_morph.argtypes = [vp, C.c_int, vp, i64, vp, i64, i32, i32, i32, vp]
         L.rt_recon_to_nuclei.argtypes = [vp, vp, vp, vp, i32, i32, i64, C.c_int, i32, i32, vp]
@@ -248,6 +249,23 @@ def rt_ccl(binary, conn=8, ctx=None):
     n = torch.zeros(1, dtype=torch.int32, device=binary.device)
     _check(lib().rt_ccl(ctx.h, _ptr(binary), _ptr(lab), w, h, binary.stride(0), conn, _ptr(n), _stream()))
     return lab, n
+
+
+def rt_ccl_noalloc(binary, labels, n_out=None, conn=8, ctx=None):
+    """rt_ccl with the library's fixed device scratch array: writes into the
+    caller's `labels` (int32, same shape and pitch as `binary`) and, when
+    given, the 1-element int32 device tensor `n_out`; allocates nothing."""
+    ctx = ctx or default_context(binary.device.index)
+    _img(binary, torch.uint8, "binary")
+    _img(labels, torch.int32, "labels")
+    if labels.shape != binary.shape or labels.stride(0) != binary.stride(0):
+        raise ValueError("labels must share shape and pitch with binary")
+    if n_out is not None and (n_out.dtype != torch.int32 or not n_out.is_cuda or n_out.numel() < 1):
+        raise ValueError("n_out must be an int32 device tensor")
+    h, w = binary.shape
+    _check(lib().rt_ccl_noalloc(ctx.h, _ptr(binary), _ptr(labels), w, h, binary.stride(0), conn,
+                                _ptr(n_out) if n_out is not None else None, _stream()))
+    return labels, n_out
 
 
 RT_ERODE, RT_DILATE, RT_OPEN = 0, 1, 2
@@ -685,7 +703,7 @@ def nn_prep_input(rgb, ctx=None):
 
 
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
-           "rt_fill_holes", "rt_ccl", "rt_features", "rt_morph", "rt_recon_to_nuclei", "rt_rbc_detect", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
+           "rt_fill_holes", "rt_ccl", "rt_ccl_noalloc", "rt_features", "rt_morph", "rt_recon_to_nuclei", "rt_rbc_detect", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
            "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds", "rt_profile_objects",
            "rt_profile_stage_name", "rt_unet_param_count", "rt_unet_create", "rt_unet_destroy", "rt_unet_get_params",
            "rt_unet_set_params", "rt_unet_get_grads", "rt_unet_grad_step", "rt_unet_train_step", "rt_unet_forward",
