@@ -15,7 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "rt_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "features_oracle.c"), os.path.join(_HERE, "morph_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "features_oracle.c"), os.path.join(_HERE, "morph_oracle.c"),
+         os.path.join(_HERE, "stitch_oracle.c")]
 
 DQ_MAX = 65535
 
@@ -83,6 +84,8 @@ def lib():
         L.or_watershed.argtypes = [u8p, u8p, C.c_int, C.c_int, C.c_int, i32p, u8p, i32p, i32p, i32p, i32p]
         L.or_segment_from_hq.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          u8p, i32p, u8p, u8p, u8p, u8p]
+        L.or_stitch_from_hq.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                        C.c_int, i32p, u8p]
         L.or_erode.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
         L.or_dilate.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
         L.or_open.argtypes = [u8p, C.c_int, C.c_int, C.c_int, u8p]
@@ -321,3 +324,14 @@ def rbc_detect(rgb, t_strong=200, t_weak=150):
     out = np.empty((h, w), np.uint8)
     lib().or_rbc_detect(_p(a, C.c_uint8), w, h, int(t_strong), int(t_weak), _p(out, C.c_uint8))
     return out
+
+
+def stitch_from_hq(hq, tile, halo, t_fg=16, min_area=20, max_area=1000, h_seed=3):
+    """Cross-tile stitching (rt_oracle.h): returns (labels, mask, n_owned)."""
+    q = _u8(hq)
+    H, W = q.shape
+    lab = np.empty((H, W), np.int32)
+    mask = np.empty((H, W), np.uint8)
+    n = lib().or_stitch_from_hq(_p(q, C.c_uint8), W, H, int(tile), int(halo), int(t_fg), int(min_area),
+                                int(max_area), int(h_seed), _p(lab, C.c_int32), _p(mask, C.c_uint8))
+    return lab, mask, int(n)

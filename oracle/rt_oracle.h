@@ -228,6 +228,23 @@ void or_recon_to_nuclei(const uint8_t *hq, int w, int h, int marker_mode, int ra
                         uint8_t *f0_out);
 void or_rbc_detect(const uint8_t *rgb, int w, int h, int t_strong, int t_weak, uint8_t *mask_out);
 
+/* ------------------------------------------------------------------------
+ * Cross-tile stitching with ghost cells (Sec. 3.4: partitions of a data
+ * region are extended with ghost cells from their neighbours).  The slide
+ * (W x H, Hq given) is cut into tile x tile cores in row-major order (the
+ * last row and column ragged); each core is extended by `halo` pixels on
+ * every side, clipped at the slide edge, and the extended region is
+ * segmented on its own (or_segment_from_hq with the given parameters).  A
+ * core owns the nuclei of its extended result whose first pixel (the root of
+ * the label) lies inside the core; each owned nucleus is written into the
+ * slide label map with the slide label 1 + (slide row-major index of its
+ * first pixel).  Where owned nuclei of two cores cover the same pixel the
+ * smaller slide label is kept.  mask_out (nullable) = labels_out != 0.
+ * Returns the number of owned nuclei.
+ * ------------------------------------------------------------------------ */
+int or_stitch_from_hq(const uint8_t *hq, int W, int H, int tile, int halo, int t_fg, int min_area, int max_area,
+                      int h_seed, int32_t *labels_out, uint8_t *mask_out);
+
 #ifdef __cplusplus
 }
 #endif
