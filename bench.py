@@ -136,22 +136,28 @@ def batch64(rtseg, synth, torch, args):
     return out
 
 
-def stream4k(rtseg, synth, torch, args, knobs):
-    """rt_segment_batch over `args.stream4k_tiles` distinct 4096 x 4096 tiles
-    (the 4096 x 4096 workload's generator, seeds 0..n-1) per call, with the
-    knob set of the single 4096 x 4096 tile (no tuning trials)."""
+def distinct_4k_tiles(synth, torch, n):
+    """n distinct 4096 x 4096 tiles of the 4096 x 4096 workload's generator
+    (seeds 0..n-1), as pinned host tensors."""
     from concurrent.futures import ThreadPoolExecutor
-
-    from paper_1405_7958_amd import tune
-    d = torch.device("cuda", 0)
-    nt = args.stream4k_tiles
     base = synth.spec_4k(0)
     specs = [synth.TileSpec(w=base.w, h=base.h, seed=i, n_nuclei=base.n_nuclei, amin=base.amin, amax=base.amax,
                             cluster_frac=base.cluster_frac, cluster_min=base.cluster_min, cluster_max=base.cluster_max,
-                            jitter=base.jitter) for i in range(nt)]
-    log(f"generating {nt} distinct 4096x4096 tiles ...")
+                            jitter=base.jitter) for i in range(n)]
+    log(f"generating {n} distinct 4096x4096 tiles ...")
     with ThreadPoolExecutor(8) as ex:
-        rgbs = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
+        return list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).pin_memory(), specs))
+
+
+def stream4k(rtseg, synth, torch, args, knobs, host_tiles):
+    """rt_segment_batch over `args.stream4k_tiles` distinct 4096 x 4096 tiles
+    (the 4096 x 4096 workload's generator, seeds 0..n-1) per call, with the
+    knob set of the single 4096 x 4096 tile (no tuning trials)."""
+    from paper_1405_7958_amd import tune
+    d = torch.device("cuda", 0)
+    nt = len(host_tiles)
+    base = synth.spec_4k(0)
+    rgbs = [t.to(d) for t in host_tiles]
     ctx = rtseg.Context(0)
     if knobs:
         tune.apply(knobs, ctx)
@@ -175,6 +181,37 @@ def stream4k(rtseg, synth, torch, args, knobs):
            "working_set_mb": round(nt * base.w * base.h * (3 + 1 + 4) / 1e6, 1),
            "knobs": knobs, "knobs_source": "the 4096x4096 tile's knob set" if knobs else "defaults",
            "pipeline_floor_frac": round(8 * px / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 5)}
+    ctx.close()
+    return out
+
+
+def host_stream_leg(rtseg, torch, knobs, host_tiles, reps=2):
+    """rt_segment_host_stream over the distinct 4096 x 4096 tiles held in
+    pinned host memory: uploads (RGB), computation and downloads (mask,
+    labels, count) overlapped (depth 3) against one after the other (depth 1);
+    tiles/s with every host-device copy inside the timed region."""
+    from paper_1405_7958_amd import tune
+    ctx = rtseg.Context(0)
+    if knobs:
+        tune.apply(knobs, ctx)
+    n = len(host_tiles)
+    out = {"tiles_per_call": n, "reps": reps}
+    outs = None
+    for depth in (3, 1):
+        outs = rtseg.rt_segment_host_stream(host_tiles, depth=depth, ctx=ctx, outs=outs)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rtseg.rt_segment_host_stream(host_tiles, depth=depth, ctx=ctx, outs=outs)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        out[f"depth{depth}_tiles_per_s"] = round(n / sec, 2)
+        out[f"depth{depth}_ms_per_tile"] = round(sec * 1e3 / n, 3)
+        log(f"host stream depth {depth}: {n / sec:.1f} tiles/s ({sec * 1e3 / n:.2f} ms/tile, copies included)")
+    px = host_tiles[0].shape[0] * host_tiles[0].shape[1]
+    out["pcie_bytes_per_tile"] = px * (3 + 1 + 4) + 4
+    out["overlap_gain"] = round(out["depth3_tiles_per_s"] / out["depth1_tiles_per_s"], 3)
+    out["pcie_gbs_depth3"] = round(out["pcie_bytes_per_tile"] * out["depth3_tiles_per_s"] / 1e9, 2)
     ctx.close()
     return out
 
@@ -498,9 +535,12 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch64(rtseg, synth, torch, args)
-    s4k = None
+    s4k = hs = None
     if not args.no_stream4k:
-        s4k = stream4k(rtseg, synth, torch, args, knobs)
+        host_tiles = distinct_4k_tiles(synth, torch, args.stream4k_tiles)
+        s4k = stream4k(rtseg, synth, torch, args, knobs, host_tiles)
+        hs = host_stream_leg(rtseg, torch, knobs, host_tiles)
+        del host_tiles
     sur = None
     if not args.no_surrogate:
         sur = surrogate_leg(rtseg, synth, torch, args, ms_step)
@@ -530,6 +570,7 @@ def main():
         "roofline": roof,
         "batch64": batch,
         "stream4k": s4k,
+        "host_stream4k": hs,
         "surrogate": sur,
         "cpu_baseline": cpu,
     }

@@ -218,6 +218,57 @@ typedef struct {
 int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt_seg_params *params, void *stream);
 
 /*
+ * Cross-tile stitching with ghost cells (Sec. 3.4: partitions of a data
+ * region are extended by ghost cells from their neighbours, so that objects
+ * cut by a partition border are processed whole).  The slide (W x H RGB,
+ * device) is cut into tile x tile cores in row-major order (the last row and
+ * column ragged); each core is extended by `halo` pixels on every side
+ * (clipped at the slide edge) and the extended tile is segmented exactly as
+ * rt_segment_tile would (launch groups of up to 64 extended tiles, read in
+ * place from the slide).  A core owns the nuclei of its extended result whose
+ * first pixel (the root of the label) lies inside the core; each owned
+ * nucleus is written into labels_out with its slide label 1 + (slide
+ * row-major index of its first pixel), the smaller slide label winning where
+ * nuclei of two cores cover one pixel.  mask_out (nullable) = labels_out != 0;
+ * hq_out (nullable) receives the slide's quantised hematoxylin channel;
+ * n_objects_dev (nullable) the number of owned nuclei.  labels, mask and Hq
+ * share out_pitch.  (tile + 2 halo)^2 <= 2^25 - 2.  Synchronises `stream`
+ * between reconstruction rounds unless the recon_async knob is set.
+ */
+int rt_segment_slide(rt_ctx *ctx, const uint8_t *rgb, int64_t rgb_pitch_bytes, int32_t W, int32_t H, int32_t tile,
+                     int32_t halo, const rt_seg_params *params, int32_t *labels_out, uint8_t *mask_out,
+                     int64_t out_pitch, uint8_t *hq_out, int32_t *n_objects_dev, void *stream);
+
+/*
+ * Host-resident tile streams (the prefetching and asynchronous copies of
+ * Sec. 3.2.1, measured as "Pref." in Sec. 5.5): segments n tiles that live in
+ * HOST memory and writes the results to host memory, overlapping the upload
+ * of tile k+1 and the download of tile k-1 with the computation of tile k
+ * (three device slots; copies on two streams of the context, computation on
+ * `stream`, ordered by events).  Each tile is computed exactly as
+ * rt_segment_tile would compute it.  Host buffers should be pinned
+ * (hipHostMalloc) for the copies to overlap; pageable memory works but its
+ * copies do not overlap.  mask / labels / n_objects may each be NULL (not
+ * downloaded).  depth 1 runs upload, computation and download one after the
+ * other (no overlap), 2 or 3 overlaps them.  The call returns when every
+ * result is in host memory (it synchronises the context's streams).
+ * Device scratch: depth slots of 8 bytes per pixel of the largest tile, plus
+ * rt_segment_tile's own.
+ * Errors: RT_EINVAL (checked for every tile before any work starts).
+ */
+typedef struct {
+    const uint8_t *rgb;      /* host, interleaved RGB */
+    int64_t rgb_pitch_bytes; /* >= 3*w */
+    int32_t w, h;            /* w*h <= 2^25 - 2 */
+    uint8_t *mask;           /* nullable host uint8, pitch out_pitch */
+    int32_t *labels;         /* nullable host int32, pitch out_pitch */
+    int64_t out_pitch;       /* elements, >= w */
+    int32_t *n_objects;      /* nullable host int32 */
+} rt_host_tile;
+int rt_segment_host_stream(rt_ctx *ctx, int32_t n, const rt_host_tile *tiles, const rt_seg_params *params,
+                           int32_t depth, void *stream);
+
+/*
  * Tuning knobs of a context (set by the autotuner; results never depend on
  * them, only speed does):
  *   "recon_levels"      0..8  threshold levels of the frame-connectivity lower
@@ -244,6 +295,19 @@ int rt_segment_batch(rt_ctx *ctx, int32_t n, const rt_tile_desc *tiles, const rt
  *                             rounds as launches, then the work queue seeded
  *                             with the tiles they left queued; default 0
  *   "recon_queue_after" 1..64 rounds before the work queue in mode 2; default 2
+ *   "recon_async"       0|1   1: the segmentation entry points never read the
+ *                             worklist on the host: they launch
+ *                             "recon_async_rounds" rounds, then one workgroup
+ *                             finishes any rounds still needed on the device
+ *                             (tile by tile; slow only for inputs that need
+ *                             many more rounds), so rt_segment_tile /
+ *                             rt_segment_batch return without waiting for the
+ *                             device (beyond the reuse of the context's 4
+ *                             argument-upload buffers) and with "graph" the
+ *                             whole call is two graph launches; recon_mode
+ *                             must be 0; default 0
+ *   "recon_async_rounds" 1..256 launched rounds in async mode; default 16
+ *   (read only) "recon_host_reads": worklist counters read by the host so far
  *   "objects_path"      0     routing of components to the per-object kernels:
  *                             crops <= 32^2 and <= 64^2 to the register-scan
  *                             classes, up to 9312 px to the LDS class, larger

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "librtseg.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "unet.cpp", "k_deconv.hip", "k_ccl.hip", "k_recon.hip", "k_objects.hip", "k_misc.hip",
-           "k_nn.hip", "noalloc.hip", "k_features.hip", "k_morph.hip"]
+           "k_nn.hip", "noalloc.hip", "k_features.hip", "k_morph.hip", "k_stitch.hip"]
 
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -78,21 +78,30 @@ int ensure_stamps(rt_ctx_impl *c, size_t ntiles) {
     return RT_OK;
 }
 
-// Pinned host buffer of at least `bytes` for argument-record uploads.
+// Pinned host buffers (a ring of kStaging) of at least `bytes` each for
+// argument-record uploads.
 int ensure_staging(rt_ctx_impl *c, size_t bytes) {
     if (bytes > c->staging_cap) {
-        if (c->staging) {
+        if (c->staging[0]) {
             RT_HIP(hipDeviceSynchronize());
-            RT_HIP(hipHostFree(c->staging));
-            c->staging = nullptr;
+            for (int i = 0; i < kStaging; ++i) {
+                if (c->staging[i]) RT_HIP(hipHostFree(c->staging[i]));
+                c->staging[i] = nullptr;
+                c->staging_pending[i] = false;
+            }
             c->staging_cap = 0;
         }
         size_t cap = std::max<size_t>(bytes, 64 * 1024);
-        if (hipHostMalloc((void **)&c->staging, cap, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            c->staging = nullptr;
-            set_error("pinned staging allocation failed");
-            return RT_ENOMEM;
+        for (int i = 0; i < kStaging; ++i) {
+            if (hipHostMalloc((void **)&c->staging[i], cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                for (int j = 0; j <= i; ++j) {
+                    if (c->staging[j]) (void)hipHostFree(c->staging[j]);
+                    c->staging[j] = nullptr;
+                }
+                set_error("pinned staging allocation failed");
+                return RT_ENOMEM;
+            }
         }
         c->staging_cap = cap;
     }
@@ -210,37 +219,42 @@ int prof_mark(rt_ctx *c, int k, hipStream_t s) {
 }
 
 // Pinned staging of argument records.  The records of a call sit back to
-// back in the arena from the first put() offset on; the staging buffer holds
-// a congruent host image of that region, uploaded by flush() in one copy.
-// The previous upload may still be reading the buffer, so the first put()
-// waits for it (an upload is a few KB and finishes quickly).
+// back in the arena from the first put() offset on; a staging buffer holds a
+// congruent host image of that region, uploaded by flush() in one copy.  The
+// calls take the buffers of a ring in turn; a buffer's previous upload (from
+// kStaging calls back) may still be queued, so the first put() waits for it.
+// The host can thus run kStaging calls ahead of the device.
 struct Stager {
     rt_ctx *c;
     size_t dev_lo = SIZE_MAX, dev_hi = 0;
+    int slot = -1;
     template <typename T>
     int put(const std::vector<T> &recs, size_t dev_off) {
         if (dev_lo == SIZE_MAX) {
-            if (c->staging_pending) {
-                RT_HIP(hipEventSynchronize(c->staging_done));
-                c->staging_pending = false;
+            slot = c->staging_next;
+            if (c->staging_pending[slot]) {
+                RT_HIP(hipEventSynchronize(c->staging_done[slot]));
+                c->staging_pending[slot] = false;
             }
             dev_lo = dev_off;
         }
         const size_t bytes = recs.size() * sizeof(T);
-        if (dev_off < dev_lo || dev_off - dev_lo + bytes > c->staging_cap) {
+        if (!c->staging[slot] || dev_off < dev_lo || dev_off - dev_lo + bytes > c->staging_cap) {
             set_error("internal: staging region too small");
             return RT_ENOMEM;
         }
-        std::memcpy(c->staging + (dev_off - dev_lo), recs.data(), bytes);
+        std::memcpy(c->staging[slot] + (dev_off - dev_lo), recs.data(), bytes);
         dev_hi = std::max(dev_hi, dev_off + bytes);
         return RT_OK;
     }
     int flush(hipStream_t s) {
         if (dev_lo == SIZE_MAX) return RT_OK;
-        RT_HIP(hipMemcpyAsync(c->arena.base + dev_lo, c->staging, dev_hi - dev_lo, hipMemcpyHostToDevice, s));
-        if (!c->staging_done) RT_HIP(hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming));
-        RT_HIP(hipEventRecord(c->staging_done, s));
-        c->staging_pending = true;
+        RT_HIP(hipMemcpyAsync(c->arena.base + dev_lo, c->staging[slot], dev_hi - dev_lo, hipMemcpyHostToDevice, s));
+        if (!c->staging_done[slot])
+            RT_HIP(hipEventCreateWithFlags(&c->staging_done[slot], hipEventDisableTiming));
+        RT_HIP(hipEventRecord(c->staging_done[slot], s));
+        c->staging_pending[slot] = true;
+        c->staging_next = (slot + 1) % kStaging;
         return RT_OK;
     }
 };
@@ -584,9 +598,17 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     // mode 2: the first rounds as launches (every tile is busy), the rest of
     // the propagation in one work-queue launch (no round barrier per step)
     const int kq = c->knobs.recon_mode == 2 ? c->knobs.recon_queue_after : 0;
+    const bool async = c->knobs.recon_async != 0 && !queue;
+    const int ka = c->knobs.recon_async_rounds;
     if (!use_graph) {
         if ((e = enqueue_front(c, P, sp, s, true))) return e;
-        if (queue) {
+        if (async) {
+            // launched rounds, then the device finishes whatever is left: no host read
+            if ((e = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, ka, s)) ||
+                (e = recon_finish_device(c, P.run, rimgs, n, P.rdt, 8, ka, s)))
+                return e;
+            rounds = ka;
+        } else if (queue) {
             int aborted = 0;
             if (kq > 0 && (e = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, kq, s))) return e;
             if ((e = recon_queue(c, P.run, rimgs, n, P.rdt, 8, s, kq)) ||
@@ -608,7 +630,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
                                 c->knobs.objects_path, c->knobs.recon_mode, kq, c->knobs.recon_level_mode,
-                                c->knobs.recon_level_frac,
+                                c->knobs.recon_level_frac, async, ka,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -639,6 +661,11 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
             c,
             [&](hipStream_t cs) {
                 int e2 = enqueue_front(c, P, sp, cs, false);
+                if (async) {
+                    if (!e2) e2 = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, ka, cs);
+                    if (!e2) e2 = recon_finish_device(c, P.run, rimgs, n, P.rdt, 8, ka, cs);
+                    return e2;
+                }
                 if (!e2 && kq > 0) e2 = recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, kq, cs);
                 if (!e2) e2 = queue ? recon_queue(c, P.run, rimgs, n, P.rdt, 8, cs, kq)
                                     : recon_launch(c, P.run, rimgs, n, P.rdt, 8, 0, budget, cs);
@@ -655,7 +682,9 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     }
     g->last_use = ++c->graph_clock;
     RT_HIP(hipGraphLaunch(g->a, s));
-    if (queue) {
+    if (async) {
+        rounds = ka;
+    } else if (queue) {
         int aborted = 0;
         if ((e = recon_queue_aborted(c, P.run, s, &aborted))) return e;
         rounds = kq + 1;
@@ -729,8 +758,10 @@ int rt_ctx_destroy(rt_ctx *c) {
     if (c->stamps) (void)hipFree(c->stamps);
     if (c->lut) (void)hipFree(c->lut);
     if (c->pinned) (void)hipHostFree(c->pinned);
-    if (c->staging) (void)hipHostFree(c->staging);
-    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    for (int i = 0; i < kStaging; ++i) {
+        if (c->staging[i]) (void)hipHostFree(c->staging[i]);
+        if (c->staging_done[i]) (void)hipEventDestroy(c->staging_done[i]);
+    }
     for (GraphPair &g : c->graphs) destroy_graph(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
@@ -742,6 +773,15 @@ int rt_ctx_destroy(rt_ctx *c) {
     for (hipEvent_t ev : c->round_events) (void)hipEventDestroy(ev);
     if (c->prof_visits) (void)hipFree(c->prof_visits);
     if (c->prof_obj_px) (void)hipFree(c->prof_obj_px);
+    if (c->slots) (void)hipFree(c->slots);
+    if (c->stitch_buf) (void)hipFree(c->stitch_buf);
+    if (c->up_stream) (void)hipStreamDestroy(c->up_stream);
+    if (c->down_stream) (void)hipStreamDestroy(c->down_stream);
+    for (int k = 0; k < 3; ++k) {
+        if (c->slot_up[k]) (void)hipEventDestroy(c->slot_up[k]);
+        if (c->slot_comp[k]) (void)hipEventDestroy(c->slot_comp[k]);
+        if (c->slot_down[k]) (void)hipEventDestroy(c->slot_down[k]);
+    }
     for (auto &v : c->obj_events)
         for (hipEvent_t ev : v) (void)hipEventDestroy(ev);
     delete c;
@@ -1137,6 +1177,169 @@ int rt_segment_tile(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t w,
     return pipeline(c, &t, 1, p, as_stream(stream));
 }
 
+int rt_segment_slide(rt_ctx *c, const uint8_t *rgb, int64_t rgb_pitch, int32_t W, int32_t H, int32_t tile, int32_t halo,
+                     const rt_seg_params *p, int32_t *labels_out, uint8_t *mask_out, int64_t out_pitch,
+                     uint8_t *hq_out, int32_t *n_objects_dev, void *stream) {
+    CHECK(c && rgb && p && labels_out, "rt_segment_slide: null argument");
+    int e = check_params(p, "rt_segment_slide");
+    if (e) return e;
+    CHECK(!bad_size(W, H) && rgb_pitch >= 3LL * W && out_pitch >= W, "rt_segment_slide: bad size or pitch");
+    CHECK(tile >= 1 && halo >= 0, "rt_segment_slide: tile %d, halo %d", tile, halo);
+    const int64_t ext = (int64_t)std::min<int64_t>(tile, std::max(W, H)) + 2LL * halo;
+    CHECK(ext * ext <= kMaxObjPixels, "rt_segment_slide: an extended tile of %lld px a side is too large",
+          (long long)ext);
+    if ((e = set_dev(c))) return e;
+    hipStream_t s = as_stream(stream);
+    // the extended tiles, row-major by core
+    struct Ext {
+        int ex0, ey0, ew, eh, x0, y0, x1, y1;
+    };
+    std::vector<Ext> all;
+    for (int y0 = 0; y0 < H; y0 += tile)
+        for (int x0 = 0; x0 < W; x0 += tile) {
+            Ext t;
+            t.x0 = x0;
+            t.y0 = y0;
+            t.x1 = std::min(W, x0 + tile);
+            t.y1 = std::min(H, y0 + tile);
+            t.ex0 = std::max(0, x0 - halo);
+            t.ey0 = std::max(0, y0 - halo);
+            t.ew = std::min(W, t.x1 + halo) - t.ex0;
+            t.eh = std::min(H, t.y1 + halo) - t.ey0;
+            all.push_back(t);
+        }
+    if ((e = launch_stitch_init(labels_out, out_pitch, W, H, n_objects_dev, c->n_cu, s))) return e;
+    for (size_t g0 = 0; g0 < all.size(); g0 += MAX_BATCH) {
+        const int n = (int)std::min<size_t>(MAX_BATCH, all.size() - g0);
+        // per-tile outputs: labels (4 B/px), mask and Hq (1 B/px each), count
+        std::vector<size_t> off(n);
+        size_t need = 0;
+        for (int i = 0; i < n; ++i) {
+            off[i] = need;
+            need += al(6 * (size_t)all[g0 + i].ew * all[g0 + i].eh + 256);
+        }
+        if (need > c->stitch_cap) {
+            RT_HIP(hipDeviceSynchronize());
+            if (c->stitch_buf) RT_HIP(hipFree(c->stitch_buf));
+            c->stitch_buf = nullptr;
+            c->stitch_cap = 0;
+            if (hipMalloc((void **)&c->stitch_buf, need) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("rt_segment_slide: %zu bytes of tile scratch failed", need);
+                return RT_ENOMEM;
+            }
+            c->stitch_cap = need;
+        }
+        std::vector<TileIn> tin(n);
+        StitchGroup G{};
+        G.n = n;
+        G.W = W;
+        G.labels = labels_out;
+        G.hq_out = hq_out;
+        G.out_pitch = out_pitch;
+        G.n_objects = n_objects_dev;
+        for (int i = 0; i < n; ++i) {
+            const Ext &t = all[g0 + i];
+            const size_t px = (size_t)t.ew * t.eh;
+            char *b = c->stitch_buf + off[i];
+            int32_t *lab = (int32_t *)b;
+            uint8_t *mask = (uint8_t *)(b + 4 * px), *hq = mask + px;
+            tin[i] = TileIn{rgb + (int64_t)t.ey0 * rgb_pitch + 3LL * t.ex0, rgb_pitch, t.ew, t.eh, mask, lab, t.ew,
+                            nullptr, hq, nullptr, nullptr};
+            G.t[i] = StitchTile{lab, hq, t.ex0, t.ey0, t.ew, t.eh, t.x0, t.y0, t.x1, t.y1};
+        }
+        if ((e = pipeline(c, tin.data(), n, p, s))) return e;
+        if ((e = launch_stitch(G, c->n_cu, s))) return e;
+    }
+    return launch_stitch_final(labels_out, mask_out, out_pitch, W, H, c->n_cu, s);
+}
+
+int rt_segment_host_stream(rt_ctx *c, int32_t n, const rt_host_tile *tiles, const rt_seg_params *p, int32_t depth,
+                           void *stream) {
+    CHECK(c && p && (n == 0 || tiles), "rt_segment_host_stream: null argument");
+    CHECK(n >= 0, "rt_segment_host_stream: negative tile count");
+    CHECK(depth >= 1 && depth <= 3, "rt_segment_host_stream: depth %d (1..3)", depth);
+    int e = check_params(p, "rt_segment_host_stream");
+    if (e) return e;
+    size_t max_px = 1;
+    for (int i = 0; i < n; ++i) {
+        const rt_host_tile &t = tiles[i];
+        CHECK(t.rgb, "rt_segment_host_stream: tile %d: null rgb", i);
+        CHECK(!bad_size(t.w, t.h, kMaxObjPixels), "rt_segment_host_stream: tile %d: bad size %dx%d", i, t.w, t.h);
+        CHECK(t.rgb_pitch_bytes >= 3LL * t.w && t.out_pitch >= t.w, "rt_segment_host_stream: tile %d: pitch", i);
+        max_px = std::max(max_px, (size_t)t.w * t.h);
+    }
+    if ((e = set_dev(c))) return e;
+    if (n == 0) return RT_OK;
+    hipStream_t s = as_stream(stream);
+    if (!c->up_stream) RT_HIP(hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking));
+    if (!c->down_stream) RT_HIP(hipStreamCreateWithFlags(&c->down_stream, hipStreamNonBlocking));
+    for (int k = 0; k < 3; ++k) {
+        if (!c->slot_up[k]) RT_HIP(hipEventCreateWithFlags(&c->slot_up[k], hipEventDisableTiming));
+        if (!c->slot_comp[k]) RT_HIP(hipEventCreateWithFlags(&c->slot_comp[k], hipEventDisableTiming));
+        if (!c->slot_down[k]) RT_HIP(hipEventCreateWithFlags(&c->slot_down[k], hipEventDisableTiming));
+    }
+    // slot layout: RGB (3 B/px), mask (1 B/px), labels (4 B/px), count
+    const size_t o_mask = al(3 * max_px), o_lab = o_mask + al(max_px), o_n = o_lab + al(4 * max_px);
+    const size_t need = o_n + 256;
+    if (need > c->slot_bytes) {
+        RT_HIP(hipDeviceSynchronize());
+        if (c->slots) RT_HIP(hipFree(c->slots));
+        c->slots = nullptr;
+        c->slot_bytes = 0;
+        if (hipMalloc((void **)&c->slots, 3 * need) != hipSuccess) {
+            (void)hipGetLastError();
+            c->slots = nullptr;
+            set_error("rt_segment_host_stream: slot allocation of %zu bytes failed", 3 * need);
+            return RT_ENOMEM;
+        }
+        c->slot_bytes = need;
+    }
+    const size_t sb = c->slot_bytes;
+    std::vector<bool> used(3, false);
+    hipStream_t up = depth == 1 ? s : c->up_stream, down = depth == 1 ? s : c->down_stream;
+    auto slot = [&](int k) { return c->slots + (size_t)(k % depth) * sb; };
+    auto upload = [&](int k) -> int {
+        const rt_host_tile &t = tiles[k];
+        const int q = k % depth;
+        // the slot's previous tile must be downloaded (and so computed) first
+        if (used[q]) RT_HIP(hipStreamWaitEvent(up, c->slot_down[q], 0));
+        RT_HIP(hipMemcpy2DAsync(slot(k), 3 * (size_t)t.w, t.rgb, (size_t)t.rgb_pitch_bytes, 3 * (size_t)t.w,
+                                (size_t)t.h, hipMemcpyHostToDevice, up));
+        RT_HIP(hipEventRecord(c->slot_up[q], up));
+        used[q] = true;
+        return RT_OK;
+    };
+    const int ahead = depth - 1;   // uploads issued before the first computation
+    for (int k = 0; k < std::min(ahead, n); ++k)
+        if ((e = upload(k))) return e;
+    for (int k = 0; k < n; ++k) {
+        const rt_host_tile &t = tiles[k];
+        const int q = k % depth;
+        if (depth == 1 && (e = upload(k))) return e;
+        if (depth > 1 && k + ahead < n && (e = upload(k + ahead))) return e;
+        char *b = slot(k);
+        uint8_t *mask = (uint8_t *)(b + o_mask);
+        int32_t *lab = (int32_t *)(b + o_lab), *cnt = (int32_t *)(b + o_n);
+        RT_HIP(hipStreamWaitEvent(s, c->slot_up[q], 0));
+        const TileIn ti{(const uint8_t *)b, 3 * (int64_t)t.w, t.w, t.h, mask, lab, t.w, cnt, nullptr, nullptr, nullptr};
+        if ((e = pipeline(c, &ti, 1, p, s))) return e;
+        RT_HIP(hipEventRecord(c->slot_comp[q], s));
+        RT_HIP(hipStreamWaitEvent(down, c->slot_comp[q], 0));
+        if (t.mask)
+            RT_HIP(hipMemcpy2DAsync(t.mask, (size_t)t.out_pitch, mask, (size_t)t.w, (size_t)t.w, (size_t)t.h,
+                                    hipMemcpyDeviceToHost, down));
+        if (t.labels)
+            RT_HIP(hipMemcpy2DAsync(t.labels, 4 * (size_t)t.out_pitch, lab, 4 * (size_t)t.w, 4 * (size_t)t.w,
+                                    (size_t)t.h, hipMemcpyDeviceToHost, down));
+        if (t.n_objects) RT_HIP(hipMemcpyAsync(t.n_objects, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, down));
+        RT_HIP(hipEventRecord(c->slot_down[q], down));
+    }
+    RT_HIP(hipStreamSynchronize(down));
+    RT_HIP(hipStreamSynchronize(s));
+    return RT_OK;
+}
+
 int rt_segment_batch(rt_ctx *c, int32_t n, const rt_tile_desc *tiles, const rt_seg_params *p, void *stream) {
     CHECK(c && p && (n == 0 || tiles), "rt_segment_batch: null argument");
     CHECK(n >= 0, "rt_segment_batch: negative tile count");
@@ -1307,6 +1510,12 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     } else if (n == "recon_queue_after") {
         CHECK(value >= 1 && value <= 64, "rt_set_knob: recon_queue_after must be 1..64");
         c->knobs.recon_queue_after = value;
+    } else if (n == "recon_async") {
+        CHECK(value == 0 || value == 1, "rt_set_knob: recon_async must be 0 or 1");
+        c->knobs.recon_async = value;
+    } else if (n == "recon_async_rounds") {
+        CHECK(value >= 1 && value <= 256, "rt_set_knob: recon_async_rounds must be 1..256");
+        c->knobs.recon_async_rounds = value;
     } else if (n == "objects_path") {
         CHECK(value >= 0 && value <= 2, "rt_set_knob: objects_path must be 0..2");
         // the alternative routings (1: no medium class, 2: the large LDS class
@@ -1345,6 +1554,12 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.recon_max_sweeps;
     else if (n == "objects_path")
         *value = c->knobs.objects_path;
+    else if (n == "recon_async")
+        *value = c->knobs.recon_async;
+    else if (n == "recon_host_reads")
+        *value = (int)std::min<int64_t>(c->recon_host_reads, INT32_MAX);
+    else if (n == "recon_async_rounds")
+        *value = c->knobs.recon_async_rounds;
     else if (n == "recon_mode")
         *value = c->knobs.recon_mode;
     else if (n == "recon_queue_after")

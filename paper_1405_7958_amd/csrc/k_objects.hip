@@ -469,6 +469,43 @@ __device__ int count_roots(const Crop<L> &m, int *red) {
     return tot;
 }
 
+// ---- row pass of the distance transform for the register classes ------------
+// Crops of at most R x R in a plane of stride R + 1, NT threads: thread t
+// takes row t % R and the output columns [(t / R) P, (t / R + 1) P) with
+// P = R * R / NT.  The row's column distances G (the column pass left them in
+// A) are read once into registers, capped at 2R (when the crop holds a
+// background pixel, every true distance in it is below 2R, so the cap never
+// decides a minimum), and each output is the minimum of (c - c')^2 + G(c')^2
+// over the whole row: independent register arithmetic instead of a search
+// with one LDS round trip per offset.
+template <int R, int NT>
+__device__ __forceinline__ void edt_rows_reg(const Crop<int32_t> &m, bool has_zero) {
+    static_assert((R * R) % NT == 0 && NT % R == 0, "thread layout");
+    constexpr int P = R * R / NT;
+    const int t = threadIdx.x;
+    const int r = t % R, c0 = (t / R) * P;
+    if (r < m.ch) {
+        int g2[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int g = c < m.cw ? min(m.A[r * m.st + c], 2 * R) : 2 * R;
+            g2[c] = g * g;
+        }
+#pragma unroll 1
+        for (int k = 0; k < P; ++k) {
+            const int c = c0 + k;
+            const int i = r * m.st + c;
+            int best = INT_MAX;
+#pragma unroll
+            for (int cc = 0; cc < R; ++cc) best = min(best, (c - cc) * (c - cc) + g2[cc]);
+            int v = 0;
+            if (c < m.cw && (m.fl[i] & F_IN)) v = has_zero ? isqrt_exact(4 * (int64_t)best) : RT_DQ_MAX;
+            m.dq[i] = v;
+        }
+        if (t < R) m.dq[r * m.st + R] = 0;   // the plane's last column (stride R + 1) is padding
+    }
+}
+
 // ---- the whole per-component stage ---------------------------------------------
 template <int R, typename L>
 __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int16_t *tw = nullptr) {
@@ -511,27 +548,33 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         }
     }
     __syncthreads();
-    for (int i = lane; i < m.n; i += blockDim.x) {
-        const int c = i % m.st, r = i / m.st;
-        if (c >= m.cw || !(m.fl[i] & F_IN)) {
-            m.dq[i] = 0;
-            continue;
+    if constexpr (R == RS_) {
+        edt_rows_reg<RS_, WAVE>(m, has_zero);
+    } else if constexpr (R == RM_) {
+        edt_rows_reg<RM_, 2 * WAVE>(m, has_zero);
+    } else {
+        for (int i = lane; i < m.n; i += blockDim.x) {
+            const int c = i % m.st, r = i / m.st;
+            if (c >= m.cw || !(m.fl[i] & F_IN)) {
+                m.dq[i] = 0;
+                continue;
+            }
+            if (!has_zero) {  // the crop is the whole tile and all foreground
+                m.dq[i] = RT_DQ_MAX;
+                continue;
+            }
+            const int32_t *row = m.A + r * m.st;
+            int64_t best = row[c] < GINF ? (int64_t)row[c] * row[c] : INT64_MAX;
+            for (int dx = 1;; ++dx) {
+                const int64_t dd = (int64_t)dx * dx;
+                if (dd >= best) break;
+                const bool lo = c - dx >= 0, hi = c + dx < m.cw;
+                if (!lo && !hi) break;
+                if (lo && row[c - dx] < GINF) best = min(best, dd + (int64_t)row[c - dx] * row[c - dx]);
+                if (hi && row[c + dx] < GINF) best = min(best, dd + (int64_t)row[c + dx] * row[c + dx]);
+            }
+            m.dq[i] = isqrt_exact(4 * best);
         }
-        if (!has_zero) {  // the crop is the whole tile and all foreground
-            m.dq[i] = RT_DQ_MAX;
-            continue;
-        }
-        const int32_t *row = m.A + r * m.st;
-        int64_t best = row[c] < GINF ? (int64_t)row[c] * row[c] : INT64_MAX;
-        for (int dx = 1;; ++dx) {
-            const int64_t dd = (int64_t)dx * dx;
-            if (dd >= best) break;
-            const bool lo = c - dx >= 0, hi = c + dx < m.cw;
-            if (!lo && !hi) break;
-            if (lo && row[c - dx] < GINF) best = min(best, dd + (int64_t)row[c - dx] * row[c - dx]);
-            if (hi && row[c + dx] < GINF) best = min(best, dd + (int64_t)row[c + dx] * row[c + dx]);
-        }
-        m.dq[i] = isqrt_exact(4 * best);
     }
     __syncthreads();
     // ---- one regional maximum of Dq means one seed (register classes, when

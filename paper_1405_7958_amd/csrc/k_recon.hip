@@ -877,6 +877,51 @@ int launch_batch_end(const BatchAux *aux, int n, hipStream_t s) {
 
 // Start of a reconstruction: no tile stamped, the three list counters zero
 // (one launch for both).
+// Device-side finish of a reconstruction after the launched rounds (no host
+// read of the worklist): one workgroup runs rounds k0, k0 + 1, ... itself,
+// each over the list the previous round left, visiting its tiles one after
+// the other, until a round starts with an empty list.  The rounds keep the
+// launched rounds' lists, counters and stamps (round k reads counter k % 3,
+// writes (k + 1) % 3, clears (k + 2) % 3); an agent-scope fence after every
+// tile visit publishes its writes to the next visits, whose loads it orders.
+// With enough launched rounds the list is already empty and the workgroup
+// leaves at once.
+template <typename T, int CONN, bool PLAIN>
+__global__ __launch_bounds__(64) void k_recon_finisher(RoundArgs ra, int32_t *lists, int k0) {
+    __shared__ __align__(16) uint8_t lds[PLAIN ? PLAIN_LDS : 64 * 65 * 4];
+    const int lane = threadIdx.x;
+    for (int k = k0;; ++k) {
+        __threadfence();
+        int32_t *cnt_in = ra.cnt + (k % 3), *cnt_out = ra.cnt + ((k + 1) % 3), *cnt_clr = ra.cnt + ((k + 2) % 3);
+        const int n_in = __hip_atomic_load(cnt_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n_in == 0) break;
+        if (lane == 0) __hip_atomic_store(cnt_clr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t *list_in = lists + (k & 1) * (size_t)ra.total;
+        int32_t *list_out = lists + ((k + 1) & 1) * (size_t)ra.total;
+        const uint32_t epoch = (uint32_t)k + 1;
+        if (ra.visits && lane == 0) atomicAdd(ra.visits, (unsigned long long)n_in);
+        for (int slot = 0; slot < n_in; ++slot) {
+            const int gtile = list_in[slot];
+            const ReconImg a = ra.imgs[recon_img_of(ra.imgs, ra.n, gtile)];
+            auto push = [&](int item, bool valid) {
+                const bool fresh = valid && atomicExch(ra.stamp + item, epoch) != epoch;
+                const uint64_t m = __ballot(fresh);
+                if (!m) return;
+                int base = 0;
+                if (lane == 0) base = atomicAdd(cnt_out, __popcll(m));
+                base = __shfl(base, 0, 64);
+                if (fresh) list_out[base + __popcll(m & ((1ull << lane) - 1))] = item;
+            };
+            if constexpr (PLAIN)
+                recon_tile_plain<CONN, false>(a, gtile, ra.max_sweeps, lds, push);
+            else
+                recon_tile<T, CONN, false>(a, gtile, ra.max_sweeps, reinterpret_cast<int (*)[65]>(lds), push);
+            __syncthreads();
+            __threadfence();
+        }
+    }
+}
+
 __global__ void k_recon_reset(uint32_t *stamp, int total, int32_t *cnt) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) stamp[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x < 3) cnt[threadIdx.x] = 0;
@@ -969,6 +1014,34 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
     return RT_OK;
 }
 
+int recon_finish_device(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
+                        int k0, hipStream_t s) {
+    if (run.total <= 0) return RT_OK;
+    if (k0 < 1) {
+        set_error("recon: the device finish follows at least one launched round");
+        return RT_EINVAL;
+    }
+    RoundArgs ra{};
+    ra.imgs = imgs_dev;
+    ra.n = n;
+    ra.total = run.total;
+    ra.cnt = run.cnt;
+    ra.stamp = c->stamps;
+    ra.max_sweeps = c->knobs.recon_max_sweeps;
+    ra.visits = c->prof_on ? c->prof_visits : nullptr;
+    if (dtype == RECON_U8_PLAIN) {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_finisher<uint8_t, 8, true>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+        else hipLaunchKernelGGL((k_recon_finisher<uint8_t, 4, true>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+    } else if (dtype == RT_U8) {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_finisher<uint8_t, 8, false>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+        else hipLaunchKernelGGL((k_recon_finisher<uint8_t, 4, false>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+    } else {
+        if (conn == 8) hipLaunchKernelGGL((k_recon_finisher<int32_t, 8, false>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+        else hipLaunchKernelGGL((k_recon_finisher<int32_t, 4, false>), dim3(1), dim3(64), 0, s, ra, run.lists, k0);
+    }
+    return hip_fail(hipGetLastError(), "k_recon_finisher");
+}
+
 int recon_queue(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
                 hipStream_t s, int from_round) {
     if (run.total <= 0) return RT_OK;
@@ -1028,6 +1101,7 @@ int recon_queue_aborted(rt_ctx_impl *c, const ReconRun &run, hipStream_t s, int 
     if (run.total <= 0) return RT_OK;
     RT_HIP(hipMemcpyAsync(c->pinned, run.qctl + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
+    c->recon_host_reads++;
     *aborted = c->pinned[0] != 0;
     return RT_OK;
 }
@@ -1040,6 +1114,7 @@ int recon_pending(rt_ctx_impl *c, const ReconRun &run, int k, hipStream_t s, int
     // the list produced by round k-1 is counted by counter k % 3
     RT_HIP(hipMemcpyAsync(c->pinned, run.cnt + (k % 3), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     RT_HIP(hipStreamSynchronize(s));
+    c->recon_host_reads++;
     *pending = c->pinned[0];
     return RT_OK;
 }

@@ -61,6 +61,9 @@ struct Knobs {
     int recon_queue_after = 2;   // recon_mode 2: rounds launched before the work queue takes over
     int graph = 0;               // replay segmentation batches from captured HIP graphs
     int graph_rounds = 24;       // reconstruction rounds inside the first graph
+    int recon_async = 0;         // 1: no host read of the worklist -- recon_async_rounds launched rounds,
+                                 // then the device-side finish (segmentation entry points)
+    int recon_async_rounds = 16;
 };
 
 // A captured segmentation batch: graph A = deconvolution, connectivity bound
@@ -73,15 +76,18 @@ struct GraphPair {
     uint64_t last_use = 0;
 };
 
+constexpr int kStaging = 4;   // argument-record upload buffers per context
+
 struct rt_ctx_impl {
     int device = 0;
     int n_cu = 256;
     Arena arena;
     int32_t *pinned = nullptr;   // small pinned host buffer for counter readback
-    char *staging = nullptr;     // pinned host staging for per-image argument records
-    size_t staging_cap = 0;
-    hipEvent_t staging_done = nullptr;   // recorded after the last upload from `staging`
-    bool staging_pending = false;
+    char *staging[kStaging] = {};       // pinned host staging for per-image argument records (a ring)
+    size_t staging_cap = 0;             // bytes of each
+    hipEvent_t staging_done[kStaging] = {};   // recorded after the last upload from each buffer
+    bool staging_pending[kStaging] = {};
+    int staging_next = 0;
     double *lut = nullptr;       // 3 x 256 FP64 deconvolution table (device)
     uint32_t *stamps = nullptr;  // per-tile stamp array (device)
     size_t stamps_cap = 0;
@@ -95,6 +101,7 @@ struct rt_ctx_impl {
     uint64_t graph_clock = 0;
     int64_t graph_replays = 0, graph_captures = 0;
     int last_rounds = 0;
+    int64_t recon_host_reads = 0;          // worklist counts the host has read (each a stream synchronisation)
     // stage timing
     bool prof_on = false;                  // round timing (modes 1 and 2)
     bool prof_stages = false;              // stage boundary events (mode 1)
@@ -113,6 +120,15 @@ struct rt_ctx_impl {
     size_t obj_used[3] = {};
     int64_t obj_launches[3] = {};
     unsigned long long *prof_obj_px = nullptr;
+    // host-resident tile streams: device slots (RGB in, mask, labels and count
+    // out) and the upload / download streams with one event per slot and phase
+    hipStream_t up_stream = nullptr, down_stream = nullptr;
+    hipEvent_t slot_up[3] = {}, slot_comp[3] = {}, slot_down[3] = {};
+    char *slots = nullptr;
+    size_t slot_bytes = 0;
+    // cross-tile stitching: per-tile outputs of one launch group
+    char *stitch_buf = nullptr;
+    size_t stitch_cap = 0;
 };
 
 int ensure_arena(rt_ctx_impl *c, size_t bytes);
@@ -218,6 +234,10 @@ int recon_prepare(rt_ctx_impl *c, int total, ReconRun &run);
 // share dtype and connectivity.
 int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn, int k0,
                  int k1, hipStream_t s);
+// Enqueues the device-side finish of rounds k0, k0 + 1, ... (one workgroup,
+// no host read; capturable); k0 >= 1.
+int recon_finish_device(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, int n, int dtype, int conn,
+                        int k0, hipStream_t s);
 // Enqueues the work-queue propagation (one persistent launch; capturable).
 // from_round > 0: seed the queue with the worklist round from_round - 1 left
 // (rounds 0 .. from_round - 1 already enqueued on s); else with every tile
@@ -358,6 +378,28 @@ int launch_tophat(const uint8_t *hq, int64_t hq_pitch, const uint8_t *r, int64_t
                   int64_t f0_pitch, int w, int h, int t, hipStream_t s);
 int launch_rbc_maps(const uint8_t *rgb, int64_t rgb_pitch, int w, int h, int t_strong, int t_weak, uint8_t *marker,
                     uint8_t *mask, int64_t pitch, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// cross-tile stitching
+// ---------------------------------------------------------------------------
+struct StitchTile {
+    const int32_t *labels;         // the extended tile's labels (dense, pitch ew)
+    const uint8_t *hq;             // its Hq (dense, pitch ew), read when hq_out is set
+    int ex0, ey0, ew, eh;          // extended region in slide coordinates
+    int x0, y0, x1, y1;            // core [x0, x1) x [y0, y1)
+};
+struct StitchGroup {               // passed by value: at most MAX_BATCH tiles
+    StitchTile t[MAX_BATCH];
+    int n;
+    int W;
+    int32_t *labels;               // slide labels, pitch out_pitch (INT32_MAX = not yet written)
+    uint8_t *hq_out;               // nullable slide Hq
+    int64_t out_pitch;
+    int32_t *n_objects;            // nullable
+};
+int launch_stitch_init(int32_t *labels, int64_t pitch, int W, int H, int32_t *n_objects, int n_cu, hipStream_t s);
+int launch_stitch(const StitchGroup &g, int n_cu, hipStream_t s);
+int launch_stitch_final(int32_t *labels, uint8_t *mask, int64_t pitch, int W, int H, int n_cu, hipStream_t s);
 
 int launch_fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
 

@@ -38,6 +38,11 @@ class rt_seg_params(C.Structure):
                 ("h_seed", C.c_int32), ("conn", C.c_int32)]
 
 
+class rt_host_tile(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("rgb_pitch_bytes", C.c_int64), ("w", C.c_int32), ("h", C.c_int32),
+                ("mask", C.c_void_p), ("labels", C.c_void_p), ("out_pitch", C.c_int64), ("n_objects", C.c_void_p)]
+
+
 class rt_tile_desc(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("rgb_pitch_bytes", C.c_int64), ("w", C.c_int32), ("h", C.c_int32),
                 ("mask_out", C.c_void_p), ("labels_out", C.c_void_p), ("out_pitch", C.c_int64),
@@ -73,6 +78,9 @@ def lib():
         L.rt_seg_params_default.argtypes = [C.POINTER(rt_seg_params)]
         L.rt_segment_tile.argtypes = [vp, vp, i64, i32, i32, C.POINTER(rt_seg_params), vp, vp, i64, vp, vp, vp]
         L.rt_segment_batch.argtypes = [vp, i32, C.POINTER(rt_tile_desc), C.POINTER(rt_seg_params), vp]
+        L.rt_segment_host_stream.argtypes = [vp, i32, C.POINTER(rt_host_tile), C.POINTER(rt_seg_params), i32, vp]
+        L.rt_segment_slide.argtypes = [vp, vp, i64, i32, i32, i32, i32, C.POINTER(rt_seg_params), vp, vp, i64, vp,
+                                       vp, vp]
         L.rt_set_knob.argtypes = [vp, C.c_char_p, C.c_int]
         L.rt_get_knob.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int)]
         L.rt_profile_enable.argtypes = [vp, C.c_int]
@@ -409,8 +417,53 @@ def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None, want_maps=False
 
 RT_PROF_STAGES = 7
 KNOBS = ("recon_levels", "recon_level_mode", "recon_level_frac", "recon_round_batch", "recon_max_sweeps", "recon_mode",
-         "recon_queue_after", "objects_path", "graph", "graph_rounds")
-READ_ONLY = ("graph_captures", "graph_replays", "last_rounds")
+         "recon_queue_after", "objects_path", "graph", "graph_rounds", "recon_async", "recon_async_rounds")
+READ_ONLY = ("graph_captures", "graph_replays", "last_rounds", "recon_host_reads")
+
+
+def rt_segment_slide(rgb, tile, halo, params=None, want_hq=False, ctx=None):
+    """Cross-tile stitching of a device slide (H, W, 3): returns (labels,
+    mask, n_objects[, hq])."""
+    ctx = ctx or default_context(rgb.device.index)
+    _img(rgb, torch.uint8, "rgb", 3)
+    p = params or default_params()
+    H, W = rgb.shape[:2]
+    d = rgb.device
+    lab = torch.empty((H, W), dtype=torch.int32, device=d)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=d)
+    hq = torch.empty((H, W), dtype=torch.uint8, device=d) if want_hq else None
+    n = torch.zeros(1, dtype=torch.int32, device=d)
+    _check(lib().rt_segment_slide(ctx.h, _ptr(rgb), rgb.stride(0), W, H, int(tile), int(halo), C.byref(p), _ptr(lab),
+                                  _ptr(mask), W, _ptr(hq), _ptr(n), _stream()))
+    return (lab, mask, n, hq) if want_hq else (lab, mask, n)
+
+
+def rt_segment_host_stream(rgbs, params=None, depth=3, want_mask=True, want_labels=True, ctx=None, outs=None):
+    """Segments host-resident tiles (CPU uint8 tensors (H, W, 3), ideally
+    pinned) with uploads, computation and downloads overlapped; results in
+    pinned host tensors: a list of (mask, labels, n_objects) (None where not
+    wanted).  `outs` (optional) reuses the output tensors of an earlier call."""
+    ctx = ctx or default_context()
+    p = params or default_params()
+    n = len(rgbs)
+    descs = (rt_host_tile * max(n, 1))()
+    res = []
+    for i, t in enumerate(rgbs):
+        if t.is_cuda or t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3 or t.stride(2) != 1 \
+                or t.stride(1) != 3:
+            raise ValueError(f"tile {i}: expected a host (H, W, 3) uint8 interleaved tensor")
+        h, w = t.shape[:2]
+        if outs is not None:
+            m, lab, cnt = outs[i]
+        else:
+            m = torch.empty((h, w), dtype=torch.uint8, pin_memory=True) if want_mask else None
+            lab = torch.empty((h, w), dtype=torch.int32, pin_memory=True) if want_labels else None
+            cnt = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        descs[i] = rt_host_tile(t.data_ptr(), t.stride(0), w, h, m.data_ptr() if m is not None else None,
+                                lab.data_ptr() if lab is not None else None, w, cnt.data_ptr())
+        res.append((m, lab, cnt))
+    _check(lib().rt_segment_host_stream(ctx.h, n, descs, C.byref(p), int(depth), _stream()))
+    return res
 
 
 def rt_set_knob(name, value, ctx=None):
@@ -704,7 +757,7 @@ def nn_prep_input(rgb, ctx=None):
 
 EXPORTS = ("rt_ctx_create", "rt_ctx_destroy", "rt_last_error", "rt_sync", "rt_deconv", "rt_morph_recon",
            "rt_fill_holes", "rt_ccl", "rt_ccl_noalloc", "rt_features", "rt_morph", "rt_recon_to_nuclei", "rt_rbc_detect", "rt_area_filter", "rt_watershed", "rt_seg_params_default",
-           "rt_segment_tile", "rt_segment_batch", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds", "rt_profile_objects",
+           "rt_segment_tile", "rt_segment_batch", "rt_segment_host_stream", "rt_segment_slide", "rt_set_knob", "rt_get_knob", "rt_profile_enable", "rt_profile_read", "rt_profile_recon_rounds", "rt_profile_objects",
            "rt_profile_stage_name", "rt_unet_param_count", "rt_unet_create", "rt_unet_destroy", "rt_unet_get_params",
            "rt_unet_set_params", "rt_unet_get_grads", "rt_unet_grad_step", "rt_unet_train_step", "rt_unet_forward",
            "rt_unet_save", "rt_unet_load", "rt_unet_adam_step", "rt_unet_get_step", "rt_unet_save_checkpoint",
