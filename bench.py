@@ -4,7 +4,7 @@ One step = rt_segment_tile over one 4096 x 4096 synthetic H&E-like tile (8000
 nuclei, semi-axes 4-14 px, 20% in touching clusters of 2-4, jitter +-20,
 seed 0), input resident in HBM.  Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-stream4k]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-stream4k] [--no-next]
                   [--no-batch] [--no-surrogate] [--no-tune] [--knobs K=V,...]
                   [--copy-calibration MB]
 
@@ -27,6 +27,13 @@ components it processes (read the label, write label and mask).  `value`
 comes from the same timed steps (the events add no synchronisation).
 `pipeline_floor_frac` is the whole tile's 8 B/px floor (RGB in, mask and
 labels out) at the measured tiles/s, as a fraction of the 8 TB/s peak.
+
+The "next_rows" object times the stages built beside the segmentation on the
+same tile: rt_features, rt_morph (opening), rt_recon_to_nuclei (opening by
+reconstruction), rt_rbc_detect and rt_segment_slide (stitching).  The
+"host_stream4k" object times rt_segment_host_stream over the distinct tiles
+below held in pinned host memory (every copy inside the timed region), with
+the copies overlapped (depth 3) and not (depth 1).
 
 The "stream4k" object times rt_segment_batch over 8 distinct 4096 x 4096
 tiles of the same generator (seeds 0..7) per call: every tile's data is
@@ -216,6 +223,47 @@ def host_stream_leg(rtseg, torch, knobs, host_tiles, reps=2):
     return out
 
 
+def next_rows_leg(rtseg, torch, rgb, lab, ctx, reps=5):
+    """The stages built beside the segmentation, timed on the 4096 x 4096
+    tile (device-resident): feature computation on the segmentation's labels,
+    disk opening, ReconToNuclei with the opening-by-reconstruction marker,
+    RBC detection, and cross-tile stitching (1024 x 1024 cores, 64-px halo)."""
+    hq = rtseg.rt_deconv(rgb, ctx=ctx)
+    H, W = hq.shape
+    N = H * W
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {}
+    nuc = {}
+
+    def feats():
+        nuc["n"] = rtseg.rt_features(lab, hq, max_nuclei=16384, ctx=ctx)[3]
+    ms = timed(feats)
+    out["features"] = {"ms_per_tile": round(ms, 3), "nuclei": nuc["n"], "nuclei_per_s": round(nuc["n"] / ms * 1e3),
+                       "read_gbs": round(5 * N / (ms * 1e-3) / 1e9, 1),
+                       "note": "includes one count read-back per call (binding)"}
+    ms = timed(lambda: rtseg.rt_morph(hq, rtseg.RT_OPEN, 5, ctx=ctx))
+    out["morph_open_r5"] = {"ms_per_tile": round(ms, 3), "gbs": round(4 * N / (ms * 1e-3) / 1e9, 1)}
+    ms = timed(lambda: rtseg.rt_recon_to_nuclei(hq, rtseg.RT_MARKER_OPEN, 5, 16, ctx=ctx))
+    out["recon_to_nuclei_open_r5"] = {"ms_per_tile": round(ms, 3)}
+    ms = timed(lambda: rtseg.rt_rbc_detect(rgb, 200, 150, ctx=ctx))
+    out["rbc_detect"] = {"ms_per_tile": round(ms, 3)}
+    ms = timed(lambda: rtseg.rt_segment_slide(rgb, 1024, 64, ctx=ctx))
+    out["stitch_1024_halo64"] = {"ms_per_slide": round(ms, 3), "mpx_per_s": round(N / (ms * 1e-3) / 1e6, 1),
+                                 "cores": 16}
+    for k, v in out.items():
+        log(f"  {k:28s} {v}")
+    return out
+
+
 def unet_forward_flops_per_px():
     """Algorithmic FLOPs per input pixel of one U-Net forward pass (2 per
     multiply-add; RGB input, levels of 16/32/64/128 channels, two 3x3 convs
@@ -309,8 +357,11 @@ def surrogate_leg(rtseg, synth, torch, args, plain_ms_4k):
     # config 5: a sample of the mixed stream, surrogate + fallback
     from concurrent.futures import ThreadPoolExecutor
     specs = [synth.spec_stream(20000 + i) for i in range(args.stream)]
+    tiles = []
     with ThreadPoolExecutor(8) as ex:
-        tiles = list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs))
+        for k0 in range(0, len(specs), 64):   # a progress line per 64 tiles
+            tiles += list(ex.map(lambda s: torch.from_numpy(synth.make_tile(s)[0]).to(d), specs[k0:k0 + 64]))
+            log(f"stream tiles generated: {len(tiles)}/{len(specs)}")
     recs, t_plain, t_sur = surrogate.evaluate(net, tiles, tau=args.tau, ctx=ctx)
     dice = np.array([1.0 if r["fallback"] else r["dice"] for r in recs])
     raw = np.array([r["dice"] for r in recs])
@@ -380,6 +431,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_4k.json"))
     ap.add_argument("--no-stream4k", action="store_true")
+    ap.add_argument("--no-next", action="store_true", help="skip the stages beside the segmentation")
     ap.add_argument("--tune-trials", action="store_true",
                     help="run tuning trials on a cache miss (default: the cached knob set or the defaults)")
     ap.add_argument("--stream4k-tiles", type=int, default=8)
@@ -532,6 +584,10 @@ def main():
             "pipeline_floor_frac": round(floor_frac, 5),
             "kernels": [{k2: (round(v, 5) if isinstance(v, float) else v) for k2, v in k.items()} for k in kern]}
 
+    nxt = None
+    if not args.no_next:
+        log("stages beside the segmentation on the 4096x4096 tile:")
+        nxt = next_rows_leg(rtseg, torch, rgb, lab, ctx)
     batch = None
     if not args.no_batch:
         batch = batch64(rtseg, synth, torch, args)
@@ -569,6 +625,7 @@ def main():
                    "knobs": knobs, "knobs_source": knobs_source, "ms_per_step_instrumented": round(ms_prof, 4), "stages": per_stage},
         "roofline": roof,
         "batch64": batch,
+        "next_rows": nxt,
         "stream4k": s4k,
         "host_stream4k": hs,
         "surrogate": sur,

@@ -469,6 +469,83 @@ __device__ int count_roots(const Crop<L> &m, int *red) {
     return tot;
 }
 
+// ---- column pass of the distance transform for the register classes ---------
+// Crops of at most R rows: thread c < min(cw, R) takes column c, reads the
+// column's membership once into a bit mask and runs both directions in
+// registers (rows at or beyond ch do not exist: the backward run starts
+// there as "no background pixel yet"), then stores the column distances.
+template <int R>
+__device__ __forceinline__ void edt_cols_reg(const Crop<int32_t> &m) {
+    const int c = threadIdx.x;
+    if (c >= R || c >= m.cw) return;
+    uint64_t in = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < m.ch && (m.fl[r * m.st + c] & F_IN)) in |= 1ull << r;
+    int d[R];
+    int run = GINF;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        run = ((in >> r) & 1) ? (run < GINF ? run + 1 : GINF) : 0;
+        d[r] = run;
+    }
+    run = GINF;
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+        if (r >= m.ch) continue;
+        run = ((in >> r) & 1) ? (run < GINF ? run + 1 : GINF) : 0;
+        d[r] = run < d[r] ? run : d[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < m.ch) m.A[r * m.st + c] = d[r];
+}
+
+// ---- number of regional maxima of Dq, capped at 2 (small register class) ----
+// After V = recon(Dq - 1 under Dq) in A: a component pixel with Dq - V > 0
+// lies in a regional maximum.  Wave 0 holds the crop's maxima as one 32-bit
+// row mask per column lane (lanes 32..63 mirror 0..31), floods from the first
+// maximum pixel in raster order through 8-neighbours inside the maxima
+// (vertical dilation by bit shifts, horizontal by DPP lane shifts) until
+// nothing changes, and reports 0 (no maximum), 1 (one 8-connected set) or 2
+// (a maximum pixel the flood did not reach).  The other waves wait.
+__device__ int count_maxima_reg(const Crop<int32_t> &m, int *red) {
+    const int tid = threadIdx.x;
+    if (tid < WAVE) {
+        const int c = tid & (RS_ - 1);
+        const bool first = c == 0, last = c == RS_ - 1;
+        uint32_t rm = 0;
+#pragma unroll
+        for (int j = 0; j < RS_; ++j) {
+            const int i = j * m.st + c;
+            if (j < m.ch && c < m.cw && (m.fl[i] & F_IN) && m.dq[i] - m.A[i] > 0) rm |= 1u << j;
+        }
+        // the first maximum pixel in raster order: the smallest (row, column)
+        int key = rm ? __builtin_ctz(rm) * RS_ + c : INT_MAX;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) key = min(key, __shfl_xor(key, d, WAVE));
+        int res = 0;
+        if (key != INT_MAX) {
+            uint32_t f = (rm && __builtin_ctz(rm) * RS_ + c == key) ? (1u << __builtin_ctz(rm)) : 0u;
+            for (;;) {
+                const uint32_t g = f | (f << 1) | (f >> 1);
+                const uint32_t gl = (uint32_t)__builtin_amdgcn_mov_dpp((int)g, 0x138, 0xf, 0xf, true);   // lane - 1
+                const uint32_t gr = (uint32_t)__builtin_amdgcn_mov_dpp((int)g, 0x130, 0xf, 0xf, true);   // lane + 1
+                const uint32_t nf = rm & (g | (first ? 0u : gl) | (last ? 0u : gr));
+                const bool grew = nf != f;
+                f = nf;
+                if (!__any(grew)) break;
+            }
+            res = __any((rm & ~f) != 0u) ? 2 : 1;
+        }
+        if (tid == 0) *red = res;
+    }
+    __syncthreads();
+    const int tot = *red;
+    __syncthreads();
+    return tot;
+}
+
 // ---- row pass of the distance transform for the register classes ------------
 // Crops of at most R x R in a plane of stride R + 1, NT threads: thread t
 // takes row t % R and the output columns [(t / R) P, (t / R + 1) P) with
@@ -532,19 +609,23 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
         }
     }
     const bool has_zero = wave_or(zero);
-    // ---- exact distance transform: column distances, then a pruned row search
-    for (int c = lane; c < m.cw; c += blockDim.x) {
-        int run = GINF;
-        for (int r = 0; r < m.ch; ++r) {
-            const int i = r * m.st + c;
-            run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
-            m.A[i] = run;
-        }
-        run = GINF;
-        for (int r = m.ch - 1; r >= 0; --r) {
-            const int i = r * m.st + c;
-            run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
-            if (run < m.A[i]) m.A[i] = run;
+    // ---- exact distance transform: column distances, then the row pass
+    if constexpr (R == RS_ || R == RM_) {
+        edt_cols_reg<R>(m);
+    } else {
+        for (int c = lane; c < m.cw; c += blockDim.x) {
+            int run = GINF;
+            for (int r = 0; r < m.ch; ++r) {
+                const int i = r * m.st + c;
+                run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
+                m.A[i] = run;
+            }
+            run = GINF;
+            for (int r = m.ch - 1; r >= 0; --r) {
+                const int i = r * m.st + c;
+                run = (m.fl[i] & F_IN) ? (run < GINF ? run + 1 : GINF) : 0;
+                if (run < m.A[i]) m.A[i] = run;
+            }
         }
     }
     __syncthreads();
@@ -590,13 +671,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - 1 : NEGV;
             __syncthreads();
             recon_any<R, L>(m, m.A, m.dq);
-            for (int i = lane; i < m.n; i += blockDim.x)
-                if ((m.fl[i] & F_IN) && m.dq[i] - m.A[i] > 0) m.fl[i] |= F_M;
-            __syncthreads();
-            crop_ccl<L, L>(m, F_M, m.B);
-            tot = count_roots(m, red);
-            for (int i = lane; i < m.n; i += blockDim.x) m.fl[i] &= (uint8_t)~F_M;
-            __syncthreads();
+            tot = count_maxima_reg(m, red);
         }
     }
     if (tot > 1) {
