@@ -307,6 +307,10 @@ int rt_segment_host_stream(rt_ctx *ctx, int32_t n, const rt_host_tile *tiles, co
  *                             whole call is two graph launches; recon_mode
  *                             must be 0; default 0
  *   "recon_async_rounds" 1..256 launched rounds in async mode; default 16
+ *   "objects_streams"   0|1   1: the three LDS per-object classes run side by
+ *                             side on the call's stream and two side streams;
+ *                             0: one after the other on the call's stream;
+ *                             default 1
  *   (read only) "recon_host_reads": worklist counters read by the host so far
  *   "objects_path"      0     routing of components to the per-object kernels:
  *                             crops <= 32^2 and <= 64^2 to the register-scan

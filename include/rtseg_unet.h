@@ -86,7 +86,9 @@ int rt_unet_get_step(rt_unet *net, int64_t *step);
  * each output pixel comes from the window whose kept part holds it, the
  * overlap of two windows being split at its middle.  fg_prob and seed_prob
  * are float maps (sigmoid of the logits) with pitch prob_pitch (elements).
- * Synchronises `stream` once per group of 16 windows.
+ * The windows run in groups of 16 back to back; the window origins of the
+ * whole tile are uploaded once, so the call waits on the host only for the
+ * previous call's origin upload (if still pending).
  */
 int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t w, int32_t h, float *fg_prob,
                     float *seed_prob, int64_t prob_pitch, void *stream);

@@ -373,7 +373,7 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool captur
     // the three per-object classes as parallel branches
     ObjStreams par{};
     (void)capturing;
-    if ((e = side_streams(c, par))) return e;
+    if (c->knobs.objects_streams && (e = side_streams(c, par))) return e;
     const bool obj_prof = c->prof_on && !capturing;
     if (obj_prof && (e = objects_timing(c, par))) return e;
     if ((e = launch_objects(at<ObjArgs>(c, P.o_ob), OL, c->n_cu, s, prof ? prof_event(c, 6) : nullptr, &par)))
@@ -630,7 +630,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     // ---- graph path: everything that fixes a launch parameter goes into the key
     std::vector<int64_t> key = {n, P.nlev, c->knobs.recon_max_sweeps, budget, c->n_cu, P.any_maps,
                                 c->knobs.objects_path, c->knobs.recon_mode, kq, c->knobs.recon_level_mode,
-                                c->knobs.recon_level_frac, async, ka,
+                                c->knobs.recon_level_frac, async, ka, c->knobs.objects_streams,
                                 (int64_t)(intptr_t)c->arena.base, (int64_t)(intptr_t)c->stamps,
                                 (int64_t)(intptr_t)c->lut};
     int64_t bits;
@@ -1510,6 +1510,9 @@ int rt_set_knob(rt_ctx *c, const char *name, int value) {
     } else if (n == "recon_queue_after") {
         CHECK(value >= 1 && value <= 64, "rt_set_knob: recon_queue_after must be 1..64");
         c->knobs.recon_queue_after = value;
+    } else if (n == "objects_streams") {
+        CHECK(value == 0 || value == 1, "rt_set_knob: objects_streams must be 0 or 1");
+        c->knobs.objects_streams = value;
     } else if (n == "recon_async") {
         CHECK(value == 0 || value == 1, "rt_set_knob: recon_async must be 0 or 1");
         c->knobs.recon_async = value;
@@ -1556,6 +1559,8 @@ int rt_get_knob(rt_ctx *c, const char *name, int *value) {
         *value = c->knobs.objects_path;
     else if (n == "recon_async")
         *value = c->knobs.recon_async;
+    else if (n == "objects_streams")
+        *value = c->knobs.objects_streams;
     else if (n == "recon_host_reads")
         *value = (int)std::min<int64_t>(c->recon_host_reads, INT32_MAX);
     else if (n == "recon_async_rounds")

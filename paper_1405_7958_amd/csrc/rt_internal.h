@@ -64,6 +64,7 @@ struct Knobs {
     int recon_async = 0;         // 1: no host read of the worklist -- recon_async_rounds launched rounds,
                                  // then the device-side finish (segmentation entry points)
     int recon_async_rounds = 16;
+    int objects_streams = 1;     // 1: the three per-object classes on three streams; 0: one after the other
 };
 
 // A captured segmentation batch: graph A = deconvolution, connectivity bound

@@ -130,6 +130,13 @@ struct rt_unet {
     bf16_t *packed = nullptr;
     int step = 0;
     Acts acts;
+    // window origins of a whole tile inference (device, pinned host copy, the
+    // event after its upload): uploaded once per call, so the window chunks
+    // run back to back with no host wait
+    int32_t *win_dev = nullptr, *win_host = nullptr;
+    int64_t win_cap = 0;
+    hipEvent_t win_done = nullptr;
+    bool win_pending = false;
 };
 
 namespace {
@@ -394,6 +401,9 @@ int rt_unet_destroy(rt_unet *net) {
     free_acts(net->acts);
     for (void *p : {(void *)net->P, (void *)net->G, (void *)net->M, (void *)net->V, (void *)net->packed})
         if (p) (void)hipFree(p);
+    if (net->win_dev) (void)hipFree(net->win_dev);
+    if (net->win_host) (void)hipHostFree(net->win_host);
+    if (net->win_done) (void)hipEventDestroy(net->win_done);
     delete net;
     return RT_OK;
 }
@@ -534,9 +544,30 @@ int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t
     int e = ensure_acts(net, chunk, win_h, win_w, false);
     if (e) return e;
     const Layer &H = layer(net, "head");
-    std::vector<int32_t> org(6 * (size_t)chunk);
+    // every chunk's origins (ox[nb], oy[nb], keep[4 nb]) back to back, one upload
+    const int64_t need = 6 * (int64_t)nwin;
+    if (net->win_pending) {   // the previous call's upload may still read the host copy
+        RT_HIP(hipEventSynchronize(net->win_done));
+        net->win_pending = false;
+    }
+    if (need > net->win_cap) {
+        RT_HIP(hipDeviceSynchronize());
+        if (net->win_dev) RT_HIP(hipFree(net->win_dev));
+        if (net->win_host) RT_HIP(hipHostFree(net->win_host));
+        net->win_dev = net->win_host = nullptr;
+        net->win_cap = 0;
+        if (hipMalloc((void **)&net->win_dev, sizeof(int32_t) * need) != hipSuccess ||
+            hipHostMalloc((void **)&net->win_host, sizeof(int32_t) * need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("rt_unet_forward: window origin buffers");
+            return RT_ENOMEM;
+        }
+        net->win_cap = need;
+    }
+    if (!net->win_done) RT_HIP(hipEventCreateWithFlags(&net->win_done, hipEventDisableTiming));
     for (int c0 = 0; c0 < nwin; c0 += chunk) {
         const int nb = std::min(chunk, nwin - c0);
+        int32_t *org = net->win_host + 6 * (int64_t)c0;
         for (int k = 0; k < nb; ++k) {
             const int wi = c0 + k;
             const int ix = wi % (int)px.size(), iy = wi / (int)px.size();
@@ -547,8 +578,13 @@ int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t
             org[2 * nb + 4 * k + 2] = pyl[iy];
             org[2 * nb + 4 * k + 3] = pyh[iy];
         }
-        int32_t *dorg = net->acts.origin;
-        RT_HIP(hipMemcpyAsync(dorg, org.data(), sizeof(int32_t) * 6 * nb, hipMemcpyHostToDevice, s));
+    }
+    RT_HIP(hipMemcpyAsync(net->win_dev, net->win_host, sizeof(int32_t) * need, hipMemcpyHostToDevice, s));
+    RT_HIP(hipEventRecord(net->win_done, s));
+    net->win_pending = true;
+    for (int c0 = 0; c0 < nwin; c0 += chunk) {
+        const int nb = std::min(chunk, nwin - c0);
+        int32_t *dorg = net->win_dev + 6 * (int64_t)c0;
         net->acts.n = nb;
         if ((e = nn_prep_input(rgb, rgb_pitch, w, h, dorg, dorg + nb, nb, win_h, win_w, net->acts.x0, s))) return e;
         if ((e = forward(net, s))) return e;
@@ -568,8 +604,6 @@ int rt_unet_forward(rt_unet *net, const uint8_t *rgb, int64_t rgb_pitch, int32_t
         ha.out_w = w;
         ha.out_h = h;
         if ((e = nn_head(ha, s))) return e;
-        // the origins buffer and its host copy are reused by the next chunk
-        RT_HIP(hipStreamSynchronize(s));
     }
     net->acts.n = chunk;
     return RT_OK;

@@ -417,7 +417,8 @@ def rt_segment_batch(rgbs, params=None, want_hq=False, ctx=None, want_maps=False
 
 RT_PROF_STAGES = 7
 KNOBS = ("recon_levels", "recon_level_mode", "recon_level_frac", "recon_round_batch", "recon_max_sweeps", "recon_mode",
-         "recon_queue_after", "objects_path", "graph", "graph_rounds", "recon_async", "recon_async_rounds")
+         "recon_queue_after", "objects_path", "graph", "graph_rounds", "recon_async", "recon_async_rounds",
+         "objects_streams")
 READ_ONLY = ("graph_captures", "graph_replays", "last_rounds", "recon_host_reads")
 
 

@@ -389,10 +389,11 @@ def test_segment_4k(rt, oracle):
                                    dict(recon_levels=8, recon_level_mode=1, recon_level_frac=300),
                                    dict(recon_levels=1, recon_level_mode=1, recon_level_frac=950),
                                    dict(recon_levels=5, recon_level_mode=1, recon_level_frac=1),
-                                   dict(recon_levels=0)])
+                                   dict(recon_levels=0), dict(objects_streams=0)])
 def test_segment_level_choices(rt, oracle, knobs):
-    """The threshold levels of the reconstruction's lower bound change only
-    speed: every choice gives the oracle's result."""
+    """The threshold levels of the reconstruction's lower bound (and the
+    per-object classes run one after the other instead of side by side)
+    change only speed: every choice gives the oracle's result."""
     d = dev()
     ctx = rt.Context(0)
     for k, v in knobs.items():
