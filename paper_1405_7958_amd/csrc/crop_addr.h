@@ -57,4 +57,22 @@ __host__ __device__ inline int64_t crop_load_offset(const CropGeom &q, int i, in
     return (int64_t)(q.cy0 + r) * pitch + q.cx0 + c;
 }
 
+// Dense order for the register classes (crops of at most 64 x 64): crop
+// pixel k (raster order over the crop's cw x ch pixels, not over the plane)
+// is row k / cw, column k - row cw, so a batch covers no padding column.  The
+// quotient is (k + 1/2) (1 / cw) rounded down in single precision: with
+// k < 4096 and cw <= 64 the rounding error of the two operations stays below
+// 1e-3 while (k + 1/2) / cw lies at least 1 / 128 from an integer, so the
+// result is exact (the host test also checks every k and cw of that range).
+__host__ __device__ inline int crop_dense_row(int k, float inv_cw) { return (int)(((float)k + 0.5f) * inv_cw); }
+
+// image offset loaded for crop pixel k, k clamped to [0, cw ch - 1]; inv_cw = 1.0f / cw
+__host__ __device__ inline int64_t crop_load_offset_dense(const CropGeom &q, int k, float inv_cw, int64_t pitch) {
+    const int last = q.cw * q.ch - 1;
+    k = k < last ? k : last;
+    k = k > 0 ? k : 0;
+    const int r = crop_dense_row(k, inv_cw);
+    return (int64_t)(q.cy0 + r) * pitch + q.cx0 + (k - r * q.cw);
+}
+
 }  // namespace rtseg

@@ -76,6 +76,36 @@ __device__ __forceinline__ int isqrt_exact(int64_t v) {
 
 __device__ __forceinline__ bool wave_or(bool b) { return __syncthreads_or(b) != 0; }
 
+// Within one wave: the hardware performs a wavefront's LDS operations in
+// order, so it suffices that every earlier LDS access has completed and that
+// the compiler moves no memory access across this point (a lane reads what
+// other lanes of the wave wrote, which per-thread alias analysis cannot see).
+__device__ __forceinline__ void wave_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Barrier between the passes over an LDS crop plane (32-bit labels).  A
+// one-wave workgroup needs no s_barrier, and no wait for its global stores
+// (which a workgroup barrier implies): the wave's own LDS operations are
+// performed in order.  Planes in global scratch (64-bit labels) keep the
+// workgroup barrier, whose wait orders the wave's global stores and loads.
+template <typename L>
+__device__ __forceinline__ void crop_sync() {
+    if (sizeof(L) == 4 && blockDim.x == WAVE)
+        wave_sync();
+    else
+        __syncthreads();
+}
+template <typename L>
+__device__ __forceinline__ bool crop_any(bool b) {
+    if (sizeof(L) == 4 && blockDim.x == WAVE) {
+        wave_sync();
+        return __any(b) != 0;
+    }
+    return __syncthreads_or(b) != 0;
+}
+
 __device__ int wave_max(int v, int *red) {
     if (threadIdx.x == 0) *red = NEGV;
     __syncthreads();
@@ -244,15 +274,6 @@ __device__ __forceinline__ bool reg_scan(int (&v)[R], const int (&mk)[R], bool f
         pr = last_col ? NEGV : sr;
     }
     return ch;
-}
-
-// Within one wave: the hardware performs a wavefront's LDS operations in
-// order, so it suffices that every earlier LDS access has completed and that
-// the compiler moves no memory access across this point (a lane reads what
-// other lanes of the wave wrote, which per-thread alias analysis cannot see).
-__device__ __forceinline__ void wave_sync() {
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // In place on the crop plane V, whose row stride is R + 1: the plane is the
@@ -501,86 +522,197 @@ __device__ __forceinline__ void edt_cols_reg(const Crop<int32_t> &m) {
         if (r < m.ch) m.A[r * m.st + c] = d[r];
 }
 
-// ---- number of regional maxima of Dq, capped at 2 (small register class) ----
-// After V = recon(Dq - 1 under Dq) in A: a component pixel with Dq - V > 0
-// lies in a regional maximum.  Wave 0 holds the crop's maxima as one 32-bit
-// row mask per column lane (lanes 32..63 mirror 0..31), floods from the first
-// maximum pixel in raster order through 8-neighbours inside the maxima
-// (vertical dilation by bit shifts, horizontal by DPP lane shifts) until
-// nothing changes, and reports 0 (no maximum), 1 (one 8-connected set) or 2
-// (a maximum pixel the flood did not reach).  The other waves wait.
-__device__ int count_maxima_reg(const Crop<int32_t> &m, int *red) {
+// ---- DPP lane shifts of a crop row mask (lane = crop column) ---------------
+// Lanes without a source read 0 (bound control), so a row mask shifted in
+// from beyond the wave is empty.
+__device__ __forceinline__ uint32_t from_left(uint32_t v) {   // lane i <- lane i - 1
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t from_right(uint32_t v) {  // lane i <- lane i + 1
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint64_t from_left(uint64_t v) {
+    return (uint64_t)from_left((uint32_t)(v >> 32)) << 32 | from_left((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t from_right(uint64_t v) {
+    return (uint64_t)from_right((uint32_t)(v >> 32)) << 32 | from_right((uint32_t)v);
+}
+__device__ __forceinline__ int from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+
+template <int R>
+struct RowMask;
+template <>
+struct RowMask<32> {
+    using T = uint32_t;
+};
+template <>
+struct RowMask<64> {
+    using T = uint64_t;
+};
+
+// ---- regional maxima of Dq in registers (register classes) -------------------
+// A component pixel lies in a regional maximum of Dq iff its plateau (the
+// 8-connected set of component pixels of its value through it) has no
+// 8-neighbour of larger value: the set Dq - recon(Dq - 1 under Dq) > 0.
+// Wave 0 holds one R-bit row mask per column lane (R = 32: lanes 32..63
+// mirror lanes 0..31): it marks the component pixels with a larger
+// neighbour, spreads the mark across equal neighbours (vertical steps by bit
+// shifts, horizontal and diagonal ones by DPP lane shifts) until it stops
+// growing, and returns the unmarked component pixels.  Dq is 0 outside the
+// component (and outside the crop rows and columns) and at least 2 inside
+// (distance >= 1 from the background), so no outside pixel is larger than or
+// equal to a component pixel.  Rows at or beyond ch hold no component pixel.
+template <int R>
+__device__ __forceinline__ typename RowMask<R>::T maxima_mask(const Crop<int32_t> &m) {
+    using MT = typename RowMask<R>::T;
+    const int c = threadIdx.x & (R - 1);
+    const bool first = c == 0, last = c == R - 1, col = c < m.cw;
+    MT in = 0, hi = 0, edn = 0, ert = 0, edr = 0, eur = 0;
+    // rows j - 1, j, j + 1: own value, left and right neighbours' values
+    int dp = 0, lp = 0, rp = 0;
+    int dc = col ? m.dq[c] : 0;
+    int lc = first ? 0 : from_left(dc), rc = last ? 0 : from_right(dc);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (j >= m.ch) break;
+        int dn = 0, ln = 0, rn = 0;
+        if (j + 1 < m.ch) {
+            dn = col ? m.dq[(j + 1) * m.st + c] : 0;
+            ln = first ? 0 : from_left(dn);
+            rn = last ? 0 : from_right(dn);
+        }
+        const int mx = max(max(max(dp, dn), max(lc, rc)), max(max(lp, ln), max(rp, rn)));
+        const MT bit = (MT)1 << j;
+        in |= dc > 0 ? bit : (MT)0;
+        hi |= mx > dc ? bit : (MT)0;
+        edn |= dc == dn ? bit : (MT)0;   // (j, c) ~ (j + 1, c)
+        ert |= dc == rc ? bit : (MT)0;   // (j, c) ~ (j, c + 1)
+        edr |= dc == rn ? bit : (MT)0;   // (j, c) ~ (j + 1, c + 1)
+        eur |= dc == rp ? bit : (MT)0;   // (j, c) ~ (j - 1, c + 1)
+        dp = dc, lp = lc, rp = rc;
+        dc = dn, lc = ln, rc = rn;
+    }
+    edn &= in, ert &= in, edr &= in, eur &= in;
+    MT n = hi & in;   // pixels whose plateau has a larger neighbour
+    for (;;) {
+        MT nr = from_right(n);
+        if (last) nr = 0;
+        MT x = (n & ert) | ((n & edr) << 1) | ((n & eur) >> 1);   // what lane c + 1 receives
+        MT xl = from_left(x);
+        if (first) xl = 0;
+        const MT nn = n | ((n & edn) << 1) | ((n >> 1) & edn) | (ert & nr) | (edr & (nr >> 1)) | (eur & (nr << 1)) | xl;
+        const bool grew = nn != n;
+        n = nn;
+        if (!__any(grew)) break;
+    }
+    return in & ~n;
+}
+
+// ---- number of regional maxima of Dq, capped at 2 (register classes) --------
+// Wave 0 floods from the first maximum pixel in raster order through
+// 8-neighbours inside the maxima mask (vertical dilation by bit shifts,
+// horizontal by DPP lane shifts) until nothing changes, and reports 0 (no
+// maximum), 1 (one 8-connected set) or 2 (a maximum pixel the flood did not
+// reach).  Two different regional maxima are never 8-adjacent (the lower of
+// two adjacent plateaus has a larger neighbour), so the 8-connected sets of
+// the mask are the regional maxima.  The other waves wait.
+template <int R, typename L>
+__device__ int count_maxima(const Crop<int32_t> &m, int *red) {
+    using MT = typename RowMask<R>::T;
     const int tid = threadIdx.x;
     if (tid < WAVE) {
-        const int c = tid & (RS_ - 1);
-        const bool first = c == 0, last = c == RS_ - 1;
-        uint32_t rm = 0;
-#pragma unroll
-        for (int j = 0; j < RS_; ++j) {
-            const int i = j * m.st + c;
-            if (j < m.ch && c < m.cw && (m.fl[i] & F_IN) && m.dq[i] - m.A[i] > 0) rm |= 1u << j;
-        }
+        const int c = tid & (R - 1);
+        const bool first = c == 0, last = c == R - 1;
+        const MT rm = maxima_mask<R>(m);
         // the first maximum pixel in raster order: the smallest (row, column)
-        int key = rm ? __builtin_ctz(rm) * RS_ + c : INT_MAX;
+        int key = rm ? (int)__builtin_ctzll((uint64_t)rm) * R + c : INT_MAX;
 #pragma unroll
         for (int d = 1; d < WAVE; d <<= 1) key = min(key, __shfl_xor(key, d, WAVE));
         int res = 0;
         if (key != INT_MAX) {
-            uint32_t f = (rm && __builtin_ctz(rm) * RS_ + c == key) ? (1u << __builtin_ctz(rm)) : 0u;
+            MT f = (rm && (int)__builtin_ctzll((uint64_t)rm) * R + c == key) ? (MT)1 << __builtin_ctzll((uint64_t)rm) : (MT)0;
             for (;;) {
-                const uint32_t g = f | (f << 1) | (f >> 1);
-                const uint32_t gl = (uint32_t)__builtin_amdgcn_mov_dpp((int)g, 0x138, 0xf, 0xf, true);   // lane - 1
-                const uint32_t gr = (uint32_t)__builtin_amdgcn_mov_dpp((int)g, 0x130, 0xf, 0xf, true);   // lane + 1
-                const uint32_t nf = rm & (g | (first ? 0u : gl) | (last ? 0u : gr));
+                const MT gv = f | (f << 1) | (f >> 1);
+                MT gl = from_left(gv), gr = from_right(gv);
+                if (first) gl = 0;
+                if (last) gr = 0;
+                const MT nf = rm & (gv | gl | gr);
                 const bool grew = nf != f;
                 f = nf;
                 if (!__any(grew)) break;
             }
-            res = __any((rm & ~f) != 0u) ? 2 : 1;
+            res = __any((rm & ~f) != 0) ? 2 : 1;
         }
         if (tid == 0) *red = res;
     }
-    __syncthreads();
+    crop_sync<L>();
     const int tot = *red;
-    __syncthreads();
+    crop_sync<L>();
     return tot;
+}
+
+__device__ __forceinline__ int isqrt_small(int v) {   // floor(sqrt(v)) for 0 <= v < 2^24
+    int r = (int)__builtin_amdgcn_sqrtf((float)v);   // within 1e-3 of sqrt(v): one step each way fixes it
+    r -= r * r > v;
+    r += (r + 1) * (r + 1) <= v;
+    return r;
 }
 
 // ---- row pass of the distance transform for the register classes ------------
 // Crops of at most R x R in a plane of stride R + 1, NT threads: thread t
-// takes row t % R and the output columns [(t / R) P, (t / R + 1) P) with
-// P = R * R / NT.  The row's column distances G (the column pass left them in
-// A) are read once into registers, capped at 2R (when the crop holds a
-// background pixel, every true distance in it is below 2R, so the cap never
-// decides a minimum), and each output is the minimum of (c - c')^2 + G(c')^2
-// over the whole row: independent register arithmetic instead of a search
-// with one LDS round trip per offset.
+// takes row t % R and the output columns c = t / R (mod NH), NH = NT / R.
+// With G(c') the column distances the column pass left in A, capped at 2R
+// (when the crop holds a background pixel every true distance in it is below
+// 2R, so the cap never decides a minimum), the squared distance is
+//   min over c' of (c - c')^2 + G(c')^2 = c^2 + min over c' of (E(c') - 2 c' c),
+//   E(c') = G(c')^2 + c'^2,
+// and E - 2 c' c lies in [-2 * 63 * 63, 128^2 + 63^2] for R <= 64, inside
+// 16 bits: two output columns share one packed 16-bit multiply-add and one
+// packed minimum per c'.  Columns c' >= cw take E = EPAD, which exceeds every
+// candidate of a crop column (at most (2R)^2 - c^2) by more than 2 (R-1)^2,
+// so they never decide the minimum and the loop over c' has a fixed length.
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
 template <int R, int NT>
-__device__ __forceinline__ void edt_rows_reg(const Crop<int32_t> &m, bool has_zero) {
-    static_assert((R * R) % NT == 0 && NT % R == 0, "thread layout");
-    constexpr int P = R * R / NT;
+__device__ __forceinline__ void edt_rows_pk(const Crop<int32_t> &m, bool has_zero) {
+    constexpr int NH = NT / R;
+    static_assert(NT % R == 0 && R <= 64, "thread layout / 16-bit range");
     const int t = threadIdx.x;
-    const int r = t % R, c0 = (t / R) * P;
-    if (r < m.ch) {
-        int g2[R];
+    const int r = t % R, h = t / R, cw = m.cw;
+    if (r >= m.ch) return;
+    constexpr int EPAD = R == 32 ? 16383 : 32767;
+    static_assert(EPAD - 2 * (R - 1) * (R - 1) > 4 * R * R, "padding never decides");
+    short e[R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const int g = c < m.cw ? min(m.A[r * m.st + c], 2 * R) : 2 * R;
-            g2[c] = g * g;
-        }
+    for (int cc = 0; cc < R; ++cc) {
+        const int gv = min(m.A[r * m.st + cc], 2 * R);
+        e[cc] = cc < cw ? (short)(gv * gv + cc * cc) : (short)EPAD;
+    }
+    const int np = (cw + 2 * NH - 1) / (2 * NH);
 #pragma unroll 1
-        for (int k = 0; k < P; ++k) {
-            const int c = c0 + k;
-            const int i = r * m.st + c;
-            int best = INT_MAX;
+    for (int p = 0; p < np; ++p) {
+        const int ca = h + 2 * NH * p, cb = ca + NH;
+        const short2_t cp = {(short)ca, (short)cb};
+        short2_t acc = {SHRT_MAX, SHRT_MAX};
 #pragma unroll
-            for (int cc = 0; cc < R; ++cc) best = min(best, (c - cc) * (c - cc) + g2[cc]);
+        for (int cc = 0; cc < R; ++cc) {
+            const short2_t k2 = {(short)(-2 * cc), (short)(-2 * cc)};
+            const short2_t e2 = {e[cc], e[cc]};
+            acc = __builtin_elementwise_min(acc, cp * k2 + e2);
+        }
+        const int cs[2] = {ca, cb}, bs[2] = {(int)acc.x + ca * ca, (int)acc.y + cb * cb};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int c = cs[s];
+            if (c >= R) continue;
+            const int i = r * m.st + c;
             int v = 0;
-            if (c < m.cw && (m.fl[i] & F_IN)) v = has_zero ? isqrt_exact(4 * (int64_t)best) : RT_DQ_MAX;
+            if (c < cw && (m.fl[i] & F_IN)) v = has_zero ? isqrt_small(4 * bs[s]) : RT_DQ_MAX;
             m.dq[i] = v;
         }
-        if (t < R) m.dq[r * m.st + R] = 0;   // the plane's last column (stride R + 1) is padding
     }
+    if (t < R) m.dq[r * m.st + R] = 0;   // the plane's last column (stride R + 1) is padding
 }
 
 // ---- the whole per-component stage ---------------------------------------------
@@ -592,23 +724,51 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // any is used (addresses clamped into the crop, crop_addr.h)
     const CropGeom geom{m.cx0, m.cy0, m.cw, m.ch, m.st, m.n};
     bool zero = false;
-    for (int i0 = 0; i0 < m.n; i0 += LOADS_IN_FLIGHT * (int)blockDim.x) {
-        int32_t v[LOADS_IN_FLIGHT];
+    if constexpr (R == RS_ || R == RM_) {
+        // register classes: loads by crop pixel (no padding column), the flag
+        // plane cleared (32-bit stores; the plane capacity is a multiple of 4)
+        // while the first batch is in flight
+        const int npx = m.cw * m.ch, nt = blockDim.x;
+        const float inv_cw = 1.0f / (float)m.cw;
+        for (int k0 = 0; k0 < npx; k0 += LOADS_IN_FLIGHT * nt) {
+            int32_t v[LOADS_IN_FLIGHT];
 #pragma unroll
-        for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
-            v[k] = a.labels[crop_load_offset(geom, i0 + k * (int)blockDim.x + lane, a.pitch)];
+            for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
+                v[k] = a.labels[crop_load_offset_dense(geom, k0 + k * nt + lane, inv_cw, a.pitch)];
+            if (k0 == 0) {
+                for (int w = lane; w < (m.n + 3) / 4; w += nt) ((uint32_t *)m.fl)[w] = 0;
+                crop_sync<L>();
+            }
 #pragma unroll
-        for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
-            const int i = i0 + k * (int)blockDim.x + lane;
-            if (i < m.n) {
-                const bool col = i % m.st < m.cw;
-                const bool in = col && v[k] == g;
-                zero |= col && !in;
-                m.fl[i] = in ? F_IN : 0;
+            for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
+                const int kk = k0 + k * nt + lane;
+                if (kk < npx) {
+                    const int r = crop_dense_row(kk, inv_cw);
+                    const bool in = v[k] == g;
+                    zero |= !in;
+                    if (in) m.fl[r * m.st + kk - r * m.cw] = F_IN;
+                }
+            }
+        }
+    } else {
+        for (int i0 = 0; i0 < m.n; i0 += LOADS_IN_FLIGHT * (int)blockDim.x) {
+            int32_t v[LOADS_IN_FLIGHT];
+#pragma unroll
+            for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
+                v[k] = a.labels[crop_load_offset(geom, i0 + k * (int)blockDim.x + lane, a.pitch)];
+#pragma unroll
+            for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
+                const int i = i0 + k * (int)blockDim.x + lane;
+                if (i < m.n) {
+                    const bool col = i % m.st < m.cw;
+                    const bool in = col && v[k] == g;
+                    zero |= col && !in;
+                    m.fl[i] = in ? F_IN : 0;
+                }
             }
         }
     }
-    const bool has_zero = wave_or(zero);
+    const bool has_zero = crop_any<L>(zero);
     // ---- exact distance transform: column distances, then the row pass
     if constexpr (R == RS_ || R == RM_) {
         edt_cols_reg<R>(m);
@@ -628,11 +788,11 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             }
         }
     }
-    __syncthreads();
+    crop_sync<L>();
     if constexpr (R == RS_) {
-        edt_rows_reg<RS_, WAVE>(m, has_zero);
+        edt_rows_pk<RS_, WAVE>(m, has_zero);
     } else if constexpr (R == RM_) {
-        edt_rows_reg<RM_, 2 * WAVE>(m, has_zero);
+        edt_rows_pk<RM_, 2 * WAVE>(m, has_zero);
     } else {
         for (int i = lane; i < m.n; i += blockDim.x) {
             const int c = i % m.st, r = i / m.st;
@@ -657,22 +817,16 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             m.dq[i] = isqrt_exact(4 * best);
         }
     }
-    __syncthreads();
+    crop_sync<L>();
     // ---- one regional maximum of Dq means one seed (register classes, when
     // no seed map is wanted): each regional maximum of the h-maxima transform
     // g = recon(Dq - h under Dq) contains a regional maximum of Dq (a plateau
     // of g at value v holds a point with Dq - h = v, and the component of
     // {Dq >= v + h} through it stays inside the plateau, so its top is a
-    // regional maximum of Dq), so g has at most as many.  Regional maxima of
-    // Dq: Dq - recon(Dq - 1 under Dq) > 0.
+    // regional maximum of Dq), so g has at most as many.
     int tot = 2;
-    if constexpr (R == RS_) {
-        if (!a.seeds && !a.fg_out) {
-            for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - 1 : NEGV;
-            __syncthreads();
-            recon_any<R, L>(m, m.A, m.dq);
-            tot = count_maxima_reg(m, red);
-        }
+    if constexpr (R == RS_ || R == RM_) {
+        if (!a.seeds && !a.fg_out) tot = count_maxima<R, L>(m, red);
     }
     if (tot > 1) {
         // ---- seeds
@@ -719,15 +873,28 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     if (tot <= 1) {
         // one seed (or none with external seeds): the whole component gets one
         // label, nothing is cut, and the relabelled component is the component
-        for (int i = lane; i < m.n; i += blockDim.x) {
-            if (!(m.fl[i] & F_IN)) continue;
-            const int c = i % m.st, r = i / m.st;
-            const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
-            a.labels[o] = area_ok ? g : 0;
-            a.mask[o] = area_ok ? 1 : 0;
+        // (its pixels already hold the label g)
+        if constexpr (R == RS_ || R == RM_) {
+            const int npx = m.cw * m.ch;
+            const float inv_cw = 1.0f / (float)m.cw;
+            for (int k = lane; k < npx; k += blockDim.x) {
+                const int r = crop_dense_row(k, inv_cw), c = k - r * m.cw;
+                if (!(m.fl[r * m.st + c] & F_IN)) continue;
+                const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+                if (!area_ok) a.labels[o] = 0;
+                a.mask[o] = area_ok ? 1 : 0;
+            }
+        } else {
+            for (int i = lane; i < m.n; i += blockDim.x) {
+                if (!(m.fl[i] & F_IN)) continue;
+                const int c = i % m.st, r = i / m.st;
+                const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+                if (!area_ok) a.labels[o] = 0;
+                a.mask[o] = area_ok ? 1 : 0;
+            }
         }
         if (lane == 0 && area_ok && a.n_kept) atomicAdd(a.n_kept, 1);
-        __syncthreads();
+        crop_sync<L>();
         return;
     }
     // ---- lambda = recon of (Dq on seeds) under Dq
