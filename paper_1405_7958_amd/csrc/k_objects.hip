@@ -490,36 +490,60 @@ __device__ int count_roots(const Crop<L> &m, int *red) {
     return tot;
 }
 
-// ---- column pass of the distance transform for the register classes ---------
-// Crops of at most R rows: thread c < min(cw, R) takes column c, reads the
-// column's membership once into a bit mask and runs both directions in
-// registers (rows at or beyond ch do not exist: the backward run starts
-// there as "no background pixel yet"), then stores the column distances.
 template <int R>
-__device__ __forceinline__ void edt_cols_reg(const Crop<int32_t> &m) {
+struct RowMask;
+template <>
+struct RowMask<32> {
+    using T = uint32_t;
+};
+template <>
+struct RowMask<64> {
+    using T = uint64_t;
+};
+
+// The planes the register-class steps of the distance transform and the
+// maxima test use, row stride st: flags, column distances G (capped at 2R)
+// and Dq.  The full per-object path keeps G and Dq in 32-bit planes, the
+// first small-class pass in bytes (both values stay below 256 there).
+template <typename GT, typename DT>
+struct RegPlanes {
+    const uint8_t *fl;
+    GT *G;
+    DT *D;
+    int st, cw, ch;
+};
+__device__ __forceinline__ RegPlanes<int32_t, int32_t> reg_planes(const Crop<int32_t> &m) {
+    return RegPlanes<int32_t, int32_t>{m.fl, m.A, m.dq, m.st, m.cw, m.ch};
+}
+
+// ---- column pass of the distance transform for the register classes ---------
+// Crops of at most R rows: thread c < min(cw, R) takes column c and reads its
+// membership once into a row mask; the distance of row r to the nearest
+// background row above (the highest background bit at or below r) and below
+// (the lowest at or above r) come from bit scans, rows at or beyond ch being
+// no background (they lie outside the crop).  Stores the column distances
+// capped at 2R (the cap the row pass applies; no background in the column:
+// the cap).
+template <int R, typename GT, typename DT>
+__device__ __forceinline__ void edt_cols_reg(const RegPlanes<GT, DT> &m) {
+    using MT = typename RowMask<R>::T;
     const int c = threadIdx.x;
     if (c >= R || c >= m.cw) return;
-    uint64_t in = 0;
+    MT in = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (r < m.ch && (m.fl[r * m.st + c] & F_IN)) in |= 1ull << r;
-    int d[R];
-    int run = GINF;
+        if (r < m.ch && (m.fl[r * m.st + c] & F_IN)) in |= (MT)1 << r;
+    const MT rows = m.ch >= R ? ~(MT)0 : (((MT)1 << m.ch) - 1);
+    const uint64_t bg = (uint64_t)(~in & rows);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        run = ((in >> r) & 1) ? (run < GINF ? run + 1 : GINF) : 0;
-        d[r] = run;
+        if (r >= m.ch) break;
+        const uint64_t above = r == 63 ? bg : bg & ((2ull << r) - 1);
+        const uint64_t below = bg >> r;
+        const int up = above ? r - (63 - __builtin_clzll(above)) : 2 * R;
+        const int dn = below ? __builtin_ctzll(below) : 2 * R;
+        m.G[r * m.st + c] = (GT)min(min(up, dn), 2 * R);
     }
-    run = GINF;
-#pragma unroll
-    for (int r = R - 1; r >= 0; --r) {
-        if (r >= m.ch) continue;
-        run = ((in >> r) & 1) ? (run < GINF ? run + 1 : GINF) : 0;
-        d[r] = run < d[r] ? run : d[r];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (r < m.ch) m.A[r * m.st + c] = d[r];
 }
 
 // ---- DPP lane shifts of a crop row mask (lane = crop column) ---------------
@@ -540,51 +564,44 @@ __device__ __forceinline__ uint64_t from_right(uint64_t v) {
 __device__ __forceinline__ int from_left(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ int from_right(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 
-template <int R>
-struct RowMask;
-template <>
-struct RowMask<32> {
-    using T = uint32_t;
-};
-template <>
-struct RowMask<64> {
-    using T = uint64_t;
-};
 
-// ---- regional maxima of Dq in registers (register classes) -------------------
-// A component pixel lies in a regional maximum of Dq iff its plateau (the
-// 8-connected set of component pixels of its value through it) has no
-// 8-neighbour of larger value: the set Dq - recon(Dq - 1 under Dq) > 0.
-// Wave 0 holds one R-bit row mask per column lane (R = 32: lanes 32..63
-// mirror lanes 0..31): it marks the component pixels with a larger
-// neighbour, spreads the mark across equal neighbours (vertical steps by bit
-// shifts, horizontal and diagonal ones by DPP lane shifts) until it stops
-// growing, and returns the unmarked component pixels.  Dq is 0 outside the
-// component (and outside the crop rows and columns) and at least 2 inside
-// (distance >= 1 from the background), so no outside pixel is larger than or
-// equal to a component pixel.  Rows at or beyond ch hold no component pixel.
-template <int R>
-__device__ __forceinline__ typename RowMask<R>::T maxima_mask(const Crop<int32_t> &m) {
+// ---- regional maxima in registers (register classes) -------------------------
+// A component pixel lies in a regional maximum of a plane V iff its plateau
+// (the 8-connected set of component pixels of its value through it) has no
+// 8-neighbour in the component of larger value: the set V - recon(V - 1
+// under V) > 0.  Wave 0 holds one R-bit row mask per column lane (R = 32:
+// lanes 32..63 mirror lanes 0..31): it marks the component pixels with a
+// larger neighbour, spreads the mark across equal neighbours (vertical steps
+// by bit shifts, horizontal and diagonal ones by DPP lane shifts) until it
+// stops growing, and returns the unmarked component pixels.  Membership comes
+// from the flags; pixels outside the component (and outside the crop rows and
+// columns) take NEGV, which no component value reaches, so they are neither
+// larger than nor equal to a component pixel.
+template <int R, typename GT, typename DT>
+__device__ __forceinline__ typename RowMask<R>::T maxima_mask(const RegPlanes<GT, DT> &m) {
     using MT = typename RowMask<R>::T;
     const int c = threadIdx.x & (R - 1);
     const bool first = c == 0, last = c == R - 1, col = c < m.cw;
     MT in = 0, hi = 0, edn = 0, ert = 0, edr = 0, eur = 0;
+    auto value = [&](int j) -> int {
+        return (col && (m.fl[j * m.st + c] & F_IN)) ? (int)m.D[j * m.st + c] : NEGV;
+    };
     // rows j - 1, j, j + 1: own value, left and right neighbours' values
-    int dp = 0, lp = 0, rp = 0;
-    int dc = col ? m.dq[c] : 0;
-    int lc = first ? 0 : from_left(dc), rc = last ? 0 : from_right(dc);
+    int dp = NEGV, lp = NEGV, rp = NEGV;
+    int dc = value(0);
+    int lc = first ? NEGV : from_left(dc), rc = last ? NEGV : from_right(dc);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         if (j >= m.ch) break;
-        int dn = 0, ln = 0, rn = 0;
+        int dn = NEGV, ln = NEGV, rn = NEGV;
         if (j + 1 < m.ch) {
-            dn = col ? m.dq[(j + 1) * m.st + c] : 0;
-            ln = first ? 0 : from_left(dn);
-            rn = last ? 0 : from_right(dn);
+            dn = value(j + 1);
+            ln = first ? NEGV : from_left(dn);
+            rn = last ? NEGV : from_right(dn);
         }
         const int mx = max(max(max(dp, dn), max(lc, rc)), max(max(lp, ln), max(rp, rn)));
         const MT bit = (MT)1 << j;
-        in |= dc > 0 ? bit : (MT)0;
+        in |= dc != NEGV ? bit : (MT)0;
         hi |= mx > dc ? bit : (MT)0;
         edn |= dc == dn ? bit : (MT)0;   // (j, c) ~ (j + 1, c)
         ert |= dc == rc ? bit : (MT)0;   // (j, c) ~ (j, c + 1)
@@ -609,6 +626,49 @@ __device__ __forceinline__ typename RowMask<R>::T maxima_mask(const Crop<int32_t
     return in & ~n;
 }
 
+// ---- row-mask set operations of wave 0 (lane = crop column) -----------------
+// 8-neighbourhood dilation (the set and its neighbours inside the crop columns
+// of the lane layout)
+template <int R>
+__device__ __forceinline__ typename RowMask<R>::T dilate8(typename RowMask<R>::T f, bool first, bool last) {
+    using MT = typename RowMask<R>::T;
+    const MT v = f | (f << 1) | (f >> 1);
+    MT l = from_left(v), r = from_right(v);
+    if (first) l = 0;
+    if (last) r = 0;
+    return v | l | r;
+}
+// the first pixel of f in raster order as row * R + column (INT_MAX: f empty)
+template <int R>
+__device__ __forceinline__ int first_key(typename RowMask<R>::T f, int c) {
+    int key = f ? (int)__builtin_ctzll((uint64_t)f) * R + c : INT_MAX;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) key = min(key, __shfl_xor(key, d, WAVE));
+    return key;
+}
+// the 8-connected part of `set` through the pixel `key` (a pixel of set)
+template <int R>
+__device__ __forceinline__ typename RowMask<R>::T flood_from(typename RowMask<R>::T set, int key, int c, bool first,
+                                                             bool last) {
+    using MT = typename RowMask<R>::T;
+    MT f = (key % R == c) ? (((MT)1 << (key / R)) & set) : (MT)0;
+    for (;;) {
+        const MT nf = set & dilate8<R>(f, first, last);
+        const bool grew = nf != f;
+        f = nf;
+        if (!__any(grew)) break;
+    }
+    return f;
+}
+// number of pixels of f over the crop columns (lanes 0..R-1)
+template <int R>
+__device__ __forceinline__ int mask_area(typename RowMask<R>::T f) {
+    int n = (int)(threadIdx.x & (WAVE - 1)) < R ? __builtin_popcountll((uint64_t)f) : 0;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) n += __shfl_xor(n, d, WAVE);
+    return n;
+}
+
 // ---- number of regional maxima of Dq, capped at 2 (register classes) --------
 // Wave 0 floods from the first maximum pixel in raster order through
 // 8-neighbours inside the maxima mask (vertical dilation by bit shifts,
@@ -617,31 +677,18 @@ __device__ __forceinline__ typename RowMask<R>::T maxima_mask(const Crop<int32_t
 // reach).  Two different regional maxima are never 8-adjacent (the lower of
 // two adjacent plateaus has a larger neighbour), so the 8-connected sets of
 // the mask are the regional maxima.  The other waves wait.
-template <int R, typename L>
-__device__ int count_maxima(const Crop<int32_t> &m, int *red) {
+template <int R, typename L, typename GT, typename DT>
+__device__ int count_maxima(const RegPlanes<GT, DT> &m, int *red) {
     using MT = typename RowMask<R>::T;
     const int tid = threadIdx.x;
     if (tid < WAVE) {
         const int c = tid & (R - 1);
         const bool first = c == 0, last = c == R - 1;
         const MT rm = maxima_mask<R>(m);
-        // the first maximum pixel in raster order: the smallest (row, column)
-        int key = rm ? (int)__builtin_ctzll((uint64_t)rm) * R + c : INT_MAX;
-#pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) key = min(key, __shfl_xor(key, d, WAVE));
         int res = 0;
+        const int key = first_key<R>(rm, c);
         if (key != INT_MAX) {
-            MT f = (rm && (int)__builtin_ctzll((uint64_t)rm) * R + c == key) ? (MT)1 << __builtin_ctzll((uint64_t)rm) : (MT)0;
-            for (;;) {
-                const MT gv = f | (f << 1) | (f >> 1);
-                MT gl = from_left(gv), gr = from_right(gv);
-                if (first) gl = 0;
-                if (last) gr = 0;
-                const MT nf = rm & (gv | gl | gr);
-                const bool grew = nf != f;
-                f = nf;
-                if (!__any(grew)) break;
-            }
+            const MT f = flood_from<R>(rm, key, c, first, last);
             res = __any((rm & ~f) != 0) ? 2 : 1;
         }
         if (tid == 0) *red = res;
@@ -674,8 +721,8 @@ __device__ __forceinline__ int isqrt_small(int v) {   // floor(sqrt(v)) for 0 <=
 // so they never decide the minimum and the loop over c' has a fixed length.
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-template <int R, int NT>
-__device__ __forceinline__ void edt_rows_pk(const Crop<int32_t> &m, bool has_zero) {
+template <int R, int NT, typename GT, typename DT>
+__device__ __forceinline__ void edt_rows_pk(const RegPlanes<GT, DT> &m, bool has_zero) {
     constexpr int NH = NT / R;
     static_assert(NT % R == 0 && R <= 64, "thread layout / 16-bit range");
     const int t = threadIdx.x;
@@ -683,11 +730,15 @@ __device__ __forceinline__ void edt_rows_pk(const Crop<int32_t> &m, bool has_zer
     if (r >= m.ch) return;
     constexpr int EPAD = R == 32 ? 16383 : 32767;
     static_assert(EPAD - 2 * (R - 1) * (R - 1) > 4 * R * R, "padding never decides");
-    short e[R];
+    short2_t e[R / 2];   // E of columns 2k and 2k + 1
 #pragma unroll
     for (int cc = 0; cc < R; ++cc) {
-        const int gv = min(m.A[r * m.st + cc], 2 * R);
-        e[cc] = cc < cw ? (short)(gv * gv + cc * cc) : (short)EPAD;
+        const int gv = min((int)m.G[r * m.st + cc], 2 * R);
+        const short ev = cc < cw ? (short)(gv * gv + cc * cc) : (short)EPAD;
+        if (cc & 1)
+            e[cc / 2].y = ev;
+        else
+            e[cc / 2].x = ev;
     }
     const int np = (cw + 2 * NH - 1) / (2 * NH);
 #pragma unroll 1
@@ -698,7 +749,8 @@ __device__ __forceinline__ void edt_rows_pk(const Crop<int32_t> &m, bool has_zer
 #pragma unroll
         for (int cc = 0; cc < R; ++cc) {
             const short2_t k2 = {(short)(-2 * cc), (short)(-2 * cc)};
-            const short2_t e2 = {e[cc], e[cc]};
+            const short ev = (cc & 1) ? e[cc / 2].y : e[cc / 2].x;
+            const short2_t e2 = {ev, ev};
             acc = __builtin_elementwise_min(acc, cp * k2 + e2);
         }
         const int cs[2] = {ca, cb}, bs[2] = {(int)acc.x + ca * ca, (int)acc.y + cb * cb};
@@ -709,15 +761,183 @@ __device__ __forceinline__ void edt_rows_pk(const Crop<int32_t> &m, bool has_zer
             const int i = r * m.st + c;
             int v = 0;
             if (c < cw && (m.fl[i] & F_IN)) v = has_zero ? isqrt_small(4 * bs[s]) : RT_DQ_MAX;
-            m.dq[i] = v;
+            m.D[i] = (DT)v;
         }
     }
-    if (t < R) m.dq[r * m.st + R] = 0;   // the plane's last column (stride R + 1) is padding
+    if (t < R) m.D[r * m.st + R] = 0;   // the plane's last column (stride R + 1) is padding
+}
+
+// ---- seeds, flood, cut and relabelling in registers (register classes) -------
+// Entered with g = the h-maxima transform of Dq in plane A; without external
+// seeds and seed maps.  The seeds are the regional maxima of g; their
+// 8-connected sets, ordered by first pixel (their labels: the crop index of
+// that pixel, so label order is raster order), are held by wave 0 as row
+// masks S_k.  With more than KMAX of them the call returns -1 and has changed
+// nothing (the caller runs the plane-based path); with one it returns 1 (one
+// seed: the caller labels the component whole).  Otherwise:
+//   * lambda = recon of (Dq on the seeds) under Dq, as in the plane path;
+//   * flood, level by level from the highest lambda: the level's unlabelled
+//     pixels are reached by synchronous breadth-first steps from the pixels
+//     labelled before the level (distance 1) and then from those reached in
+//     the previous step; a pixel reached in a step takes the smallest label
+//     among the sets that reach it in that step (the smallest key (distance,
+//     label) of the plane flood); pixels of a level never reached stay
+//     unlabelled;
+//   * cut: a labelled pixel is kept iff no component neighbour has a smaller
+//     label or is unlabelled (unlabelled pixels count as label -1 and are
+//     always kept), so the kept pixels of different labels are never adjacent;
+//   * relabelling: each 8-connected piece of the kept pixels of one label (or
+//     of the unlabelled ones) is labelled by its first pixel and kept when
+//     its area passes the final filter; the component's pixels are written.
+// Returns 2 when the component is done.  The seed sets wait in plane B (as
+// 64-bit words) while the lambda reconstruction holds the registers.
+constexpr int KMAX = 8;
+
+template <int R, typename L>
+__device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16_t *tw) {
+    using MT = typename RowMask<R>::T;
+    const int tid = threadIdx.x;
+    const int c = tid & (R - 1);
+    const bool first = c == 0, last = c == R - 1, lead = tid < WAVE;
+    const bool col = c < m.cw, writer = tid < R && col;
+    uint64_t *stash = (uint64_t *)m.B;   // KMAX x WAVE words (plane B holds at least R (R + 1) 4-byte entries)
+    MT S[KMAX];
+    int K = 0;
+    if (lead) {
+        const MT rm = maxima_mask<R>(RegPlanes<int32_t, int32_t>{m.fl, m.A, m.A, m.st, m.cw, m.ch});
+        MT rest = rm;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            S[k] = 0;
+            if (__any(rest != 0)) {
+                S[k] = flood_from<R>(rest, first_key<R>(rest, c), c, first, last);
+                rest &= ~S[k];
+                ++K;
+            }
+        }
+        if (__any(rest != 0)) K = KMAX + 1;
+        if (tid == 0) *red = K;
+    }
+    crop_sync<L>();
+    K = *red;
+    crop_sync<L>();
+    if (K > KMAX) return -1;
+    if (K <= 1) return 1;
+    // lambda marker: Dq on the seeds (wave 0 writes its columns; reg_recon
+    // sets everything outside the crop and the component itself)
+    if (lead) {
+        MT seeds = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            seeds |= S[k];
+            stash[k * WAVE + tid] = (uint64_t)S[k];
+        }
+        if (writer)
+            for (int j = 0; j < m.ch; ++j) {
+                const int i = j * m.st + c;
+                m.A[i] = ((seeds >> j) & 1) ? m.dq[i] : NEGV;
+            }
+    }
+    crop_sync<L>();
+    recon_any<R, L>(m, m.A, m.dq, tw, red);   // A = lambda
+    int kept = 0;
+    if (lead) {
+        MT inm = 0, lab = 0;
+        int lam[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            lam[j] = NEGV;
+            if (j < m.ch && col && (m.fl[j * m.st + c] & F_IN)) {
+                inm |= (MT)1 << j;
+                lam[j] = m.A[j * m.st + c];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            S[k] = (MT)stash[k * WAVE + tid];
+            lab |= S[k];
+        }
+        MT U = inm & ~lab, unreached = 0;
+        // flood, level by level
+        for (;;) {
+            int lv_val = NEGV;
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if ((U >> j) & 1) lv_val = max(lv_val, lam[j]);
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) lv_val = max(lv_val, __shfl_xor(lv_val, d, WAVE));
+            if (lv_val == NEGV) break;
+            MT lv = 0;
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (((U >> j) & 1) && lam[j] == lv_val) lv |= (MT)1 << j;
+            U &= ~lv;
+            MT F[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) F[k] = S[k];
+            for (;;) {
+                MT taken = 0;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    const MT nk = k < K ? dilate8<R>(F[k], first, last) & lv & ~taken : (MT)0;
+                    taken |= nk;
+                    F[k] = nk;
+                    S[k] |= nk;
+                }
+                lv &= ~taken;
+                if (!__any(taken != 0)) break;
+            }
+            unreached |= lv;
+        }
+        unreached |= U;   // pixels lambda never reached (none when every pixel is connected to a seed)
+        // cut: kept iff no neighbour of a smaller label (unreached pixels: -1)
+        MT P = unreached, keep_all = unreached;
+        MT keep[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            keep[k] = S[k] & ~dilate8<R>(P, first, last);
+            P |= S[k];
+            keep_all |= keep[k];
+        }
+        // pixels cut away
+        const int64_t rowbase = (int64_t)m.cy0 * a.pitch + m.cx0 + c;
+        if (writer)
+            for (MT b = inm & ~keep_all; b; b &= b - 1) {
+                const int64_t o = rowbase + (int64_t)__builtin_ctzll((uint64_t)b) * a.pitch;
+                a.labels[o] = 0;
+                a.mask[o] = 0;
+            }
+        // pieces of each label's kept pixels, and of the unreached ones
+#pragma unroll
+        for (int k = 0; k <= KMAX; ++k) {
+            MT rest = k < KMAX ? keep[k] : unreached;
+            while (__any(rest != 0)) {
+                const int key = first_key<R>(rest, c);
+                const MT f = flood_from<R>(rest, key, c, first, last);
+                rest &= ~f;
+                const int ar = mask_area<R>(f);
+                int lb = 0;
+                if (ar >= a.min_area && (a.max_area < 0 || ar <= a.max_area)) {
+                    lb = (m.cy0 + key / R) * a.w + m.cx0 + key % R + 1;
+                    ++kept;
+                }
+                if (writer)
+                    for (MT b = f; b; b &= b - 1) {
+                        const int64_t o = rowbase + (int64_t)__builtin_ctzll((uint64_t)b) * a.pitch;
+                        a.labels[o] = lb;
+                        a.mask[o] = lb ? 1 : 0;
+                    }
+            }
+        }
+        if (tid == 0 && kept && a.n_kept) atomicAdd(a.n_kept, kept);
+    }
+    crop_sync<L>();
+    return 2;
 }
 
 // ---- the whole per-component stage ---------------------------------------------
 template <int R, typename L>
-__device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int16_t *tw = nullptr) {
+__device__ __forceinline__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int *hist, int16_t *tw = nullptr) {
     const int lane = threadIdx.x;
     const int area = a.st_area[g];
     // ---- load the component: LOADS_IN_FLIGHT loads per thread issued before
@@ -771,7 +991,7 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     const bool has_zero = crop_any<L>(zero);
     // ---- exact distance transform: column distances, then the row pass
     if constexpr (R == RS_ || R == RM_) {
-        edt_cols_reg<R>(m);
+        edt_cols_reg<R>(reg_planes(m));
     } else {
         for (int c = lane; c < m.cw; c += blockDim.x) {
             int run = GINF;
@@ -790,9 +1010,9 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     }
     crop_sync<L>();
     if constexpr (R == RS_) {
-        edt_rows_pk<RS_, WAVE>(m, has_zero);
+        edt_rows_pk<RS_, WAVE>(reg_planes(m), has_zero);
     } else if constexpr (R == RM_) {
-        edt_rows_pk<RM_, 2 * WAVE>(m, has_zero);
+        edt_rows_pk<RM_, 2 * WAVE>(reg_planes(m), has_zero);
     } else {
         for (int i = lane; i < m.n; i += blockDim.x) {
             const int c = i % m.st, r = i / m.st;
@@ -825,8 +1045,9 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
     // {Dq >= v + h} through it stays inside the plateau, so its top is a
     // regional maximum of Dq), so g has at most as many.
     int tot = 2;
+    bool one_seed = false;   // the register path found one seed
     if constexpr (R == RS_ || R == RM_) {
-        if (!a.seeds && !a.fg_out) tot = count_maxima<R, L>(m, red);
+        if (!a.seeds && !a.fg_out) tot = count_maxima<R, L>(reg_planes(m), red);
     }
     if (tot > 1) {
         // ---- seeds
@@ -847,27 +1068,40 @@ __device__ void process_object(const ObjArgs &a, int g, Crop<L> m, int *red, int
             for (int i = lane; i < m.n; i += blockDim.x) m.A[i] = (m.fl[i] & F_IN) ? m.dq[i] - a.h_seed : NEGV;
             __syncthreads();
             recon_any<R, L>(m, m.A, m.dq, tw, red);  // g = h-maxima of Dq
-            for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
-            __syncthreads();
-            if constexpr (R > 0 || sizeof(L) == 4)
-                recon_any<R, L>(m, (int32_t *)m.B, m.A, tw, red);   // recon of g-1 under g
-            else
-                recon_scans<L, L>(m, m.B, m.A);
-            for (int i = lane; i < m.n; i += blockDim.x)
-                if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
-            __syncthreads();
-        }
-        if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
-            for (int i = lane; i < m.n; i += blockDim.x) {
-                if (!(m.fl[i] & F_IN)) continue;
-                const int c = i % m.st, r = i / m.st;
-                const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
-                a.fg_out[o] = 1;
-                a.seeds_out[o] = (m.fl[i] & F_RM) ? 1 : 0;
+            if constexpr (R == RS_ || R == RM_) {
+                if (!a.fg_out) {
+                    const int r = reg_watershed<R, L>(a, m, red, tw);
+                    if (r == 2) return;
+                    one_seed = r == 1;
+                }
+            }
+            if (!one_seed) {
+                for (int i = lane; i < m.n; i += blockDim.x) m.B[i] = (m.fl[i] & F_IN) ? (L)(m.A[i] - 1) : (L)NEGV;
+                __syncthreads();
+                if constexpr (R > 0 || sizeof(L) == 4)
+                    recon_any<R, L>(m, (int32_t *)m.B, m.A, tw, red);   // recon of g-1 under g
+                else
+                    recon_scans<L, L>(m, m.B, m.A);
+                for (int i = lane; i < m.n; i += blockDim.x)
+                    if ((m.fl[i] & F_IN) && (L)m.A[i] - m.B[i] > 0) m.fl[i] |= F_RM;
+                __syncthreads();
             }
         }
-        crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
-        tot = count_roots(m, red);
+        if (one_seed) {
+            tot = 1;
+        } else {
+            if (a.fg_out) {   // the foreground A and its seed map, for callers that want them
+                for (int i = lane; i < m.n; i += blockDim.x) {
+                    if (!(m.fl[i] & F_IN)) continue;
+                    const int c = i % m.st, r = i / m.st;
+                    const int64_t o = (int64_t)(m.cy0 + r) * a.pitch + m.cx0 + c;
+                    a.fg_out[o] = 1;
+                    a.seeds_out[o] = (m.fl[i] & F_RM) ? 1 : 0;
+                }
+            }
+            crop_ccl<L, L>(m, F_RM, m.B);  // B = seed label (crop index of the seed root) or -1
+            tot = count_roots(m, red);
+        }
     }
     const bool area_ok = area >= a.min_area && (a.max_area < 0 || area <= a.max_area);
     if (tot <= 1) {
@@ -1035,6 +1269,66 @@ __device__ void erase_object(const ObjArgs &a, int g, const CropGeom &q) {
     }
 }
 
+// ---- first small-class pass: components with at most one seed ---------------
+// Crops of at most 32 x 32, one wave, byte planes (flags, capped column
+// distances, Dq: all below 256 for these crops) in `pl` (3 CAP_S bytes), so
+// many waves fit a CU.  Loads the component, and unless its crop holds no
+// background pixel (then Dq is constant on it: one maximum), runs the
+// distance transform and counts the regional maxima of Dq.  At most one
+// means one seed (see process_object): the component keeps its label g when
+// its area passes the final filter and is erased otherwise, and the call
+// returns true.  Otherwise it returns false and writes nothing: the caller
+// defers the component to the full path.
+__device__ __forceinline__ bool single_seed_object(const ObjArgs &a, int g, const CropGeom &q, uint8_t *pl, int *red) {
+    const int lane = threadIdx.x;
+    const RegPlanes<uint8_t, uint8_t> p{pl, pl + CAP_S, pl + 2 * CAP_S, q.st, q.cw, q.ch};
+    uint8_t *fl = pl;
+    const int npx = q.cw * q.ch;
+    const float inv_cw = 1.0f / (float)q.cw;
+    bool zero = false;
+    for (int k0 = 0; k0 < npx; k0 += LOADS_IN_FLIGHT * WAVE) {
+        int32_t v[LOADS_IN_FLIGHT];
+#pragma unroll
+        for (int k = 0; k < LOADS_IN_FLIGHT; ++k)
+            v[k] = a.labels[crop_load_offset_dense(q, k0 + k * WAVE + lane, inv_cw, a.pitch)];
+        if (k0 == 0)
+            for (int w = lane; w < (q.n + 3) / 4; w += WAVE) ((uint32_t *)fl)[w] = 0;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < LOADS_IN_FLIGHT; ++k) {
+            const int kk = k0 + k * WAVE + lane;
+            if (kk < npx) {
+                const int r = crop_dense_row(kk, inv_cw);
+                const bool in = v[k] == g;
+                zero |= !in;
+                if (in) fl[r * q.st + kk - r * q.cw] = F_IN;
+            }
+        }
+    }
+    wave_sync();
+    int tot = 1;
+    if (__any(zero)) {
+        edt_cols_reg<RS_>(p);
+        wave_sync();
+        edt_rows_pk<RS_, WAVE>(p, true);
+        wave_sync();
+        tot = count_maxima<RS_, int32_t>(p, red);
+    }
+    if (tot > 1) return false;
+    const int area = a.st_area[g];
+    const bool area_ok = area >= a.min_area && (a.max_area < 0 || area <= a.max_area);
+    for (int k = lane; k < npx; k += WAVE) {
+        const int r = crop_dense_row(k, inv_cw), c = k - r * q.cw;
+        if (!(fl[r * q.st + c] & F_IN)) continue;
+        const int64_t o = (int64_t)(q.cy0 + r) * a.pitch + q.cx0 + c;
+        if (!area_ok) a.labels[o] = 0;
+        a.mask[o] = area_ok ? 1 : 0;
+    }
+    if (lane == 0 && area_ok && a.n_kept) atomicAdd(a.n_kept, 1);
+    wave_sync();
+    return true;
+}
+
 template <int CAP>
 __device__ __forceinline__ Crop<int32_t> lds_crop(unsigned char *smem, const CropGeom &q) {
     Crop<int32_t> m;
@@ -1098,12 +1392,13 @@ __global__ void k_objects_classify(const ObjArgs *args, ObjLists L) {
     }
 }
 
-// small class: erases components below the first area threshold and
-// processes crops up to 32 x 32
-__global__ __launch_bounds__(WAVE, 3) void k_objects_s(const ObjArgs *args, ObjLists L) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// small class, first pass: erases components below the first area
+// threshold, finishes the crops up to 32 x 32 with at most one seed, and
+// defers the others (and, with external seeds or seed maps wanted, every
+// component it keeps) to the full pass
+__global__ __launch_bounds__(WAVE, 6) void k_objects_s1(const ObjArgs *args, ObjLists L) {
+    __shared__ __align__(16) uint8_t pl[3 * CAP_S];
     __shared__ int red;
-    __shared__ int hist[HBINS + 1];
     const int nobj = *L.n_s;
     for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
         const int code = L.list_s[o];
@@ -1114,7 +1409,22 @@ __global__ __launch_bounds__(WAVE, 3) void k_objects_s(const ObjArgs *args, ObjL
             erase_object(a, g, q);
             continue;
         }
-        process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, with_stride(q, RS_ + 1)), &red, hist);
+        const bool done = !a.seeds && !a.fg_out && single_seed_object(a, g, with_stride(q, RS_ + 1), pl, &red);
+        if (!done && threadIdx.x == 0) L.list_sd[atomicAdd(L.n_sd, 1)] = code;
+    }
+}
+
+// small class, full pass: the deferred components, crops up to 32 x 32
+__global__ __launch_bounds__(WAVE, 2) void k_objects_s(const ObjArgs *args, ObjLists L) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int red;
+    __shared__ int hist[HBINS + 1];
+    const int nobj = *L.n_sd;
+    for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
+        const int code = L.list_sd[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
+        process_object<RS_, int32_t>(a, g, lds_crop<CAP_S>(smem, with_stride(crop_geom(a, g), RS_ + 1)), &red, hist);
     }
 }
 
@@ -1272,6 +1582,8 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
     hipLaunchKernelGGL(k_objects_m, dim3(n_cu * 4), dim3(2 * WAVE), lds_m, s, args_dev, L);
     RT_HIP(hipGetLastError());
     if ((e = mark(1, 1, s)) || (e = mark(0, 0, t))) return e;
+    hipLaunchKernelGGL(k_objects_s1, dim3(n_cu * 32), dim3(WAVE), 0, t, args_dev, L);
+    RT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_objects_s, dim3(n_cu * 24), dim3(WAVE), lds_s, t, args_dev, L);
     RT_HIP(hipGetLastError());
     if ((e = mark(0, 1, t))) return e;

@@ -312,6 +312,9 @@ struct ObjLists {                  // shared by the batch; entries are image << 
     int path = 0;                  // 0: small / medium register classes, then large LDS;
                                    // 1: small register class, then large LDS;
                                    // 2: large LDS class for every crop that fits
+    int32_t *list_sd = nullptr, *n_sd = nullptr;   // small components with several seeds (or any, with
+                                   // external seeds or seed maps wanted), deferred by the first small-class
+                                   // pass to the full one; n_sd zeroed by the caller
 };
 constexpr int64_t MID_MAX_PX = 257 * 256;   // crops up to 256 x 256
 // Optional side stream for the small class, joined back into the caller's
