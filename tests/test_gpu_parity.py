@@ -295,6 +295,34 @@ def test_watershed_every_object_class(rt, oracle):
     assert_equal(to_np(mask), emask, "watershed object classes mask")
 
 
+def test_watershed_seed_counts(rt, oracle):
+    """Grids of overlapping discs, one seed per disc, in crops of the small
+    (<= 32^2) and the medium (<= 64^2) class: from 4 seeds to 25, so that
+    both the register path (at most 8 seeds) and the plane path it defers
+    to (more) run in both classes."""
+    d = dev()
+    H, W = 230, 260
+    yy, xx = np.mgrid[0:H, 0:W]
+    fg = np.zeros((H, W), bool)
+    # (origin, rows, columns, radius, step): r 3 / step 6 grids stay in small crops, the others in medium ones
+    grids = [((10, 10), 2, 2, 3, 6), ((10, 50), 2, 3, 3, 6), ((10, 100), 2, 4, 3, 6), ((10, 150), 3, 3, 3, 6),
+             ((10, 200), 3, 4, 3, 6), ((80, 10), 2, 3, 6, 11), ((80, 70), 2, 4, 6, 11), ((80, 140), 3, 3, 5, 10),
+             ((160, 10), 4, 4, 5, 10), ((160, 80), 5, 5, 5, 10)]
+    for (y0, x0), ny, nx, r, step in grids:
+        for i in range(ny):
+            for j in range(nx):
+                cy, cx = y0 + r + i * step, x0 + r + j * step
+                fg |= (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+    fg = fg.astype(np.uint8)
+    say("watershed seed counts")
+    lab, mask = rt.rt_watershed(to_dev(fg, d))
+    elab, emask = oracle.watershed(fg)
+    assert_equal(to_np(lab), elab, "watershed seed counts")
+    assert_equal(to_np(mask), emask, "watershed seed counts mask")
+    # one piece per disc: 4 + 6 + 8 + 9 + 12 + 6 + 8 + 9 + 16 + 25
+    assert len(np.unique(elab[elab > 0])) == 103
+
+
 def test_watershed_all_foreground(rt, oracle):
     d = dev()
     fg = np.ones((40, 50), np.uint8)
