@@ -307,22 +307,26 @@ __device__ __forceinline__ void reg_recon(const Crop<L> &m, int32_t *V, int32_t 
             mr[j] = M[cl * TS + j];
         }
         wave_sync();
+        // fixpoint: four consecutive scans (two vertical, two horizontal) that
+        // change nothing; V holds the values whenever the loop leaves
+        bool hprev = true;   // the previous horizontal scans changed something
         for (;;) {
-            bool ch = reg_scan<R>(v, mc, first, last);
+            const bool cv = __any(reg_scan<R>(v, mc, first, last));
 #pragma unroll
             for (int j = 0; j < R; ++j) V[j * TS + cl] = v[j];
             wave_sync();
+            if (!cv && !hprev) break;
 #pragma unroll
             for (int i = 0; i < R; ++i) v[i] = V[cl * TS + i];
             wave_sync();
-            ch |= reg_scan<R>(v, mr, first, last);
+            hprev = __any(reg_scan<R>(v, mr, first, last));
 #pragma unroll
             for (int i = 0; i < R; ++i) V[cl * TS + i] = v[i];
             wave_sync();
+            if (!cv && !hprev) break;
 #pragma unroll
             for (int j = 0; j < R; ++j) v[j] = V[j * TS + cl];
             wave_sync();
-            if (!__any(ch)) break;
         }
     }
     __syncthreads();
@@ -879,10 +883,12 @@ __device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16
                 MT taken = 0;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
-                    const MT nk = k < K ? dilate8<R>(F[k], first, last) & lv & ~taken : (MT)0;
-                    taken |= nk;
-                    F[k] = nk;
-                    S[k] |= nk;
+                    if (k < K) {   // K is uniform: a scalar branch
+                        const MT nk = dilate8<R>(F[k], first, last) & lv & ~taken;
+                        taken |= nk;
+                        F[k] = nk;
+                        S[k] |= nk;
+                    }
                 }
                 lv &= ~taken;
                 if (!__any(taken != 0)) break;
@@ -895,9 +901,12 @@ __device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16
         MT keep[KMAX];
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            keep[k] = S[k] & ~dilate8<R>(P, first, last);
-            P |= S[k];
-            keep_all |= keep[k];
+            keep[k] = 0;
+            if (k < K) {
+                keep[k] = S[k] & ~dilate8<R>(P, first, last);
+                P |= S[k];
+                keep_all |= keep[k];
+            }
         }
         // pixels cut away
         const int64_t rowbase = (int64_t)m.cy0 * a.pitch + m.cx0 + c;
@@ -910,6 +919,7 @@ __device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16
         // pieces of each label's kept pixels, and of the unreached ones
 #pragma unroll
         for (int k = 0; k <= KMAX; ++k) {
+            if (k < KMAX && k >= K) continue;
             MT rest = k < KMAX ? keep[k] : unreached;
             while (__any(rest != 0)) {
                 const int key = first_key<R>(rest, c);
@@ -1038,18 +1048,9 @@ __device__ __forceinline__ void process_object(const ObjArgs &a, int g, Crop<L> 
         }
     }
     crop_sync<L>();
-    // ---- one regional maximum of Dq means one seed (register classes, when
-    // no seed map is wanted): each regional maximum of the h-maxima transform
-    // g = recon(Dq - h under Dq) contains a regional maximum of Dq (a plateau
-    // of g at value v holds a point with Dq - h = v, and the component of
-    // {Dq >= v + h} through it stays inside the plateau, so its top is a
-    // regional maximum of Dq), so g has at most as many.
-    int tot = 2;
+    int tot = 0;
     bool one_seed = false;   // the register path found one seed
-    if constexpr (R == RS_ || R == RM_) {
-        if (!a.seeds && !a.fg_out) tot = count_maxima<R, L>(reg_planes(m), red);
-    }
-    if (tot > 1) {
+    {
         // ---- seeds
         if (a.seeds) {
             for (int i0 = 0; i0 < m.n; i0 += LOADS_IN_FLIGHT * (int)blockDim.x) {
@@ -1275,10 +1276,14 @@ __device__ void erase_object(const ObjArgs &a, int g, const CropGeom &q) {
 // many waves fit a CU.  Loads the component, and unless its crop holds no
 // background pixel (then Dq is constant on it: one maximum), runs the
 // distance transform and counts the regional maxima of Dq.  At most one
-// means one seed (see process_object): the component keeps its label g when
-// its area passes the final filter and is erased otherwise, and the call
-// returns true.  Otherwise it returns false and writes nothing: the caller
-// defers the component to the full path.
+// means one seed: each regional maximum of the h-maxima transform
+// g = recon(Dq - h under Dq) contains a regional maximum of Dq (a plateau of g
+// at value v holds a point with Dq - h = v, and the component of
+// {Dq >= v + h} through it stays inside the plateau, so its top is a regional
+// maximum of Dq), so g has at most as many.  Then the component keeps its
+// label g when its area passes the final filter and is erased otherwise, and
+// the call returns true.  Otherwise it returns false and writes nothing: the
+// caller defers the component to the full path.
 __device__ __forceinline__ bool single_seed_object(const ObjArgs &a, int g, const CropGeom &q, uint8_t *pl, int *red) {
     const int lane = threadIdx.x;
     const RegPlanes<uint8_t, uint8_t> p{pl, pl + CAP_S, pl + 2 * CAP_S, q.st, q.cw, q.ch};
