@@ -749,14 +749,18 @@ __device__ __forceinline__ void edt_rows_pk(const RegPlanes<GT, DT> &m, bool has
     for (int p = 0; p < np; ++p) {
         const int ca = h + 2 * NH * p, cb = ca + NH;
         const short2_t cp = {(short)ca, (short)cb};
-        short2_t acc = {SHRT_MAX, SHRT_MAX};
+        short2_t part[4];   // four independent minimum chains, combined at the end
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[q] = short2_t{SHRT_MAX, SHRT_MAX};
 #pragma unroll
         for (int cc = 0; cc < R; ++cc) {
             const short2_t k2 = {(short)(-2 * cc), (short)(-2 * cc)};
             const short ev = (cc & 1) ? e[cc / 2].y : e[cc / 2].x;
             const short2_t e2 = {ev, ev};
-            acc = __builtin_elementwise_min(acc, cp * k2 + e2);
+            part[cc & 3] = __builtin_elementwise_min(part[cc & 3], cp * k2 + e2);
         }
+        const short2_t acc = __builtin_elementwise_min(__builtin_elementwise_min(part[0], part[1]),
+                                                       __builtin_elementwise_min(part[2], part[3]));
         const int cs[2] = {ca, cb}, bs[2] = {(int)acc.x + ca * ca, (int)acc.y + cb * cb};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -846,14 +850,20 @@ __device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16
     recon_any<R, L>(m, m.A, m.dq, tw, red);   // A = lambda
     int kept = 0;
     if (lead) {
-        MT inm = 0, lab = 0;
-        int lam[R];
+        // lambda of the component's pixels as eight bit planes (lambda lies
+        // between the smallest and the largest Dq of the component, and Dq of a
+        // crop of at most 64 x 64 that holds a background pixel is below
+        // 2 * 64 * sqrt(2) < 256)
+        MT inm = 0, lab = 0, bp[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) bp[b] = 0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            lam[j] = NEGV;
             if (j < m.ch && col && (m.fl[j * m.st + c] & F_IN)) {
                 inm |= (MT)1 << j;
-                lam[j] = m.A[j * m.st + c];
+                const unsigned v = (unsigned)m.A[j * m.st + c];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) bp[b] |= (MT)((v >> b) & 1u) << j;
             }
         }
 #pragma unroll
@@ -862,19 +872,16 @@ __device__ int reg_watershed(const ObjArgs &a, const Crop<L> &m, int *red, int16
             lab |= S[k];
         }
         MT U = inm & ~lab, unreached = 0;
-        // flood, level by level
-        for (;;) {
-            int lv_val = NEGV;
+        // flood, level by level; the pixels of U at the highest lambda come
+        // from the bit planes, top bit first (keep the candidates that have the
+        // bit whenever some do)
+        while (__any(U != 0)) {
+            MT lv = U;
 #pragma unroll
-            for (int j = 0; j < R; ++j)
-                if ((U >> j) & 1) lv_val = max(lv_val, lam[j]);
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1) lv_val = max(lv_val, __shfl_xor(lv_val, d, WAVE));
-            if (lv_val == NEGV) break;
-            MT lv = 0;
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (((U >> j) & 1) && lam[j] == lv_val) lv |= (MT)1 << j;
+            for (int b = 7; b >= 0; --b) {
+                const MT t = lv & bp[b];
+                if (__any(t != 0)) lv = t;
+            }
             U &= ~lv;
             MT F[KMAX];
 #pragma unroll
