@@ -282,7 +282,7 @@ struct TileIn {
 struct Plan {
     int n = 0, nlev = 0;
     size_t o_dec = 0, o_cl = 0, o_rec = 0, o_cf = 0, o_cc = 0, o_ob = 0, o_aux = 0;
-    size_t o_obj = 0, o_s = 0, o_sd = 0, o_m = 0, o_l = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
+    size_t o_obj = 0, o_s = 0, o_sd = 0, o_e = 0, o_m = 0, o_l = 0, o_big = 0, o_huge = 0, o_ctr = 0, o_slices = 0, slice = 0, o_mid = 0, mid_slice = 0;
     int slices = 4, mid_slices = 8;
     int64_t dec_total = 0;
     int ccl_total = 0, rec_total = 0;
@@ -369,6 +369,8 @@ int enqueue_back(rt_ctx *c, const Plan &P, hipStream_t s, bool prof, bool captur
                 at<void>(c, P.o_mid), P.mid_slice, P.mid_slices, at<void>(c, P.o_slices), P.slice, P.slices};
     OL.list_sd = at<int32_t>(c, P.o_sd);
     OL.n_sd = ctr + 11;
+    OL.list_e = at<int32_t>(c, P.o_e);
+    OL.n_e = ctr + 12;
     OL.path = c->knobs.objects_path;
     // side streams also under capture: a stream that waits on an event
     // recorded in the capturing stream joins the capture, so the graph keeps
@@ -462,6 +464,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     P.o_l = L.add(sizeof(int32_t) * obj_cap);
     P.o_s = L.add(sizeof(int32_t) * obj_cap);
     P.o_sd = L.add(sizeof(int32_t) * obj_cap);
+    P.o_e = L.add(sizeof(int32_t) * obj_cap);
     P.o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     P.slice = al(big_object_bytes(big_w, big_h));
     P.o_slices = L.add(P.slice * P.slices);
@@ -1100,7 +1103,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     const size_t mo = max_obj_of(w, h);
     Layout L;
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 7);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 8);
     const size_t o_ctr = L.add(16 * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -1160,6 +1163,8 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
                 obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     OL.list_sd = obj + 6 * mo;
     OL.n_sd = ctr + 11;
+    OL.list_e = obj + 7 * mo;
+    OL.n_e = ctr + 12;
     ObjStreams par{};
     if ((e = side_streams(c, par))) return e;
     return launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, nullptr, &par);
@@ -1393,7 +1398,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     const size_t o_f = L.add(N);
     const size_t o_reg = L.add(sizeof(int32_t) * n1 * 6);
     const size_t mo = max_obj_of(w, h);
-    const size_t o_obj = L.add(sizeof(int32_t) * mo * 7);
+    const size_t o_obj = L.add(sizeof(int32_t) * mo * 8);
     const size_t o_ctr = L.add(kSharedCounters * sizeof(int32_t));
     const size_t slice = al(big_object_bytes(w, h));
     const size_t o_slices = L.add(slice * 4);
@@ -1486,6 +1491,8 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
                 obj + 3 * mo, ctr + 8, at<void>(c, o_mid), mid_slice, mid_n, at<void>(c, o_slices), slice, 4};
     OL.list_sd = obj + 6 * mo;
     OL.n_sd = ctr + 11;
+    OL.list_e = obj + 7 * mo;
+    OL.n_e = ctr + 12;
     ObjStreams par{};
     if ((e = side_streams(c, par))) return e;
     if ((e = launch_objects(at<ObjArgs>(c, o_ob), OL, c->n_cu, s, nullptr, &par))) return e;

@@ -75,4 +75,11 @@ __host__ __device__ inline int64_t crop_load_offset_dense(const CropGeom &q, int
     return (int64_t)(q.cy0 + r) * pitch + q.cx0 + (k - r * q.cw);
 }
 
+// Loads of the erase pass (one wave per component, lane = crop column c < cw,
+// rows in batches of eight): row r clamped to the crop's last row.
+__host__ __device__ inline int64_t crop_erase_offset(const CropGeom &q, int c, int r, int64_t pitch) {
+    r = r < q.ch - 1 ? r : q.ch - 1;
+    return (int64_t)(q.cy0 + r) * pitch + q.cx0 + c;
+}
+
 }  // namespace rtseg

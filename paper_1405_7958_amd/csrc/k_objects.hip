@@ -1266,15 +1266,22 @@ __device__ __forceinline__ CropGeom crop_geom(const ObjArgs &a, int g) {
 // reconstruction (the plane capacity is R x (R + 1)).
 __device__ __forceinline__ CropGeom with_stride(CropGeom q, int st) { return crop_with_stride(q, st); }
 
+// One wave per component: lane = crop column (strips of 64 columns), eight
+// rows' loads issued before any is tested.
 __device__ void erase_object(const ObjArgs &a, int g, const CropGeom &q) {
-    for (int i = threadIdx.x; i < q.cw * q.ch; i += blockDim.x) {
-        const int c = i % q.cw, r = i / q.cw;
-        const int64_t o = (int64_t)(q.cy0 + r) * a.pitch + q.cx0 + c;
-        if (a.labels[o] == g) {
-            a.labels[o] = 0;
-            a.mask[o] = 0;
+    for (int c = threadIdx.x; c < q.cw; c += WAVE)
+        for (int r0 = 0; r0 < q.ch; r0 += 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = a.labels[crop_erase_offset(q, c, r0 + k, a.pitch)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (r0 + k < q.ch && v[k] == g) {
+                    const int64_t o = crop_erase_offset(q, c, r0 + k, a.pitch);
+                    a.labels[o] = 0;
+                    a.mask[o] = 0;
+                }
         }
-    }
 }
 
 // ---- first small-class pass: components with at most one seed ---------------
@@ -1388,7 +1395,9 @@ __global__ void k_objects_classify(const ObjArgs *args, ObjLists L) {
             const ObjArgs a = args[code >> 25];
             const int g = code & CODE_MASK;
             const CropGeom q = crop_geom(a, g);
-            if (a.st_area[g] < a.min_area_pre || (L.path != 2 && q.cw <= RS_ && q.ch <= RS_))
+            if (a.st_area[g] < a.min_area_pre)
+                cls = 4;
+            else if (L.path != 2 && q.cw <= RS_ && q.ch <= RS_)
                 cls = 0;
             else if (L.path == 0 && q.cw <= RM_ && q.ch <= RM_)
                 cls = 1;
@@ -1401,13 +1410,25 @@ __global__ void k_objects_classify(const ObjArgs *args, ObjLists L) {
         wave_append(cls == 1, code, L.list_m, L.n_m);
         wave_append(cls == 2, code, L.list_l, L.n_l);
         wave_append(cls == 3, code, L.big, L.n_big);
+        wave_append(cls == 4, code, L.list_e, L.n_e);
     }
 }
 
-// small class, first pass: erases components below the first area
-// threshold, finishes the crops up to 32 x 32 with at most one seed, and
-// defers the others (and, with external seeds or seed maps wanted, every
-// component it keeps) to the full pass
+// components below the first area threshold: their pixels are cleared in
+// the labels and the mask (one wave each)
+__global__ __launch_bounds__(WAVE) void k_objects_erase(const ObjArgs *args, ObjLists L) {
+    const int nobj = *L.n_e;
+    for (int o = blockIdx.x; o < nobj; o += gridDim.x) {
+        const int code = L.list_e[o];
+        const ObjArgs a = args[code >> 25];
+        const int g = code & CODE_MASK;
+        erase_object(a, g, crop_geom(a, g));
+    }
+}
+
+// small class, first pass: finishes the crops up to 32 x 32 with at most one
+// seed, and defers the others (and, with external seeds or seed maps wanted,
+// every component) to the full pass
 __global__ __launch_bounds__(WAVE, 6) void k_objects_s1(const ObjArgs *args, ObjLists L) {
     __shared__ __align__(16) uint8_t pl[3 * CAP_S];
     __shared__ int red;
@@ -1417,10 +1438,6 @@ __global__ __launch_bounds__(WAVE, 6) void k_objects_s1(const ObjArgs *args, Obj
         const ObjArgs a = args[code >> 25];
         const int g = code & CODE_MASK;
         const CropGeom q = crop_geom(a, g);
-        if (a.st_area[g] < a.min_area_pre) {
-            erase_object(a, g, q);
-            continue;
-        }
         const bool done = !a.seeds && !a.fg_out && single_seed_object(a, g, with_stride(q, RS_ + 1), pl, &red);
         if (!done && threadIdx.x == 0) L.list_sd[atomicAdd(L.n_sd, 1)] = code;
     }
@@ -1587,6 +1604,8 @@ int launch_objects(const ObjArgs *args_dev, const ObjLists &L, int n_cu, hipStre
         return RT_OK;
     };
     int e;
+    hipLaunchKernelGGL(k_objects_erase, dim3(n_cu * 8), dim3(WAVE), 0, u, args_dev, L);
+    RT_HIP(hipGetLastError());
     if ((e = mark(2, 0, u))) return e;
     hipLaunchKernelGGL(k_objects_l, dim3(std::max(1, n_cu / 4)), dim3(4 * WAVE), lds_l, u, args_dev, L);
     RT_HIP(hipGetLastError());

@@ -298,7 +298,7 @@ struct ObjArgs {                   // one record per image
 };
 struct ObjLists {                  // shared by the batch; entries are image << 25 | root
     const int32_t *obj, *n_obj;
-    int32_t *list_s, *n_s;         // small class (and components to erase)
+    int32_t *list_s, *n_s;         // small class
     int32_t *list_m, *n_m;         // deferred to the medium LDS class
     int32_t *list_l, *n_l;         // deferred to the large LDS class
     int32_t *big, *n_big;          // deferred to the global-memory classes
@@ -312,6 +312,7 @@ struct ObjLists {                  // shared by the batch; entries are image << 
     int path = 0;                  // 0: small / medium register classes, then large LDS;
                                    // 1: small register class, then large LDS;
                                    // 2: large LDS class for every crop that fits
+    int32_t *list_e = nullptr, *n_e = nullptr;     // components below the first area threshold, to erase
     int32_t *list_sd = nullptr, *n_sd = nullptr;   // small components with several seeds (or any, with
                                    // external seeds or seed maps wanted), deferred by the first small-class
                                    // pass to the full one; n_sd zeroed by the caller

@@ -4,8 +4,8 @@
 // box: the three plane strides in use (R + 1 for the register classes when
 // the crop fits them, cw | 1 otherwise), every thread count in use, every
 // batch and every load of a batch, through the kernels' own address function
-// (crop_addr.h), and the dense loads of the register classes (crops of at
-// most 32 x 32 and 64 x 64, 64 and 128 threads).  Each offset must address a
+// (crop_addr.h), the loads of the erase pass, and the dense loads of the
+// register classes (crops of at most 32 x 32 and 64 x 64, 64 and 128 threads).  Each offset must address a
 // pixel of the crop, and so lie in [0, (h - 1) * pitch + w).  The dense row
 // of every pixel of every crop of at most 64 x 64 is checked against integer
 // division first.  Prints "ok <loads>" or the first failure.
@@ -63,6 +63,19 @@ int main() {
                         }
             }
         }
+        // erase pass: lane = column, rows in batches of eight, clamped
+        for (int c = 0; c < base.cw; ++c)
+            for (int r0 = 0; r0 < base.ch; r0 += 8)
+                for (int k = 0; k < 8; ++k) {
+                    const long long o = crop_erase_offset(base, c, r0 + k, pitch);
+                    const long long y = o / pitch, x = o % pitch;
+                    ++loads;
+                    if (o < 0 || o >= end || x < base.cx0 || x >= base.cx0 + base.cw || y < base.cy0 ||
+                        y >= base.cy0 + base.ch) {
+                        printf("FAIL erase box %d (%d %d %d %d) c %d r %d: offset %lld\n", b, x0, y0, x1, y1, c, r0 + k, o);
+                        return 1;
+                    }
+                }
         // dense loads of the register classes (64 threads for 32 x 32, 128 for 64 x 64)
         for (int rc = 0; rc < 2; ++rc) {
             const int R = rc ? 64 : 32, nt = rc ? 128 : 64;
