@@ -196,12 +196,21 @@ __device__ __forceinline__ void gfind4_ro(const int32_t *ids, int x[4]) {
     }
 }
 
+// The walks read the forest with plain loads, through the XCD's own L2, which
+// may hold an older copy of a line that another XCD's atomics have changed
+// since.  That is safe: parent links only ever move to smaller ancestors in
+// the same set, so an older link is still a valid path to an ancestor (the
+// walk ends, at a node that is or was a root), equal stale roots prove the two
+// nodes joined, and linking is a device-scope atomic minimum that returns the
+// true entry -- when the node is no longer a root the loop goes on from that
+// entry, which is smaller each time.  Agent-scope loads would fetch a line
+// from memory for every 4-byte node.
 __device__ __forceinline__ void gunite(int32_t *ids, int a, int b) {
     for (;;) {
-        int pa = ld_agent(ids + a), pb = ld_agent(ids + b);
+        int pa = ids[a], pb = ids[b];
         while (pa != a || pb != b) {
-            const int ga = pa != a ? ld_agent(ids + pa) : a;
-            const int gb = pb != b ? ld_agent(ids + pb) : b;
+            const int ga = pa != a ? ids[pa] : a;
+            const int gb = pb != b ? ids[pb] : b;
             if (pa != a) {
                 if (ga != pa) atomicMin(ids + a, ga);
                 a = pa;
