@@ -68,10 +68,6 @@ __device__ __forceinline__ WaveMem wave_mem(int wave) {
 // forest slot of the run start at tile index li = y * 64 + s
 __device__ __forceinline__ int slot(int li) { return (li >> 6) * (CT / 2) + ((li & (CT - 1)) >> 1); }
 
-__device__ __forceinline__ int ld_agent(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Forest entries: the tile index of the parent run start (12 bits) and the
 // two tags.  The local phase keeps them in 16 bits (4 KB per tile, which
 // doubles the waves an LDS budget holds); the BWLabel flatten keeps 32 bits,
@@ -139,17 +135,6 @@ __device__ __forceinline__ void lunite(PT *P, int a, int b) {
         if (old == a) return;
         a = old;
     }
-}
-
-__device__ __forceinline__ int gfind(int32_t *ids, int x) {
-    int p = ld_agent(ids + x);
-    while (p != x) {
-        const int gp = ld_agent(ids + p);
-        if (gp != p) atomicMin(ids + x, gp);
-        x = p;
-        p = gp;
-    }
-    return x;
 }
 
 // Read-only find for the flatten pass: the forest no longer changes once the

@@ -99,6 +99,8 @@ struct MaskRegs<int32_t> {
 
 // one scan step: value of this pixel given the three predecessors' maximum m
 __device__ __forceinline__ int step_val(int rv, int m, int mv) { return max(rv, min(m, mv)); }
+// the median of three (one v_med3 instruction): step_val(a, b, c) when a <= c
+__device__ __forceinline__ int med3(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
 
 __device__ __forceinline__ int shr0(int v) {  // lane i <- lane i-1 (lane 0: don't care)
     return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
@@ -113,10 +115,17 @@ __device__ void recon_tile(const ReconImg &a, int gtile, int max_sweeps, int (*T
 // Plain uint8 images (no domain), the reconstruction of ReconToNuclei.
 //
 // Every value is >= 0 here, so a pixel outside the image carries the value 0
-// and every non-member (outside the image, or on the ring) carries the mask
-// 0: for it max(r, min(m, 0)) = r, so it never changes, and the zeros it
-// feeds to its neighbours' scan steps never raise a member, whose value is
-// >= 0.  Scan steps then need no membership test.  Both images are staged
+// and the mask 0: for it max(r, min(m, 0)) = r, so it never changes, and the
+// zeros it feeds to its neighbours' scan steps never raise a member, whose
+// value is >= 0.  Every other position of the block, the ring included,
+// carries its mask: values start at min(marker, mask) and never pass the
+// mask, so value <= mask holds everywhere and a scan step
+// max(r, min(m, mask)) is the median of the three (one instruction).  A ring
+// pixel may then rise in the registers; it rises only to a value its own
+// reconstruction reaches too (the neighbours it takes from hold lower bounds
+// of theirs), so the interior stays a lower bound of the result, the ring's
+// registers are never written back, and at the fixpoint of the whole image
+// no ring pixel rises.  Scan steps need no membership test.  Both images are staged
 // through LDS in row order: each lane loads 17 aligned dwords per image (the
 // 64-byte rows of a block start at any byte), each clamped to a dword that
 // holds at least one byte of its row; an aligned dword never crosses a page,
@@ -197,6 +206,12 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
     const bool row_m = lane >= 1 && lane <= limh;
     const bool edge = x0 == 0 || y0 == 0 || x0 + RIN >= a.w || y0 + RIN >= a.h;
     const uint32_t colmask = col_m ? ~0u : 0u, rowmask = row_m ? ~0u : 0u;
+    // the masks of every position inside the image, the ring included (rows
+    // and columns outside the image: 0)
+    const int gyl = y0 - 1 + lane;
+    const uint32_t colimg = col_ok ? ~0u : 0u, rowimg = (gyl >= 0 && gyl < a.h) ? ~0u : 0u;
+    const int jlo = y0 == 0 ? 1 : 0, jhi = min(63, a.h - y0);
+    const int clo = x0 == 0 ? 1 : 0, chi = min(63, a.w - x0);
     int r[64];
     uint32_t mc[16], mr[16];
 #pragma unroll
@@ -210,7 +225,7 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
             r[j] = sR[j * SP + oR + lane];
             p |= (uint32_t)sM[j * SP + oM + lane] << (8 * b);
         }
-        mc[k] = p & byte_span(k, 1, limh) & colmask;
+        mc[k] = p & byte_span(k, jlo, jhi) & colimg;
         // at most eight LDS reads in flight: the counter holds no more anyway
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -232,7 +247,7 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
         for (int d = 0; d < 17; ++d) dw[d] = srow[d];
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            mr[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], o) & byte_span(k, 1, limw) & rowmask;
+            mr[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], o) & byte_span(k, clo, chi) & rowimg;
         oL = (int)((uint32_t)sR[lane * SP + orr + 1] & rowmask);
         oR = (int)((uint32_t)sR[lane * SP + orr + RIN] & (limw >= RIN ? rowmask : 0u));
     }
@@ -252,13 +267,13 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
 #pragma unroll
             for (int j = 1; j < 64; ++j) {
                 const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
-                pc = max(r[j], min(m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u)));
+                pc = med3(r[j], m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u));
                 r[j] = pc;
             }
 #pragma unroll
             for (int j = 62; j >= 0; --j) {
                 const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
-                pc = max(r[j], min(m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u)));
+                pc = med3(r[j], m, (int)((mc[j >> 2] >> (8 * (j & 3))) & 255u));
                 r[j] = pc;
             }
         }
@@ -275,14 +290,14 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
 #pragma unroll
             for (int i = 1; i < 64; ++i) {
                 const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
-                pc = max(r[i], min(m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u)));
+                pc = med3(r[i], m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u));
                 r[i] = pc;
             }
             acc = pc;
 #pragma unroll
             for (int i = 62; i >= 0; --i) {
                 const int m = CONN == 8 ? max(pc, max(shr0(pc), shl0(pc))) : pc;
-                pc = max(r[i], min(m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u)));
+                pc = med3(r[i], m, (int)((mr[i >> 2] >> (8 * (i & 3))) & 255u));
                 r[i] = pc;
                 acc += pc;
             }
@@ -339,7 +354,7 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
 }
 
 template <typename T, int CONN, bool PLAIN>
-__global__ __launch_bounds__(64, PLAIN ? 3 : 1) void k_recon_round(RoundArgs ra) {
+__global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_round(RoundArgs ra) {
     __shared__ __align__(16) uint8_t lds[PLAIN ? PLAIN_LDS : 64 * 65 * 4];
     const int lane = threadIdx.x;
     int32_t *cnt_in = ra.cnt + (ra.k % 3);
