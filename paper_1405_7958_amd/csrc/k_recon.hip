@@ -1012,8 +1012,10 @@ int recon_launch(rt_ctx_impl *c, const ReconRun &run, const ReconImg *imgs_dev, 
         ra.list_out = run.lists + ((k + 1) & 1) * (size_t)run.total;
         ra.epoch = (uint32_t)k + 1;
         if (dtype == RECON_U8_PLAIN) {
-            // three waves per SIMD fit the plain kernel's registers
-            const int g = std::min(run.total, c->n_cu * 12);
+            // two waves per SIMD fit the plain kernel's registers: a grid of
+            // exactly the resident workgroups (larger grids measured slower:
+            // workgroups that start late hold back the round's end)
+            const int g = std::min(run.total, c->n_cu * 8);
             if (conn == 8) launch_round<uint8_t, 8, true>(ra, g, s);
             else launch_round<uint8_t, 4, true>(ra, g, s);
         } else if (dtype == RT_U8) {
