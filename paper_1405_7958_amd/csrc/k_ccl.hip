@@ -65,8 +65,9 @@ __device__ __forceinline__ WaveMem wave_mem(int wave) {
     return {base, P, P + NSLOT, P + NSLOT + NLIST};
 }
 
-// forest slot of the run start at tile index li = y * 64 + s
-__device__ __forceinline__ int slot(int li) { return (li >> 6) * (CT / 2) + ((li & (CT - 1)) >> 1); }
+// forest slot of the run start at tile index li = y * 64 + s: y * 32 + s / 2
+// (one slot per pixel pair of a row), which is li / 2
+__device__ __forceinline__ int slot(int li) { return li >> 1; }
 
 // Forest entries: the tile index of the parent run start (12 bits) and the
 // two tags.  The local phase keeps them in 16 bits (4 KB per tile, which
@@ -229,8 +230,6 @@ __device__ __forceinline__ int run_start_of(uint64_t m, int b) {   // m has bit 
     uint64_t z = ~m & ((1ull << b) - 1);
     return z ? 64 - __builtin_clzll(z) : 0;
 }
-__device__ __forceinline__ uint64_t bits_upto(int e) { return e >= 63 ? ~0ull : (2ull << e) - 1; }
-__device__ __forceinline__ uint64_t run_bits(int s, int len) { return bits_upto(s + len - 1) & ~((1ull << s) - 1); }
 
 // The runs of m that hold a bit of s (s within m): adding s to m clears each
 // run from its lowest seed to its end (the carry stops at the first zero);
@@ -367,43 +366,109 @@ __device__ void build_rows(const CclArgs &A, const Tile &t, int level, uint64_t 
     __syncthreads();
 }
 
+// The pixels of mask m's run that starts at bit s (adding that bit to m
+// carries through the run and clears it), widened by one pixel on each side
+// for 8-connectivity: the window in which a run of the row above touches it.
+__device__ __forceinline__ uint64_t touch_window(uint64_t m, uint64_t bit, int conn) {
+    const uint64_t run = m & ~(m + bit);
+    return conn == 8 ? run | (run << 1) | (run >> 1) : run;
+}
+
 // Tile forest over runs.  Lane = row.  With FLAT, after the call
 // P[slot(y*64+s)] = local root (tile index of a run start) for every run
 // start s of row y; without it the forest is final but not flattened (a root
 // is still its own entry, and lroot walks to it), which is all the local
 // phase needs: it looks up the roots of border runs only.
+//
+// Built in three passes, so that no lane walks long parent chains:
+//   1. every run takes as parent the first run of the row above that touches
+//      it (plain stores, no finds);
+//   2. pointer jumping re-points every run whose parent is not a root to its
+//      grandparent, until all point at roots (the trees are at most 64 rows
+//      deep, so at most six rounds; a run whose parent is a root stays done,
+//      since no link happens in this pass; four runs of a lane per step keep
+//      their loads in flight);
+//   3. the runs that touch further runs above unite with them by union-find
+//      (path halving, atomic links), on the now shallow forest.
+// Parents always have smaller indices and links join roots by minimum, so
+// the root of a component is its smallest run start, as with plain unions.
+// Every pass is lane-divergent over the runs of a row, so each run's step is
+// kept to a few 64-bit mask operations.
 template <typename PT, bool FLAT = true>
 __device__ void run_forest(const uint64_t *rows, PT *P, int conn) {
     const int y = lane_id();
+    const int yb = y * CT;
     const uint64_t m = rows[y];
+    const uint64_t pm = y > 0 ? rows[y - 1] : 0ull;
+    const uint64_t ps = run_starts(pm);
+    uint64_t more = 0;   // runs of row y that touch two or more runs above
+    uint64_t pend = 0;   // runs of row y whose parent may not be a root
     for (uint64_t st = run_starts(m); st; st &= st - 1) {
-        const int li = y * CT + __builtin_ctzll(st);
-        P[slot(li)] = (PT)li;
+        const uint64_t bit = st & (0ull - st);
+        const int s = __builtin_ctzll(st);
+        const uint64_t w = touch_window(m, bit, conn);
+        const uint64_t tm = pm & w;
+        int par = yb + s;
+        if (tm) {
+            // the first touching run above: its start is the first touching
+            // pixel, unless that run began left of the window; any other run
+            // start in the window is a further touching run
+            const int f = __builtin_ctzll(tm);
+            const uint64_t wps = ps & w;
+            int s2 = f;
+            bool two;
+            if ((ps >> f) & 1ull) {
+                two = (wps & (wps - 1)) != 0;
+            } else {
+                s2 = run_start_of(pm, f);
+                two = wps != 0;
+            }
+            par = yb - CT + s2;
+            pend |= bit;
+            if (two) more |= bit;
+        }
+        P[slot(yb + s)] = (PT)par;
     }
     __syncthreads();
-    if (y > 0) {
-        const uint64_t pm = rows[y - 1];
-        if (m && pm) {
-            for (uint64_t st = run_starts(m); st; st &= st - 1) {
-                int s = __builtin_ctzll(st);
-                int e = s + run_len(m, s) - 1;
-                int lo = conn == 8 ? max(s - 1, 0) : s;
-                int hi = conn == 8 ? min(e + 1, 63) : e;
-                uint64_t ov = pm & bits_upto(hi) & ~((1ull << lo) - 1);
-                while (ov) {
-                    int b = __builtin_ctzll(ov);
-                    int s2 = run_start_of(pm, b);
-                    int e2 = s2 + run_len(pm, s2) - 1;
-                    lunite(P, y * CT + s, (y - 1) * CT + s2);
-                    ov &= ~bits_upto(e2);
-                }
+    while (__any(pend != 0)) {
+        uint64_t next = 0;
+        for (uint64_t st = pend; st;) {
+            int li[4], p[4], g[4];
+            uint64_t bk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                bk[k] = st & (0ull - st);
+                li[k] = st ? yb + __builtin_ctzll(st) : -1;
+                st ^= bk[k];
             }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) p[k] = li[k] >= 0 ? p_load(P, slot(li[k])) : 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[k] = li[k] >= 0 ? p_load(P, slot(p[k])) : 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (li[k] >= 0 && g[k] != p[k]) {
+                    p_halve(P, slot(li[k]), g[k]);
+                    next |= bk[k];
+                }
         }
+        pend = next;
+        __syncthreads();
+    }
+    for (uint64_t st = more; st; st &= st - 1) {
+        const uint64_t bit = st & (0ull - st);
+        const int s = __builtin_ctzll(st);
+        const uint64_t w = touch_window(m, bit, conn);
+        // the run starts in the window after the first touching pixel: the
+        // touching runs other than the tree parent
+        const uint64_t tm = pm & w;
+        for (uint64_t o = ps & w & ~(tm & (0ull - tm)); o; o &= o - 1)
+            lunite(P, yb + s, yb - CT + __builtin_ctzll(o));
     }
     __syncthreads();
     if constexpr (FLAT) {
         for (uint64_t st = run_starts(m); st; st &= st - 1) {
-            const int li = y * CT + __builtin_ctzll(st);
+            const int li = yb + __builtin_ctzll(st);
             P[slot(li)] = (PT)lfind(P, li);
         }
         __syncthreads();
@@ -470,22 +535,34 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
     // the level sets hold many small components (short chains to walk), the
     // other sets few large ones, where one flattening pass beats long walks
     run_forest<uint16_t, PR != CclPred::Level>(rows, P, A.conn);
-    mark_touch(t, rows, P);
+    // Roots of this lane's four border pixels (-1: not a member): column 0
+    // and column tw - 1 of row `lane`, row 0 and row th - 1 of column `lane`.
+    // The forest no longer changes (tags only go to root entries, and lroot
+    // masks them), so every use below shares these.
     const int y = lane;
     const uint64_t m = rows[y];
-    const bool tile_on_frame = t.x0 == 0 || t.y0 == 0 || t.x0 + t.tw == A.w || t.y0 + t.th == A.h;
-    if (A.frame_virtual && tile_on_frame) {
-        // frame columns (lane = row)
-        if (y < t.th) {
-            if (t.x0 == 0 && (m & 1ull)) p_or(P, slot(root_of(rows, P, 0, y)), FRAME_BIT);
-            if (t.x0 + t.tw == A.w && ((m >> (t.tw - 1)) & 1ull))
-                p_or(P, slot(root_of(rows, P, t.tw - 1, y)), FRAME_BIT);
-        }
-        // frame rows (lane = column): every run, at its start
-        const int yb = t.th - 1;
-        if (t.y0 == 0 && ((run_starts(rows[0]) >> lane) & 1ull)) p_or(P, slot(lroot(P, lane)), FRAME_BIT);
-        if (t.y0 + t.th == A.h && ((run_starts(rows[yb]) >> lane) & 1ull))
-            p_or(P, slot(lroot(P, yb * CT + lane)), FRAME_BIT);
+    const int xr = t.tw - 1, yl = t.th - 1;
+    const uint64_t top = rows[0], bot = rows[yl];
+    const int r_l = (m & 1ull) ? lroot(P, y * CT) : -1;
+    const int r_r = ((m >> xr) & 1ull) ? lroot(P, y * CT + run_start_of(m, xr)) : -1;
+    const int r_t = ((top >> lane) & 1ull) ? lroot(P, run_start_of(top, lane)) : -1;
+    const int r_b = ((bot >> lane) & 1ull) ? lroot(P, yl * CT + run_start_of(bot, lane)) : -1;
+    const bool s_t = (run_starts(top) >> lane) & 1ull;   // a run of row 0 starts at column `lane`
+    const bool s_b = (run_starts(bot) >> lane) & 1ull;   // the same for row th - 1
+    // Tag the roots of components that reach the tile border (only those can
+    // join other tiles) and, with a virtual frame node, of those that reach
+    // the image frame (they reach the tile border too).  Rows are tagged once
+    // per run, at its start.
+    {
+        const bool fv = A.frame_virtual;
+        const int fl = fv && t.x0 == 0 ? FRAME_BIT : 0;
+        const int fr = fv && t.x0 + t.tw == A.w ? FRAME_BIT : 0;
+        const int ft = fv && t.y0 == 0 ? FRAME_BIT : 0;
+        const int fb = fv && t.y0 + t.th == A.h ? FRAME_BIT : 0;
+        if (r_l >= 0) p_or(P, slot(r_l), TOUCH_BIT | fl);
+        if (r_r >= 0) p_or(P, slot(r_r), TOUCH_BIT | fr);
+        if (s_t) p_or(P, slot(r_t), TOUCH_BIT | ft);
+        if (s_b) p_or(P, slot(r_b), TOUCH_BIT | fb);
         __syncthreads();
     }
     if (!live) return;
@@ -514,36 +591,16 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
             const int id = gid(A, t, r & (CT - 1), r >> 6);
             ids[id] = (p_load(P, slot(r)) & FRAME_BIT) ? 0 : id;
         };
-        if (y < t.th) {
-            if (m & 1ull) publish(root_of(rows, P, 0, y));
-            if ((m >> (t.tw - 1)) & 1ull) publish(root_of(rows, P, t.tw - 1, y));
-        }
-        const int yb = t.th - 1;
-        if ((run_starts(rows[0]) >> lane) & 1ull) publish(lroot(P, lane));
-        if (yb > 0 && ((run_starts(rows[yb]) >> lane) & 1ull)) publish(lroot(P, yb * CT + lane));
+        if (r_l >= 0) publish(r_l);
+        if (r_r >= 0) publish(r_r);
+        if (s_t) publish(r_t);
+        if (yl > 0 && s_b) publish(r_b);
     }
-    // edge pixels that are not roots: left / right columns (lane = row)
-    if (m & 1ull) {
-        const int r = root_of(rows, P, 0, y);
-        if (r != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r & 63, r >> 6);
-    }
-    if (t.tw > 1 && ((m >> (t.tw - 1)) & 1ull)) {
-        const int r = root_of(rows, P, t.tw - 1, y);
-        if (r != y * CT + t.tw - 1) ids[gid(A, t, t.tw - 1, y)] = gid(A, t, r & 63, r >> 6);
-    }
-    // top / bottom rows (lane = column)
-    {
-        const int x = lane;
-        if ((rows[0] >> x) & 1ull) {
-            const int r = root_of(rows, P, x, 0);
-            if (r != x) ids[gid(A, t, x, 0)] = gid(A, t, r & 63, r >> 6);
-        }
-        const int yb = t.th - 1;
-        if (yb > 0 && ((rows[yb] >> x) & 1ull)) {
-            const int r = root_of(rows, P, x, yb);
-            if (r != yb * CT + x) ids[gid(A, t, x, yb)] = gid(A, t, r & 63, r >> 6);
-        }
-    }
+    // border pixels that are not roots point at their root
+    if (r_l >= 0 && r_l != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r_l & 63, r_l >> 6);
+    if (xr > 0 && r_r >= 0 && r_r != y * CT + xr) ids[gid(A, t, xr, y)] = gid(A, t, r_r & 63, r_r >> 6);
+    if (r_t >= 0 && r_t != lane) ids[gid(A, t, lane, 0)] = gid(A, t, r_t & 63, r_t >> 6);
+    if (yl > 0 && r_b >= 0 && r_b != yl * CT + lane) ids[gid(A, t, lane, yl)] = gid(A, t, r_b & 63, r_b >> 6);
 }
 
 // One wave per (tile, level): unit u is tile u / nw at level u % nw.
