@@ -324,6 +324,10 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &q, int i) {
     return (w >> ((i & 3) * 8)) & 255u;
 }
 
+// The low 4 bits of x as the bytes of a word (bit k -> byte k, 0 or 1): the
+// multiplier places bit k at bit 8k, and no two partial products overlap.
+__device__ __forceinline__ uint32_t nibble_bytes(uint32_t x) { return (__umul24(x & 15u, 0x204081u)) & 0x01010101u; }
+
 // Loads the 16 bytes at p (nvalid of them inside the image; the rest read 0).
 __device__ __forceinline__ uint4 load16(const uint8_t *p, int nvalid, bool wide) {
     if (wide && nvalid == 16) return *(const uint4 *)p;
@@ -433,21 +437,23 @@ __device__ void run_forest(const uint64_t *rows, PT *P, int conn) {
     while (__any(pend != 0)) {
         uint64_t next = 0;
         for (uint64_t st = pend; st;) {
+            // up to four runs; an empty place repeats the first run, so that
+            // all loads are unconditional and in flight together
             int li[4], p[4], g[4];
             uint64_t bk[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 bk[k] = st & (0ull - st);
-                li[k] = st ? yb + __builtin_ctzll(st) : -1;
+                li[k] = st ? yb + __builtin_ctzll(st) : li[0];
                 st ^= bk[k];
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) p[k] = li[k] >= 0 ? p_load(P, slot(li[k])) : 0;
+            for (int k = 0; k < 4; ++k) p[k] = p_load(P, slot(li[k]));
 #pragma unroll
-            for (int k = 0; k < 4; ++k) g[k] = li[k] >= 0 ? p_load(P, slot(p[k])) : 0;
+            for (int k = 0; k < 4; ++k) g[k] = p_load(P, slot(p[k]));
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (li[k] >= 0 && g[k] != p[k]) {
+                if (bk[k] && g[k] != p[k]) {
                     p_halve(P, slot(li[k]), g[k]);
                     next |= bk[k];
                 }
@@ -795,11 +801,7 @@ __device__ __forceinline__ void ccl_flatten_fc_tile(const CclArgs &A, int b, int
 
     const bool wide = OU == CclOut::LevelBound ? aligned16(A.bound, A.pitch_r) : aligned16(A.fill, A.pitch_f);
     const int nw = OU == CclOut::LevelBound ? blockDim.x / CT : 1;
-    int lv[MAXLEV];
-    if constexpr (OU == CclOut::LevelBound) {
-#pragma unroll
-        for (int l = 0; l < MAXLEV; ++l) lv[l] = l < A.n_levels && l < nw ? A.levels[l] : 0;
-    }
+    const int nlev = OU == CclOut::LevelBound ? min(nw, A.n_levels) : 0;
     for (int i = (int)threadIdx.x; i < CT * 4; i += nw * CT) {   // 16-pixel chunks
         const int y = i >> 2, c = i & 3;
         const int nvalid = y < t.th ? max(0, min(16, t.tw - 16 * c)) : 0;
@@ -810,25 +812,42 @@ __device__ __forceinline__ void ccl_flatten_fc_tile(const CclArgs &A, int b, int
         if constexpr (OU == CclOut::FillHoles) {
             // F = input | not frame-connected: members of the background
             // components that reach the frame are the only zeros
-            const uint32_t fc = (uint32_t)(rows[y] >> (16 * c)) & 0xffffu;
+            const uint32_t fc = ~(uint32_t)(rows[y] >> (16 * c));
 #pragma unroll
-            for (int k = 0; k < 16; ++k) w[k >> 2] |= (((fc >> k) & 1u) ? 0u : 1u) << ((k & 3) * 8);
+            for (int q = 0; q < 4; ++q) w[q] = nibble_bytes(fc >> (4 * q));
             store16(A.fill + gy * A.pitch_f + gx, w, nvalid, wide);
         } else {
-            uint32_t fcl[MAXLEV];
+            if (gy == 0 || gy == A.h - 1) {
+                // a frame row: the frame marker J = Hq, which is also the
+                // bound there (a frame pixel joins every level set it is in)
+                const uint4 q = load16(A.a + gy * A.pitch_a + gx, nvalid, aligned16(A.a, A.pitch_a));
+                w[0] = q.x;
+                w[1] = q.y;
+                w[2] = q.z;
+                w[3] = q.w;
+            } else {
+                // the highest level whose frame-connected set holds the
+                // pixel: the level sets are nested and the levels come in
+                // non-decreasing order, so each level overwrites the bytes
+                // of its set
+                for (int l = 0; l < nlev; ++l) {
+                    const uint32_t f = (uint32_t)(ccl_smem[l * CT + y] >> (16 * c));
+                    const uint32_t L = (uint32_t)A.levels[l] * 0x01010101u;
 #pragma unroll
-            for (int l = 0; l < MAXLEV; ++l) fcl[l] = l < nw ? (uint32_t)(ccl_smem[l * CT + y] >> (16 * c)) & 0xffffu : 0u;
-            const bool frame_row = gy == 0 || gy == A.h - 1;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                int v = 0;
-#pragma unroll
-                for (int l = 0; l < MAXLEV; ++l)
-                    if ((fcl[l] >> k) & 1u) v = max(v, lv[l]);
-                const int xg = gx + k;
-                if (k < nvalid && (frame_row || xg == 0 || xg == A.w - 1))
-                    v = max(v, (int)A.a[gy * A.pitch_a + xg]);   // frame marker J = Hq
-                w[k >> 2] |= (uint32_t)v << ((k & 3) * 8);
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t b = nibble_bytes(f >> (4 * q)) * 0xffu;
+                        w[q] = (b & L) | (~b & w[q]);
+                    }
+                }
+                // frame columns: J = Hq
+                auto put = [&](int k) {
+                    const uint32_t v = A.a[gy * A.pitch_a + gx + k];
+                    const int sh = (k & 3) * 8;
+                    w[k >> 2] = (w[k >> 2] & ~(0xffu << sh)) | (v << sh);
+                };
+                if (gx == 0) put(0);
+                const int kr = A.w - 1 - gx;
+                if (kr >= 0 && kr < nvalid) put(kr);
             }
             store16(A.bound + gy * A.pitch_r + gx, w, nvalid, wide);
         }

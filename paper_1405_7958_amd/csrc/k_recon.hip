@@ -784,7 +784,8 @@ __global__ void k_batch_begin(const BatchAux *aux, int n, int32_t *shared_ctr, i
 // highest value whose upper set holds at least frac_permille / 1000 of the
 // pixels, and the levels are v0 - n + 2 .. v0 + 1.  Mode 0 (quantiles): level
 // k is the lowest value whose upper set holds at most q_k of the pixels, q_k
-// from 0.75 down to 0.33.
+// from 0.75 down to 0.33.  In both modes the levels are non-decreasing in k,
+// which the writer of the bound relies on.
 __global__ __launch_bounds__(64) void k_batch_levels(const BatchAux *aux, int n_levels, int mode, int frac_permille) {
     const BatchAux a = aux[blockIdx.x];
     const int t = threadIdx.x;
