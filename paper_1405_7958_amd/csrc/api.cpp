@@ -556,7 +556,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         C.ids = regA;
         C.labels = t.labels;
         C.pitch_l = t.out_pitch;
-        C.bg_zero_mask = t.mask;
+        C.zero_mask = t.mask;
         C.pitch_m = t.out_pitch;
         C.st_area = regA + n1;
         C.st_x0 = regA + 2 * n1;
@@ -1127,7 +1127,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     A.ids = reg;
     A.labels = labels_out;
     A.pitch_l = pitch;
-    A.bg_zero_mask = mask_out;
+    A.zero_mask = mask_out;
     A.pitch_m = pitch;
     A.st_area = reg + n1;
     A.st_x0 = reg + 2 * n1;
@@ -1455,7 +1455,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     A.ids = reg;
     A.labels = labels_out;
     A.pitch_l = out_pitch;
-    A.bg_zero_mask = mask_out;
+    A.zero_mask = mask_out;
     A.pitch_m = out_pitch;
     A.st_area = reg + n1;
     A.st_x0 = reg + 2 * n1;

@@ -854,34 +854,32 @@ __device__ __forceinline__ void ccl_flatten_fc_tile(const CclArgs &A, int b, int
     }
 }
 
-// BWLabel output: labels, background zeros of the output mask, and the
-// per-component statistics.  A tile's runs are first summed per component in
+__device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows, const int *P);
+__device__ void write_labels(const CclArgs &A, const Tile &t, const uint64_t *rows, const int *P);
+
+// BWLabel output: labels, the cleared output mask, and the per-component
+// statistics.  A tile's runs are first summed per component in
 // an LDS table (a few entries per tile), so each component costs one set of
 // global atomics per tile instead of one per run; components are registered
 // with one counter update per wave.
 __device__ __forceinline__ void ccl_flatten_labels_tile(const CclArgs &A, int b) {
     const Tile t = tile_of(A, b);
-    const int lane = lane_id();
     const WaveMem M = wave_mem(0);
     uint64_t *rows = M.rows;
     int *P = M.P;
     build_rows<CclPred::NonZero>(A, t, 0, rows);
     run_forest(rows, P, A.conn);
     resolve_roots(A, t, M, A.ids, true);
-    {
-        const int x = lane;
-        if (x < t.tw) {
-            const int gx = t.x0 + x;
-#pragma unroll 4
-            for (int y = 0; y < t.th; ++y) {
-                const int64_t gy = t.y0 + y;
-                const bool mem = (rows[y] >> x) & 1ull;
-                A.labels[gy * A.pitch_l + gx] = mem ? global_of(rows, P, x, y) : 0;
-                if (!mem && A.bg_zero_mask) A.bg_zero_mask[gy * A.pitch_m + gx] = 0;
-            }
-        }
-    }
-    if (!A.st_area && !A.obj_list) return;
+    // statistics first: the list registration waits for its counter, and
+    // that wait (one count of vector memory operations) also covers every
+    // store issued before it
+    if (A.st_area || A.obj_list) tile_stats(A, t, rows, P);
+    write_labels(A, t, rows, P);
+}
+
+// Per-component area, bounding box and registration of the tile's roots.
+__device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows, const int *P) {
+    const int lane = lane_id();
     int *key = (int *)(ccl_smem + WAVE_LDS / 8);
     int *area = key + NHASH, *x0 = area + NHASH, *x1 = x0 + NHASH, *y0 = x1 + NHASH, *y1 = y0 + NHASH;
     int *reg = y1 + NHASH;
@@ -952,6 +950,45 @@ __device__ __forceinline__ void ccl_flatten_labels_tile(const CclArgs &A, int b)
             base = __shfl(base, 0);
             if (r) A.obj_list[base + __popcll(bm & ((1ull << lane) - 1))] = (A.img << 25) | g;
         }
+    }
+}
+
+// Labels of the tile, 16 bytes per lane and row: lane = group of 4 columns
+// (lane % 16) and row phase (lane / 16), so that one store covers 4 rows.
+// The mask is cleared over the whole tile with 16-byte stores; the
+// per-object stage writes every member pixel afterwards.
+__device__ void write_labels(const CclArgs &A, const Tile &t, const uint64_t *rows, const int *P) {
+    const int lane = lane_id();
+    const int x4 = 4 * (lane & 15);
+    const int nv = max(0, min(4, t.tw - x4));
+    const bool wide = aligned16(A.labels, A.pitch_l * (int64_t)sizeof(int32_t));
+    for (int y = lane >> 4; y < t.th; y += 4) {
+        const uint64_t m = rows[y];
+        const uint32_t g4 = (uint32_t)(m >> x4) & 15u;
+        // run start of each of the 4 pixels (any column for a non-member):
+        // a member continues its left neighbour's run or starts one
+        int rs[4];
+        rs[0] = (g4 & 1u) ? run_start_of(m, x4) : x4;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) rs[j] = ((g4 >> (j - 1)) & 1u) ? rs[j - 1] : x4 + j;
+        int v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = global_of_run(P, y * CT + rs[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = ((g4 >> j) & 1u) ? v[j] : 0;
+        int32_t *dst = A.labels + (t.y0 + y) * A.pitch_l + t.x0 + x4;
+        if (wide && nv == 4) {
+            *(int4 *)dst = make_int4(v[0], v[1], v[2], v[3]);
+        } else {
+            for (int j = 0; j < nv; ++j) dst[j] = v[j];
+        }
+    }
+    if (A.zero_mask) {
+        const int c = lane & 3;
+        const int nvm = max(0, min(16, t.tw - 16 * c));
+        const bool wm = aligned16(A.zero_mask, A.pitch_m);
+        const uint32_t z[4] = {0, 0, 0, 0};
+        for (int y = lane >> 2; y < t.th; y += 16) store16(A.zero_mask + (t.y0 + y) * A.pitch_m + t.x0 + 16 * c, z, nvm, wm);
     }
 }
 

@@ -183,7 +183,7 @@ struct CclArgs {
     int32_t *labels; int64_t pitch_l;   // Labels: root id or 0
     uint8_t *fill; int64_t pitch_f;     // FillHoles: F0 | !frame-connected
     uint8_t *bound; int64_t pitch_r;    // LevelBound: bound = max(bound, level) where frame-connected
-    uint8_t *bg_zero_mask; int64_t pitch_m;  // Labels: write 0 to this mask at background pixels (nullable)
+    uint8_t *zero_mask; int64_t pitch_m;     // Labels: this mask is cleared over the image (nullable; the per-object stage then writes every member pixel)
     // per-component statistics (Labels, nullable): indexed by root id
     int32_t *st_area, *st_x0, *st_x1, *st_y0, *st_y1;
     int32_t *obj_list, *n_obj;     // components registered here (nullable); entries are image << 25 | root
