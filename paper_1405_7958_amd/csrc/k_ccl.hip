@@ -43,9 +43,16 @@ constexpr int FRAME_BIT = 1 << 12;     // tags a local root whose component touc
 constexpr int TOUCH_BIT = 1 << 13;     // tags a local root whose component touches the tile border
 constexpr int LIDX = 0xfff;
 constexpr int NLIST = 128;             // components touching a tile border: at most 126 (one per two border pixels)
-constexpr int WAVE_LDS = CT * 8 + NSLOT * 4 + NLIST * 4 + 16;   // bytes per wave: row masks, forest, root list
-constexpr int NHASH = 128;             // per-tile component table of the statistics pass
-constexpr int LABELS_LDS = WAVE_LDS + NHASH * 7 * 4;
+constexpr int NHASH = 64;              // per-tile component table of the statistics pass
+// After the row masks and the 32-bit forest, one region holds first the root
+// list of the global lookups and then the statistics table (key, area with
+// the root flag, x0, x1, y0, y1): 10,240 bytes per BWLabel tile, so that 16
+// tiles share a CU's 160 KB.
+constexpr int TAIL_LDS = NHASH * 6 * 4;
+static_assert(TAIL_LDS >= NLIST * 4 + 4, "the root list and its count fit the table's space");
+constexpr int WAVE_LDS = CT * 8 + NSLOT * 4 + TAIL_LDS;
+constexpr int LABELS_LDS = WAVE_LDS;
+constexpr int ROOT_FLAG = 1 << 30;     // statistics table area: the component's root run lies in this tile
 constexpr int LOCAL_LDS = CT * 8 + NSLOT * 2;   // local phase: row masks + 16-bit forest
 
 extern __shared__ uint64_t ccl_smem[];
@@ -55,7 +62,7 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (CT - 1); }
 struct WaveMem {
     uint64_t *rows;   // rows[y] bit x = member (x, y)
     int *P;           // forest over run starts, indexed by slot()
-    int *list;        // border-touching roots of the tile
+    int *list;        // border-touching roots of the tile (then the statistics table)
     int *count;       // their number
 };
 
@@ -880,9 +887,8 @@ __device__ __forceinline__ void ccl_flatten_labels_tile(const CclArgs &A, int b)
 // Per-component area, bounding box and registration of the tile's roots.
 __device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows, const int *P) {
     const int lane = lane_id();
-    int *key = (int *)(ccl_smem + WAVE_LDS / 8);
+    int *key = wave_mem(0).list;   // the root list is no longer needed
     int *area = key + NHASH, *x0 = area + NHASH, *x1 = x0 + NHASH, *y0 = x1 + NHASH, *y1 = y0 + NHASH;
-    int *reg = y1 + NHASH;
     for (int i = lane; i < NHASH; i += CT) {
         key[i] = -1;
         area[i] = 0;
@@ -890,7 +896,6 @@ __device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows
         x1[i] = -1;
         y0[i] = 0x7fffffff;
         y1[i] = -1;
-        reg[i] = 0;
     }
     __syncthreads();
     // per run (lane = row)
@@ -917,7 +922,7 @@ __device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows
             atomicMax(x1 + k, t.x0 + s + len - 1);
             atomicMin(y0 + k, t.y0 + y);
             atomicMax(y1 + k, t.y0 + y);
-            if (is_root) reg[k] = 1;
+            if (is_root) atomicOr(area + k, ROOT_FLAG);
         } else {   // table full: this run goes to global memory directly
             if (A.st_area) {
                 atomicAdd(A.st_area + g, len);
@@ -934,14 +939,15 @@ __device__ void tile_stats(const CclArgs &A, const Tile &t, const uint64_t *rows
         const int g = key[i];
         bool r = false;
         if (g >= 0) {
+            const int ar = area[i];
             if (A.st_area) {
-                atomicAdd(A.st_area + g, area[i]);
+                atomicAdd(A.st_area + g, ar & ~ROOT_FLAG);
                 atomicMin(A.st_x0 + g, x0[i]);
                 atomicMax(A.st_x1 + g, x1[i]);
                 atomicMin(A.st_y0 + g, y0[i]);
                 atomicMax(A.st_y1 + g, y1[i]);
             }
-            r = A.obj_list && reg[i];
+            r = A.obj_list && (ar & ROOT_FLAG);
         }
         const uint64_t bm = __ballot(r);
         if (bm) {
