@@ -114,8 +114,9 @@ int rt_ccl(rt_ctx *ctx, const uint8_t *mask, int32_t *labels, int32_t w, int32_t
  * rt_ccl without allocation, for callers that cannot allocate memory during a
  * call (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, definition and output as rt_ccl.  Its
- * scratch (an argument record, the union-find array of 4 (w*h + 1) bytes
- * and, when n_out_dev is given, a component list) lives in one fixed device
+ * scratch (an argument record, the union-find array of 4 (w*h + 1) bytes,
+ * a border table of 1 KB per 64 x 64 tile and, when n_out_dev is given, a
+ * component list) lives in one fixed device
  * array of RT_NOALLOC_SCRATCH_BYTES bytes, which every device the library
  * runs on holds until the process ends; the array's device address is
  * looked up when a context is first created on the device.  The call makes

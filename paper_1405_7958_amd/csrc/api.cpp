@@ -424,7 +424,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
     const int budget = c->knobs.graph_rounds;
     // ---- scratch layout
     struct Per {
-        size_t hq, R, F, hist, levels, regA, kept;
+        size_t hq, R, F, hist, levels, regA, bt, kept;
         int64_t dec0;
         int ccl0, rec0;
     };
@@ -446,6 +446,8 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         q.levels = L.add(8 * sizeof(int32_t));
         // level ids, then fill-holes ids, then component ids + 5 statistics
         q.regA = L.add(sizeof(int32_t) * (N + 1) * (size_t)std::max(P.nlev, 6));
+        // CCL border tables: the levels', then reused by the later CCL stages
+        q.bt = L.add(sizeof(int32_t) * ccl_border_ints(t.w, t.h) * (size_t)std::max(P.nlev, 1));
         q.kept = L.add(sizeof(int32_t));
         q.dec0 = P.dec_total;
         q.ccl0 = P.ccl_total;
@@ -499,6 +501,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         uint8_t *R = at<uint8_t>(c, q.R);
         uint8_t *F = at<uint8_t>(c, q.F);
         int32_t *regA = at<int32_t>(c, q.regA);
+        int32_t *bt = at<int32_t>(c, q.bt);
         // with hq_out the caller guarantees out_pitch == w
         const int64_t pw = t.w;
         dec[i] = DeconvImg{t.rgb, t.rgb_pitch, hq, pw, nullptr, 0, at<uint32_t>(c, q.hist), t.w, t.h, q.dec0};
@@ -517,6 +520,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         A.levels = at<int32_t>(c, q.levels);
         A.n_levels = P.nlev;
         A.ids = regA;
+        A.bt = bt;
         A.bound = R;
         A.pitch_r = pw;
         A.img = i;
@@ -539,6 +543,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         B.pitch_b = pw;
         B.t = p->t_fg;
         B.ids = regA;
+        B.bt = bt;
         B.fill = F;
         B.pitch_f = pw;
         B.img = i;
@@ -554,6 +559,7 @@ int pipeline(rt_ctx *c, const TileIn *tiles, int n, const rt_seg_params *p, hipS
         C.a = F;
         C.pitch_a = pw;
         C.ids = regA;
+        C.bt = bt;
         C.labels = t.labels;
         C.pitch_l = t.out_pitch;
         C.zero_mask = t.mask;
@@ -867,6 +873,7 @@ int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t
     Layout L;
     const size_t o_args = L.add(sizeof(CclArgs));
     const size_t o_ids = L.add(sizeof(int32_t) * ((size_t)w * h + 1));
+    const size_t o_bt = L.add(sizeof(int32_t) * ccl_border_ints(w, h));
     if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, sizeof(CclArgs) + 4096))) return e;
     CclArgs A{};
     A.pred = CclPred::Zero;
@@ -878,6 +885,7 @@ int rt_fill_holes(rt_ctx *c, const uint8_t *in, uint8_t *out, int32_t w, int32_t
     A.a = in;
     A.pitch_a = pitch;
     A.ids = at<int32_t>(c, o_ids);
+    A.bt = at<int32_t>(c, o_bt);
     A.fill = out;
     A.pitch_f = pitch;
     Stager sg{c};
@@ -896,6 +904,7 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     Layout L;
     const size_t o_args = L.add(sizeof(CclArgs));
     const size_t o_ids = L.add(sizeof(int32_t) * ((size_t)w * h + 1));
+    const size_t o_bt = L.add(sizeof(int32_t) * ccl_border_ints(w, h));
     const size_t o_list = L.add(sizeof(int32_t) * (n_out_dev ? max_components(w, h, conn) : 1));
     if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, sizeof(CclArgs) + 4096))) return e;
     CclArgs A{};
@@ -907,6 +916,7 @@ int rt_ccl(rt_ctx *c, const uint8_t *mask, int32_t *labels, int32_t w, int32_t h
     A.a = mask;
     A.pitch_a = pitch;
     A.ids = at<int32_t>(c, o_ids);
+    A.bt = at<int32_t>(c, o_bt);
     A.labels = labels;
     A.pitch_l = pitch;
     if (n_out_dev) {
@@ -1110,6 +1120,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     const size_t mid_slice = al(mid_object_bytes(w, h));
     const int mid_n = mid_slices_for((int64_t)w * h);
     const size_t o_mid = L.add(mid_slice * mid_n);
+    const size_t o_bt = L.add(sizeof(int32_t) * ccl_border_ints(w, h));
     const size_t o_cc = L.add(sizeof(CclArgs));
     const size_t o_ob = L.add(sizeof(ObjArgs));
     if ((e = ensure_arena(c, L.off + 4096)) || (e = ensure_staging(c, L.off - o_cc + 4096))) return e;
@@ -1125,6 +1136,7 @@ int rt_watershed(rt_ctx *c, const uint8_t *fg, const uint8_t *seeds, int32_t h_s
     A.a = fg;
     A.pitch_a = pitch;
     A.ids = reg;
+    A.bt = at<int32_t>(c, o_bt);
     A.labels = labels_out;
     A.pitch_l = pitch;
     A.zero_mask = mask_out;
@@ -1405,6 +1417,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     const size_t mid_slice = al(mid_object_bytes(w, h));
     const int mid_n = mid_slices_for((int64_t)w * h);
     const size_t o_mid = L.add(mid_slice * mid_n);
+    const size_t o_bt = L.add(sizeof(int32_t) * ccl_border_ints(w, h));
     const size_t o_cf = L.add(sizeof(CclArgs));
     const size_t o_cc = L.add(sizeof(CclArgs));
     const size_t o_ob = L.add(sizeof(ObjArgs));
@@ -1442,6 +1455,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     B.a = at<uint8_t>(c, o_f0);
     B.pitch_a = w;
     B.ids = reg;
+    B.bt = at<int32_t>(c, o_bt);
     B.fill = at<uint8_t>(c, o_f);
     B.pitch_f = w;
     CclArgs A{};
@@ -1453,6 +1467,7 @@ int rt_segment_tile_surrogate(rt_ctx *c, rt_unet *net, const uint8_t *rgb, int64
     A.a = at<uint8_t>(c, o_f);
     A.pitch_a = w;
     A.ids = reg;
+    A.bt = at<int32_t>(c, o_bt);
     A.labels = labels_out;
     A.pitch_l = out_pitch;
     A.zero_mask = mask_out;

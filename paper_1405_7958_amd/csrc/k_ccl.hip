@@ -9,17 +9,19 @@
 // atomicMin, the root is always the smallest index, so labels are canonical
 // by construction).  Two run starts of one row are at least two pixels apart,
 // so the forest needs one LDS slot per pixel pair.  Three launches:
-//   local  : build the tile forest; publish only its roots and its edge
-//            pixels to the global id array (id 0 = virtual node, pixel p has
-//            id p + 1);
+//   local  : build the tile forest; publish its border-touching roots to
+//            the global id array (id 0 = virtual node, pixel p has id p + 1)
+//            and, in the tile's border table, each border pixel's local
+//            root (or -1);
 //   merge  : one wave per tile edge unites, across the tile's right or
 //            bottom edge, each pair of touching edge runs once (global
-//            atomicMin);
+//            atomicMin), starting from the local roots in the two tables;
 //   flatten: BWLabel rebuilds the tile forest (it costs 1 byte/pixel of
 //            input instead of 4 bytes/pixel of stored local roots), finds
 //            each local root's global root once, and writes the labels;
-//            FillHoles and the bound look up only the border runs' roots and
-//            flood the frame-connected set inside the tile.
+//            FillHoles and the bound look up only the border runs' roots
+//            (from the border table) and flood the frame-connected set inside
+//            the tile.
 // Modes: BWLabel (labels, per-component area and bounding box, component
 // list), FillHoles (background components joined to a virtual frame node),
 // and the multi-level frame-connectivity lower bound that starts the
@@ -283,12 +285,6 @@ __device__ __forceinline__ bool pred_val(const CclArgs &A, uint32_t a, uint32_t 
     else return (int)a >= level;
 }
 
-template <CclPred PR>
-__device__ __forceinline__ bool eval_pred(const CclArgs &A, int x, int y, int level) {
-    const uint32_t a = A.a[(int64_t)y * A.pitch_a + x];
-    const uint32_t b = PR == CclPred::TophatBg ? A.b[(int64_t)y * A.pitch_b + x] : 0u;
-    return pred_val<PR>(A, a, b, level);
-}
 
 struct Tile {
     int tx, ty, x0, y0, tw, th;
@@ -320,6 +316,14 @@ __device__ __forceinline__ Tile tile_of(const CclArgs &A, int b) {
 
 __device__ __forceinline__ int gid(const CclArgs &A, const Tile &t, int x, int y) {
     return (t.y0 + y) * A.w + t.x0 + x + 1;
+}
+
+// Border table of tile b at level lev: 256 ints, the left column (index =
+// row), the right column, the top row (index = column) and the bottom row;
+// each entry is the id of the pixel's local root, or -1 for a non-member.
+__device__ __forceinline__ int32_t *border_table(const CclArgs &A, int lev, int b) {
+    const int64_t nt = (int64_t)((A.w + CT - 1) / CT) * ((A.h + CT - 1) / CT);
+    return A.bt + (lev * nt + b) * 256;
 }
 
 __device__ __forceinline__ bool aligned16(const void *p, int64_t pitch) {
@@ -609,16 +613,21 @@ __device__ __forceinline__ void ccl_local_tile(const CclArgs &A, int b, int wave
         if (s_t) publish(r_t);
         if (yl > 0 && s_b) publish(r_b);
     }
-    // border pixels that are not roots point at their root
-    if (r_l >= 0 && r_l != y * CT) ids[gid(A, t, 0, y)] = gid(A, t, r_l & 63, r_l >> 6);
-    if (xr > 0 && r_r >= 0 && r_r != y * CT + xr) ids[gid(A, t, xr, y)] = gid(A, t, r_r & 63, r_r >> 6);
-    if (r_t >= 0 && r_t != lane) ids[gid(A, t, lane, 0)] = gid(A, t, r_t & 63, r_t >> 6);
-    if (yl > 0 && r_b >= 0 && r_b != yl * CT + lane) ids[gid(A, t, lane, yl)] = gid(A, t, r_b & 63, r_b >> 6);
+    // the border table: the local root's id of each border pixel (-1: not a
+    // member), four coalesced rows of 64
+    int32_t *bt = border_table(A, live ? wave : 0, b);
+    auto rid = [&](int r) { return r >= 0 ? gid(A, t, r & 63, r >> 6) : -1; };
+    bt[lane] = rid(r_l);
+    bt[64 + lane] = rid(r_r);
+    bt[128 + lane] = rid(r_t);
+    bt[192 + lane] = rid(r_b);
 }
 
-// One wave per (tile, level): unit u is tile u / nw at level u % nw.
+// One wave per (tile, level): unit u is tile u / nw at level u % nw.  The
+// level sets' launch has 32 waves per CU, all resident only with at most 64
+// registers a lane.
 template <CclPred PR, CclOut OU>
-__global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, int total, int nw) {
+__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(PR == CclPred::Level ? 8 : 1))) void k_ccl_local(const CclArgs *args, int n, int total, int nw) {
     for (int u = blockIdx.x; u < total * nw; u += gridDim.x) {
         const int tu = u / nw;
         const CclArgs A = args[img_of(args, n, tu)];
@@ -633,11 +642,13 @@ __global__ __launch_bounds__(CT) void k_ccl_local(const CclArgs *args, int n, in
 // unites the pairs (a(i), b(i+d)), d in {-1,0,1} (8-conn) or {0} (4-conn),
 // along an edge; a/b bit i = member at position i (b has two extra members
 // at i = -1 and i = 64, passed as bm1 / b64; they lie in the diagonal
-// neighbour tiles).  About one union per pair of touching runs: a pair is
+// neighbour tiles).  The nodes are the local roots of the edge pixels, from
+// the border tables: ida = a(i)'s, idb_m / idb_0 / idb_p = those of b(i-1),
+// b(i), b(i+1).  About one union per pair of touching runs: a pair is
 // skipped when a pair with a lower position, together with an adjacency
 // inside one tile (always joined by that tile's forest), implies it.
-__device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bool b64, int conn, int i,
-                            int ida, int idb_base, int idb_stride) {
+__device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bool b64, int conn, int i, int ida,
+                            int idb_m, int idb_0, int idb_p) {
     if (!((am >> i) & 1ull)) return;
     auto bset = [&](int j) -> bool {
         if (j == -1) return bm1;
@@ -649,7 +660,7 @@ __device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bo
     if (conn == 4) {
         if (!bset(i)) return;
         if (aset(i - 1) && bset(i - 1)) return;
-        gunite(ids, ida, idb_base + i * idb_stride);
+        gunite(ids, ida, idb_0);
         return;
     }
     for (int d = -1; d <= 1; ++d) {
@@ -661,12 +672,15 @@ __device__ void edge_unions(int32_t *ids, uint64_t am, uint64_t bm, bool bm1, bo
         // same tile (positions 0..63); across a tile corner the two edges
         // could otherwise each rely on the other's skipped union
         if (j >= 1 && j <= 63 && bset(j - 1) && (j - 1) - i <= 1 && (j - 1) - i >= -1) continue;
-        gunite(ids, ida, idb_base + j * idb_stride);
+        gunite(ids, ida, d < 0 ? idb_m : d == 0 ? idb_0 : idb_p);
     }
 }
 
 // Wave 2l handles the right edge and wave 2l + 1 the bottom edge of the
-// tile at level l, so the two edges' unions overlap.
+// tile at level l, so the two edges' unions overlap.  Membership and the
+// nodes come from the border tables the local phase wrote (coalesced rows,
+// where the image's columns would be one cache line per pixel), and every
+// union starts at a local root.
 template <CclPred PR>
 __device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b, int wave) {
     const Tile t = tile_of(A, b);
@@ -675,30 +689,27 @@ __device__ __forceinline__ void ccl_merge_tile(const CclArgs &A, int b, int wave
     const bool right_edge = (wave & 1) == 0;
     if (PR == CclPred::Level && lev >= A.n_levels) return;
     const int64_t nid = (int64_t)A.w * A.h + 1;
-    const int level = wave_level<PR>(A, lev);
     int32_t *ids = A.ids + lev * nid;
-    if (right_edge) {   // a = column x0+63, b = column x0+64, position = row
+    const int ntx = (A.w + CT - 1) / CT;
+    auto tb = [&](int tx, int ty) -> const int32_t * { return border_table(A, lev, ty * ntx + tx); };
+    int ra, rb, rbm1, rb64;
+    if (right_edge) {   // a = this tile's right column, b = the right neighbour's left column, position = row
         if (t.x0 + CT >= A.w) return;
-        const int xa = t.x0 + CT - 1, xb = t.x0 + CT;
-        const bool ok = lane < t.th;
-        const bool a = ok && eval_pred<PR>(A, xa, t.y0 + lane, level);
-        const bool b = ok && eval_pred<PR>(A, xb, t.y0 + lane, level);
-        const bool bm1 = t.y0 > 0 && eval_pred<PR>(A, xb, t.y0 - 1, level);
-        const bool b64 = t.y0 + CT < A.h && eval_pred<PR>(A, xb, t.y0 + CT, level);
-        const uint64_t am = __ballot(a), bm = __ballot(b);
-        if (ok)
-            edge_unions(ids, am, bm, bm1, b64, A.conn, lane, (t.y0 + lane) * A.w + xa + 1, t.y0 * A.w + xb + 1, A.w);
-    } else {  // a = row y0+63, b = row y0+64, position = column
+        ra = tb(t.tx, t.ty)[64 + lane];
+        rb = tb(t.tx + 1, t.ty)[lane];
+        rbm1 = t.y0 > 0 ? tb(t.tx + 1, t.ty - 1)[CT - 1] : -1;          // (x0 + 64, y0 - 1)
+        rb64 = t.y0 + CT < A.h ? tb(t.tx + 1, t.ty + 1)[0] : -1;        // (x0 + 64, y0 + 64)
+    } else {            // a = this tile's bottom row, b = the lower neighbour's top row, position = column
         if (t.y0 + CT >= A.h) return;
-        const int ya = t.y0 + CT - 1, yb = t.y0 + CT;
-        const bool ok = lane < t.tw;
-        const bool a = ok && eval_pred<PR>(A, t.x0 + lane, ya, level);
-        const bool b = ok && eval_pred<PR>(A, t.x0 + lane, yb, level);
-        const bool bm1 = t.x0 > 0 && eval_pred<PR>(A, t.x0 - 1, yb, level);
-        const bool b64 = t.x0 + CT < A.w && eval_pred<PR>(A, t.x0 + CT, yb, level);
-        const uint64_t am = __ballot(a), bm = __ballot(b);
-        if (ok) edge_unions(ids, am, bm, bm1, b64, A.conn, lane, ya * A.w + t.x0 + lane + 1, yb * A.w + t.x0 + 1, 1);
+        ra = tb(t.tx, t.ty)[192 + lane];
+        rb = tb(t.tx, t.ty + 1)[128 + lane];
+        rbm1 = t.x0 > 0 ? tb(t.tx - 1, t.ty + 1)[128 + CT - 1] : -1;   // (x0 - 1, y0 + 64)
+        rb64 = t.x0 + CT < A.w ? tb(t.tx + 1, t.ty + 1)[128] : -1;      // (x0 + 64, y0 + 64)
     }
+    const uint64_t am = __ballot(ra >= 0), bm = __ballot(rb >= 0);
+    const int rbl = __shfl(rb, lane > 0 ? lane - 1 : 0), rbr = __shfl(rb, lane < CT - 1 ? lane + 1 : CT - 1);
+    edge_unions(ids, am, bm, rbm1 >= 0, rb64 >= 0, A.conn, lane, ra, lane > 0 ? rbl : rbm1, rb,
+                lane < CT - 1 ? rbr : rb64);
 }
 
 // One workgroup per tile, one wave per (level, edge).
@@ -787,12 +798,14 @@ __device__ __forceinline__ void ccl_flatten_fc_tile(const CclArgs &A, int b, int
     const uint64_t top = rows[0], bot = rows[t.th - 1];
     const uint64_t above = lane > 0 ? rows[lane - 1] : 0ull;
     const int xr = t.tw - 1;
+    // each border run's local root, from the border table, once per run
     int x[4] = {-1, -1, -1, -1};
     if (live) {
-        if ((run_starts(top) >> lane) & 1ull) x[0] = gid(A, t, lane, 0);
-        if (t.th > 1 && ((run_starts(bot) >> lane) & 1ull)) x[1] = gid(A, t, lane, t.th - 1);
-        if ((m & 1ull) && !(above & 1ull)) x[2] = gid(A, t, 0, lane);
-        if (xr > 0 && ((m >> xr) & 1ull) && !((above >> xr) & 1ull)) x[3] = gid(A, t, xr, lane);
+        const int32_t *bt = border_table(A, wave, b);
+        if ((run_starts(top) >> lane) & 1ull) x[0] = bt[128 + lane];
+        if (t.th > 1 && ((run_starts(bot) >> lane) & 1ull)) x[1] = bt[192 + lane];
+        if ((m & 1ull) && !(above & 1ull)) x[2] = bt[lane];
+        if (xr > 0 && ((m >> xr) & 1ull) && !((above >> xr) & 1ull)) x[3] = bt[64 + lane];
     }
     gfind4_ro(A.ids + (live ? wave : 0) * nid, x);
     const uint64_t s_top = __ballot(x[0] == 0), s_bot = __ballot(x[1] == 0);

@@ -53,7 +53,7 @@ int noalloc_init_device(int device) {
 
 size_t noalloc_ccl_bytes(int w, int h, int conn, bool want_count) {
     const size_t npx = (size_t)w * h;
-    size_t b = 256 + al256(sizeof(int32_t) * (npx + 1));
+    size_t b = 256 + al256(sizeof(int32_t) * (npx + 1)) + al256(sizeof(int32_t) * ccl_border_ints(w, h));
     if (want_count) b += al256(sizeof(int32_t) * max_components(w, h, conn));
     return b;
 }
@@ -78,7 +78,8 @@ int ccl_noalloc(int device, int n_cu, const uint8_t *mask, int32_t *labels, int 
     char *p = (char *)base;
     CclArgs *args = (CclArgs *)p;
     int32_t *ids = (int32_t *)(p + 256);
-    int32_t *list = (int32_t *)(p + 256 + al256(sizeof(int32_t) * ((size_t)w * h + 1)));
+    int32_t *bt = (int32_t *)(p + 256 + al256(sizeof(int32_t) * ((size_t)w * h + 1)));
+    int32_t *list = (int32_t *)((char *)bt + al256(sizeof(int32_t) * ccl_border_ints(w, h)));
     CclArgs A{};
     A.pred = CclPred::NonZero;
     A.out = CclOut::Labels;
@@ -88,6 +89,7 @@ int ccl_noalloc(int device, int n_cu, const uint8_t *mask, int32_t *labels, int 
     A.a = mask;
     A.pitch_a = pitch;
     A.ids = ids;
+    A.bt = bt;
     A.labels = labels;
     A.pitch_l = pitch;
     if (n_out_dev) {

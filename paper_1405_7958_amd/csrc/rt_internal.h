@@ -179,6 +179,7 @@ struct CclArgs {
     const int32_t *levels;         // Level: device array of levels
     int n_levels;
     int32_t *ids;                  // w*h+1 (times n_levels for Level)
+    int32_t *bt;                   // border table: ccl_border_ints(w, h) (times n_levels for Level)
     // outputs
     int32_t *labels; int64_t pitch_l;   // Labels: root id or 0
     uint8_t *fill; int64_t pitch_f;     // FillHoles: F0 | !frame-connected
@@ -191,6 +192,9 @@ struct CclArgs {
     int unit0;                     // first 64 x 64 tile of this image
 };
 int ccl_tiles(int w, int h);   // number of 64 x 64 CCL tiles of a w x h image
+// ints of the CCL border table of a w x h image (256 per tile): for each
+// border pixel of a tile, the id of its local root, or -1
+inline size_t ccl_border_ints(int w, int h) { return (size_t)ccl_tiles(w, h) * 256; }
 // All records of one launch share the predicate and output (and, in the
 // multi-level mode, the number of levels).
 int launch_ccl(const CclArgs *args_dev, int n, int total_units, int n_cu, hipStream_t s, CclPred pred, CclOut out,
