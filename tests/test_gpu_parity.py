@@ -165,7 +165,7 @@ def test_recon_in_place(rt, oracle):
 # FillHoles, BWLabel, AreaThreshold
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (40, 1), (33, 65), (200, 300), (1024, 1000)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (40, 1), (33, 65), (129, 193), (200, 300), (1024, 1000)])
 def test_fill_holes(rt, oracle, shape):
     d = dev()
     for p in (0.3, 0.55, 0.8):
@@ -178,7 +178,8 @@ def test_fill_holes(rt, oracle, shape):
     assert_equal(to_np(rt.rt_fill_holes(to_dev(rings, d))), oracle.fill_holes(rings), "rings")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 50), (50, 1), (31, 33), (64, 64), (300, 257), (1500, 1100)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 50), (50, 1), (31, 33), (64, 64), (129, 65), (65, 129), (300, 257),
+                                   (1500, 1100)])
 def test_ccl(rt, oracle, shape):
     d = dev()
     for p in (0.2, 0.45, 0.6, 0.9):
@@ -355,7 +356,7 @@ def test_segment_small_tile(rt, oracle):
     assert _check_tile(rt, oracle, rgb, d, "small") > 50
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 64), (37, 1), (100, 333), (700, 613)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 64), (37, 1), (100, 333), (129, 193), (700, 613)])
 def test_segment_ragged(rt, oracle, shape):
     d = dev()
     spec = synth.TileSpec(w=shape[1], h=shape[0], seed=shape[0] + shape[1], n_nuclei=max(1, shape[0] * shape[1] // 2500),
