@@ -236,8 +236,9 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
             r[j] = (col_ok && gy >= 0 && gy < a.h) ? r[j] : 0;
         }
     }
-    // lane = row: the mask's row, and the original values of columns 1 and 62
-    int oL, oR;
+    // lane = row: the mask's row, the original values of columns 1 and 62,
+    // and those of the ring columns 0 and 63 (0 outside the image)
+    int oL, oR, oL0, oR0;
     {
         const int yo = min(max(y0 - 1 + lane, 0), a.h - 1) * pitch;
         const int o = (aM + yo + x0 - 1) & 3, orr = (aR + yo + x0 - 1) & 3;
@@ -250,8 +251,11 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
             mr[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], o) & byte_span(k, clo, chi) & rowimg;
         oL = (int)((uint32_t)sR[lane * SP + orr + 1] & rowmask);
         oR = (int)((uint32_t)sR[lane * SP + orr + RIN] & (limw >= RIN ? rowmask : 0u));
+        oL0 = (int)((uint32_t)sR[lane * SP + orr] & (x0 > 0 ? rowimg : 0u));
+        oR0 = (int)((uint32_t)sR[lane * SP + orr + 63] & (x0 + RIN < a.w ? rowimg : 0u));
     }
     const int oT = r[1], oB = r[62];
+    const int oT0 = r[0], oB0 = r[63];   // the ring rows as loaded
     int tot0 = 0;
 #pragma unroll
     for (int j = 0; j < 64; ++j) tot0 += r[j];
@@ -328,6 +332,32 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
     const bool cT = col_m && r[1] != oT, cB = col_m && r[62] != oB;
     const bool cL = row_m && (int)Tw[lane * TP + 1] != oL, cR = row_m && (int)Tw[lane * TP + RIN] != oR;
     const uint64_t mT = __ballot(cT), mB = __ballot(cB), mL = __ballot(cL), mR = __ballot(cR);
+    // neighbours to visit: a side whose edge changed; with 8-connectivity a
+    // diagonal neighbour when the interior corner next to it changed
+    bool pT = mT != 0, pB = mB != 0, pL = mL != 0, pR = mR != 0;
+    bool pTL = (mT >> 1) & 1ull, pTR = (mT >> 62) & 1ull, pBL = (mB >> 1) & 1ull, pBR = (mB >> 62) & 1ull;
+    if (converged) {
+        // The ring pixels rose in registers to every value this tile's pixels
+        // can give them (the block is at its fixpoint), so a neighbour whose
+        // ring pixels all kept their loaded values, which are at most its
+        // current ones, has nothing to gain from this tile.  A neighbour is
+        // visited when an edge pixel next to it changed and one of its ring
+        // pixels rose; an unchanged edge pixel gave its value at an earlier
+        // visit, which queued the neighbour then if it needed it.  (Without
+        // convergence the ring values are not final: every changed side
+        // counts.)
+        const uint64_t uT = __ballot(r[0] > oT0), uB = __ballot(r[63] > oB0);
+        const uint64_t uL = __ballot((int)Tw[lane * TP] > oL0), uR = __ballot((int)Tw[lane * TP + 63] > oR0);
+        const uint64_t mid = ~1ull & ~(1ull << 63);   // ring positions 1..62 belong to the side's neighbour
+        pT = pT && (uT & mid);
+        pB = pB && (uB & mid);
+        pL = pL && (uL & mid);
+        pR = pR && (uR & mid);
+        pTL = pTL && (uT & 1ull);
+        pTR = pTR && (uT >> 63);
+        pBL = pBL && (uB & 1ull);
+        pBR = pBR && (uB >> 63);
+    }
     if constexpr (QUEUE) __threadfence();   // release the tile's writes before announcing them
     int nb[9];
     int nn = 0;
@@ -335,15 +365,15 @@ __device__ void recon_tile_plain(const ReconImg &a, int gtile, int max_sweeps, u
         int nx = tx + dx, ny = ty + dy;
         if (nx >= 0 && ny >= 0 && nx < a.ntx && ny < a.nty) nb[nn++] = a.unit0 + ny * a.ntx + nx;
     };
-    if (mT) add(0, -1);
-    if (mB) add(0, 1);
-    if (mL) add(-1, 0);
-    if (mR) add(1, 0);
+    if (pT) add(0, -1);
+    if (pB) add(0, 1);
+    if (pL) add(-1, 0);
+    if (pR) add(1, 0);
     if (CONN == 8) {
-        if ((mT >> 1) & 1ull) add(-1, -1);
-        if ((mT >> 62) & 1ull) add(1, -1);
-        if ((mB >> 1) & 1ull) add(-1, 1);
-        if ((mB >> 62) & 1ull) add(1, 1);
+        if (pTL) add(-1, -1);
+        if (pTR) add(1, -1);
+        if (pBL) add(-1, 1);
+        if (pBR) add(1, 1);
     }
     if (!converged) nb[nn++] = gtile;
     int mine = -1;
