@@ -30,7 +30,7 @@ SPACE = {
     "recon_level_mode": [1, 0],
     "recon_level_frac": [500, 450, 550, 400, 600],
     "recon_levels": [2, 1, 3, 4, 6, 8, 0],
-    "recon_round_batch": [4, 8, 16, 32],
+    "recon_round_batch": [4, 5, 6, 8, 16, 32],
     "recon_max_sweeps": [16, 32, 64, 128],
     "objects_path": [0],
     "recon_mode": [0, 1, 2],
