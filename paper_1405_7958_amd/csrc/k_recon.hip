@@ -425,8 +425,11 @@ __global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_round(RoundArgs ra)
 
 // Work-queue variant: one persistent launch in which every wave takes a
 // ticket, waits for the tile pushed under that ticket, processes it and
-// pushes the neighbours its change reaches (a tile is in the queue at most
-// once: inq).  `pending` counts tiles pushed and not yet finished; the waves
+// pushes the neighbours its change reaches.  inq holds a tile's state: 0 idle,
+// 1 queued, 2 in a visit, 3 in a visit and pushed meanwhile.  Only an idle
+// tile enters the queue, and a tile pushed during its visit enters it again
+// when that visit ends, so no two visits of one tile overlap (an older visit
+// finishing last would write back values below the newer one's).  `pending` counts tiles pushed and not yet finished; the waves
 // leave when it reaches zero.  A waiting wave that sees no tile finished
 // anywhere for spin_limit wall-clock ticks (a stall: one tile visit takes far
 // less) raises `abort` and leaves; the host then finishes with ordinary
@@ -488,7 +491,7 @@ __global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_queue(QueueArgs q) 
         item = __shfl(item, 0, 64);
         if (item < 0) break;
         if (lane == 0) {
-            atomicExch(q.inq + item, 0u);
+            atomicExch(q.inq + item, 2u);   // queued -> in a visit
             if (q.visits) atomicAdd(q.visits, 1ull);
         }
         // acquire after leaving the queue: a neighbour that changed this
@@ -497,13 +500,25 @@ __global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_queue(QueueArgs q) 
         // above; fencing before the exchange could keep stale lines cached
         __threadfence();
         const ReconImg a = q.imgs[recon_img_of(q.imgs, q.n, item)];
+        auto enqueue = [&](int nb) {
+            atomicAdd(pending, 1u);
+            const unsigned t = atomicAdd(tail, 1u);
+            __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        };
         auto push = [&](int nb, bool valid) {
-            if (valid && atomicExch(q.inq + nb, 1u) == 0u) {
-                atomicAdd(pending, 1u);
-                const unsigned t = atomicAdd(tail, 1u);
-                __hip_atomic_store(q.ring + t % cap, ((unsigned long long)t << 32) | (unsigned)nb,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!valid) return;
+            // idle -> queued (enqueue), in a visit -> pushed meanwhile; a
+            // queued or already marked tile is left as it is
+            unsigned old = __hip_atomic_load(q.inq + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (;;) {
+                const unsigned want = old == 0u ? 1u : old == 2u ? 3u : old;
+                if (want == old) return;
+                const unsigned got = atomicCAS(q.inq + nb, old, want);
+                if (got == old) break;
+                old = got;
             }
+            if (old == 0u) enqueue(nb);
         };
         if constexpr (PLAIN)
             recon_tile_plain<CONN, true>(a, item, q.max_sweeps, lds, push);
@@ -511,6 +526,12 @@ __global__ __launch_bounds__(64, PLAIN ? 2 : 1) void k_recon_queue(QueueArgs q) 
             recon_tile<T, CONN, true>(a, item, q.max_sweeps, reinterpret_cast<int (*)[65]>(lds), push);
         __syncthreads();
         if (lane == 0) {
+            // leave the visit; pushed meanwhile (3): queue the tile again
+            // (pushers leave state 3 alone, so the exchange below is safe)
+            if (atomicCAS(q.inq + item, 2u, 0u) != 2u) {
+                atomicExch(q.inq + item, 1u);
+                enqueue(item);
+            }
             atomicAdd(done, 1u);
             atomicSub(pending, 1u);
         }
